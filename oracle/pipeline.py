@@ -1,0 +1,68 @@
+"""The plain heat method end to end in FP64 (test infrastructure only).
+
+Steps (Algorithm 1 of the paper, with the direct solves of the original
+heat method that the paper's iterations replace):
+
+1. assembly: cotangent stiffness K, lumped areas A, t = m h^2 (Eq. 27);
+2. diffusion: (diag(A) + t K) u = u_0 (Eq. 4) by range-safe sparse LU;
+3. normalisation: h_f = -grad u / |grad u| (Eq. 3);
+4. Poisson: face form K d = r, or the edge-form variant L_E d = b_E, with
+   d = 0 at every source.
+
+Also returns the breadth-first sets and pairing (Eq. 6, Sec. 3.3) so that
+tests can drive the integration steps.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import assembly, bfs, diffusion, gradient, mesh, poisson
+
+
+@dataclass
+class HeatResult:
+    t: float
+    hbar: float
+    logu: np.ndarray
+    h: np.ndarray
+    d: np.ndarray
+    level: np.ndarray
+    parent: np.ndarray
+    topo: mesh.Topology
+
+
+def prepare(verts, tris):
+    topo = mesh.build_topology(tris, verts.shape[0])
+    K = assembly.cotan_stiffness(verts, tris)
+    A = assembly.lumped_areas(verts, tris)
+    hbar = assembly.mean_edge_length(verts, topo.edges)
+    return topo, K, A, hbar
+
+
+def heat_method(verts, tris, sources, m: float = 1.0, t: float | None = None,
+                form: str = "face", gauge: bool = True) -> HeatResult:
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    sources = np.unique(np.asarray(sources, dtype=np.int64))
+    topo, K, A, hbar = prepare(verts, tris)
+    if t is None or t <= 0:
+        t = m * hbar * hbar
+    M = diffusion.heat_matrix(K, A, t)
+    psi = diffusion.edge_path_potential(verts, topo.edges, sources, t)
+    if not gauge:
+        psi = np.where(np.isfinite(psi), 0.0, np.inf)
+    logu = diffusion.solve_log(M, sources, psi)
+    h = gradient.normalized_field(verts, tris, logu)
+    reach = np.isfinite(psi)
+    if form == "face":
+        d = poisson.poisson_face(verts, tris, h, sources, reach)
+    elif form == "edge":
+        d = poisson.poisson_edge(verts, tris, topo, h, sources, reach)
+    else:
+        raise ValueError(form)
+    rp, col = mesh.vertex_adjacency(verts.shape[0], topo.edges)
+    level, parent = bfs.bfs_levels_vec(verts.shape[0], rp, col, sources)
+    return HeatResult(t=t, hbar=hbar, logu=logu, h=h, d=d, level=level,
+                      parent=parent, topo=topo)

@@ -1,0 +1,357 @@
+"""Pins of the oracle's diffusion, normalisation, Poisson, ADMM, BFS and
+integration steps against facts the mathematics and the paper fix."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import dijkstra, shortest_path
+
+import meshgen
+from oracle import admm, assembly, bfs, diffusion, gradient, integrate, mesh, metrics, pipeline, poisson
+
+
+def _setup(v, f, m=1.0):
+    topo = mesh.build_topology(f, v.shape[0])
+    K = assembly.cotan_stiffness(v, f)
+    A = assembly.lumped_areas(v, f)
+    t = m * assembly.mean_edge_length(v, topo.edges) ** 2
+    return topo, K, A, t
+
+
+@pytest.fixture(scope="module")
+def bumpy3():
+    v, f = meshgen.icosphere(3)
+    v = meshgen.harmonic_displacement(v, seed=3)
+    return v, f
+
+
+# ------------------------------------------------------------ diffusion
+def test_diffusion_dense_solve_and_gauge(bumpy3):
+    v, f = bumpy3
+    topo, K, A, t = _setup(v, f)
+    M = diffusion.heat_matrix(K, A, t)
+    src = [17]
+    dense = np.linalg.solve(M.toarray(), np.eye(v.shape[0])[17])
+    l_plain = diffusion.solve_log(M, src)
+    l_band = diffusion.solve_log(M, src, diffusion.edge_path_potential(v, topo.edges, src, t), band=2.5, margin=30.0)
+    psi = diffusion.edge_path_potential(v, topo.edges, src, t)
+    l_gauge = diffusion.solve_log(M, src, psi)
+    assert np.abs(l_plain - np.log(dense)).max() < 1e-11
+    assert np.abs(l_gauge - np.log(dense)).max() < 1e-11
+    assert np.abs(l_band - np.log(dense)).max() < 1e-11
+
+
+def test_diffusion_mass_conservation_and_symmetry(bumpy3):
+    """1^T K = 0 gives sum_j A_j u_j = #sources; M symmetric gives
+    u^(a)_b = u^(b)_a (Green's function symmetry)."""
+    v, f = bumpy3
+    topo, K, A, t = _setup(v, f, m=2.0)
+    M = diffusion.heat_matrix(K, A, t)
+    for src in ([5], [5, 300, 511]):
+        psi = diffusion.edge_path_potential(v, topo.edges, src, t)
+        u = np.exp(diffusion.solve_log(M, src, psi))
+        assert abs((A * u).sum() - len(src)) < 1e-12 * len(src)
+    a, b = 3, 600
+    ua = diffusion.solve_log(M, [a], diffusion.edge_path_potential(v, topo.edges, [a], t))
+    ub = diffusion.solve_log(M, [b], diffusion.edge_path_potential(v, topo.edges, [b], t))
+    assert abs(ua[b] - ub[a]) < 1e-11
+
+
+def test_diffusion_extended_range_matches_plain_where_representable():
+    """The gauge route keeps componentwise relative accuracy where plain FP64
+    already represents u, and stays finite where plain FP64 underflows."""
+    v, f = meshgen.icosphere(6)
+    topo, K, A, t = _setup(v, f, m=0.01)      # tiny t: u spans ~e^-1200
+    M = diffusion.heat_matrix(K, A, t)
+    src = [0]
+    psi = diffusion.edge_path_potential(v, topo.edges, src, t)
+    lg = diffusion.solve_log(M, src, psi)
+    lp = diffusion.solve_log(M, src)
+    assert np.all(np.isfinite(lg))
+    ok = np.isfinite(lp) & (lp > -650)
+    assert ok.sum() > 0.3 * v.shape[0]
+    assert np.abs(lg[ok] - lp[ok]).max() < 1e-9
+    assert lg.min() < -700                      # a range plain FP64 cannot hold
+
+
+def test_paper_iterations_converge_to_direct(bumpy3):
+    """The breadth-first Gauss-Seidel of Eqs. 6-7 and plain Jacobi sweeps
+    have the exact solve as their fixed point."""
+    v, f = bumpy3
+    topo, K, A, t = _setup(v, f)
+    M = diffusion.heat_matrix(K, A, t)
+    src = [40]
+    lexact = diffusion.solve_log(M, src)
+    rp, col = mesh.vertex_adjacency(v.shape[0], topo.edges)
+    lev, _ = bfs.bfs_levels(v.shape[0], rp, col, src)
+    u_gs = diffusion.gauss_seidel_bfs(K, A, t, src, lev, 300)
+    u_j = diffusion.jacobi(K, A, t, src, 600)
+    assert np.abs(np.log(u_gs) - lexact).max() < 1e-10
+    assert np.abs(np.log(u_j) - lexact).max() < 1e-10
+
+
+# -------------------------------------------------------- normalisation
+def test_normalized_field_unit_and_scale_invariant(bumpy3):
+    v, f = bumpy3
+    lu = -np.linalg.norm(v - v[0], axis=1) * 7.0
+    h = gradient.normalized_field(v, f, lu)
+    assert np.abs(np.linalg.norm(h, axis=1) - 1).max() < 1e-12
+    assert np.abs(gradient.normalized_field(v, f, lu - 900.0) - h).max() < 1e-10
+    # h points against grad u: for u = exp(-|p - p0|), along +grad|p - p0|
+    g = gradient.face_gradients(v, f, np.linalg.norm(v - v[0], axis=1))
+    assert np.all(np.einsum("fc,fc->f", h, g) > 0)
+
+
+def test_normalized_field_degenerate_is_zero():
+    v, f = meshgen.grid(5, 0.0)
+    h = gradient.normalized_field(v, f, np.zeros(v.shape[0]))
+    assert np.all(h == 0)
+    lu = np.full(v.shape[0], -np.inf)
+    assert np.all(gradient.normalized_field(v, f, lu) == 0)
+
+
+# --------------------------------------------------------------- Poisson
+def _tiny_disk():
+    return meshgen.grid(6, 0.2, seed=4)
+
+
+def test_face_qp_kkt_equals_poisson():
+    """Dense KKT solve of the constrained problem Eqs. 9-10 gives the face
+    gradients of the oracle's Poisson distance (Sec. 3.2 / 4.2 remark)."""
+    v, f = _tiny_disk()
+    topo = mesh.build_topology(f, v.shape[0])
+    rng = np.random.default_rng(2)
+    h = rng.standard_normal((f.shape[0], 3))
+    h[:, 2] = 0.0
+    h /= np.linalg.norm(h, axis=1, keepdims=True)
+    area, _, _ = assembly.face_geometry(v, f)
+    nf = f.shape[0]
+    inter = np.flatnonzero(topo.edge_nfaces == 2)
+    C = np.zeros((inter.size, 3 * nf))
+    for r, e in enumerate(inter):
+        ev = v[topo.edges[e, 1]] - v[topo.edges[e, 0]]
+        ev /= np.linalg.norm(ev)
+        f1, f2 = topo.edge_faces[e]
+        C[r, 3 * f1:3 * f1 + 3] = ev
+        C[r, 3 * f2:3 * f2 + 3] = -ev
+    W = np.diag(np.repeat(area, 3))
+    kkt = np.block([[2 * W, C.T], [C, np.zeros((inter.size, inter.size))]])
+    rhs = np.concatenate([2 * W @ h.reshape(-1), np.zeros(inter.size)])
+    sol = np.linalg.lstsq(kkt, rhs, rcond=None)[0]
+    g = sol[:3 * nf].reshape(nf, 3)
+    d = poisson.poisson_face(v, f, h, [7])
+    gd = gradient.face_gradients(v, f, d)
+    assert np.abs(g - gd).max() < 1e-9
+    assert np.abs(C @ g.reshape(-1)).max() < 1e-10
+
+
+def test_edge_qp_kkt_equals_edge_variant():
+    """Dense KKT of the edge problem Eqs. 19-20 equals D d of the oracle's
+    edge variant (closed = exact on a disk)."""
+    v, f = _tiny_disk()
+    topo = mesh.build_topology(f, v.shape[0])
+    rng = np.random.default_rng(5)
+    h = rng.standard_normal((f.shape[0], 3))
+    h[:, 2] = 0.0
+    Z = gradient.edge_targets(v, topo, h)
+    ne, nf = topo.ne, f.shape[0]
+    R = np.zeros((3 * nf, ne))
+    R[np.arange(3 * nf), topo.face_edges.reshape(-1)] = 1.0
+    Cn = np.zeros((nf, ne))
+    for fi in range(nf):
+        Cn[fi, topo.face_edges[fi]] = topo.face_signs[fi]
+    kkt = np.block([[R.T @ R, Cn.T], [Cn, np.zeros((nf, nf))]])
+    rhs = np.concatenate([R.T @ Z.reshape(-1), np.zeros(nf)])
+    x = np.linalg.lstsq(kkt, rhs, rcond=None)[0][:ne]
+    d = poisson.poisson_edge(v, f, topo, h, [9])
+    assert np.abs(x - (d[topo.edges[:, 1]] - d[topo.edges[:, 0]])).max() < 1e-9
+
+
+def test_integrable_target_reproduced_exactly():
+    """h = grad(ell) for a linear ell gives d = ell - ell(s) in both forms."""
+    v, f = meshgen.grid(9, 0.2, seed=6)
+    topo = mesh.build_topology(f, v.shape[0])
+    a = np.array([0.6, -0.8, 0.0])
+    h = np.tile(a, (f.shape[0], 1))
+    ell = v @ a
+    s = 40
+    for d in (poisson.poisson_face(v, f, h, [s]), poisson.poisson_edge(v, f, topo, h, [s])):
+        assert np.abs(d - (ell - ell[s])).max() < 1e-12
+
+
+def test_euclidean_distance_under_refinement():
+    errs = []
+    for n in (17, 33, 65):
+        v, f = meshgen.grid(n, 0.2, seed=1)
+        s = meshgen.grid_center_source(v)
+        r = pipeline.heat_method(v, f, [s])
+        de = np.linalg.norm(v - v[s], axis=1)
+        errs.append(np.abs(r.d - de).mean())
+    assert errs[1] < errs[0] and errs[2] < errs[1]
+    assert errs[2] < 0.01
+
+
+def test_great_circle_under_refinement():
+    errs = []
+    for L in (3, 4, 5):
+        v, f = meshgen.icosphere(L)
+        r = pipeline.heat_method(v, f, [0])
+        gc = np.arccos(np.clip(v @ v[0], -1, 1))
+        errs.append(np.abs(r.d - gc).mean())
+    assert errs[1] < errs[0] and errs[2] < errs[1]
+    assert errs[2] < 0.02
+
+
+def test_distance_bounds_chord_and_dijkstra(bumpy3):
+    v, f = bumpy3
+    topo = mesh.build_topology(f, v.shape[0])
+    s = 11
+    r = pipeline.heat_method(v, f, [s], form="face")
+    hbar = r.hbar
+    w = np.linalg.norm(v[topo.edges[:, 0]] - v[topo.edges[:, 1]], axis=1)
+    nv = v.shape[0]
+    G = sp.csr_matrix((np.r_[w, w], (np.r_[topo.edges[:, 0], topo.edges[:, 1]],
+                                     np.r_[topo.edges[:, 1], topo.edges[:, 0]])), shape=(nv, nv))
+    dd = dijkstra(G, indices=s)
+    chord = np.linalg.norm(v - v[s], axis=1)
+    assert np.all(r.d >= chord - 1.5 * hbar)
+    assert np.all(r.d <= dd + 1.5 * hbar)
+
+
+def test_unit_sphere_near_rotational_symmetry():
+    v, f = meshgen.icosphere(4)
+    s = 0
+    r = pipeline.heat_method(v, f, [s])
+    z = np.round(v @ v[s], 6)
+    spread = [np.ptp(r.d[z == zz]) for zz in np.unique(z) if (z == zz).sum() >= 5]
+    assert max(spread) < 0.05
+
+
+# ------------------------------------------------------------------ ADMM
+def test_y_update_is_constrained_minimiser():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        q1, q2 = rng.standard_normal(3), rng.standard_normal(3)
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        A1, A2 = rng.uniform(0.1, 2, 2)
+        y1, y2 = admm.y_update(q1, q2, e, np.float64(A1), np.float64(A2))
+        # brute-force KKT of min A1|y1-q1|^2 + A2|y2-q2|^2 s.t. e.(y1-y2)=0
+        H = np.diag(np.r_[np.full(3, 2 * A1), np.full(3, 2 * A2)])
+        c = np.r_[e, -e]
+        kkt = np.block([[H, c[:, None]], [c[None, :], np.zeros((1, 1))]])
+        sol = np.linalg.solve(kkt, np.r_[2 * A1 * q1, 2 * A2 * q2, 0.0])
+        assert np.abs(np.r_[y1, y2] - sol[:6]).max() < 1e-12
+        assert abs(e @ (y1 - y2)) < 1e-12
+
+
+def test_g_update_zero_gradient():
+    rng = np.random.default_rng(4)
+    mu, A = 100.0, 0.7
+    al = np.sqrt(A)
+    h = rng.standard_normal(3)
+    ys = rng.standard_normal((3, 3))
+    lams = rng.standard_normal((3, 3))
+    acc = (ys + lams / (mu * al)).sum(axis=0)
+    g = admm.g_update(h[None], acc[None], [3], mu)[0]
+    # gradient of A|g-h|^2 + mu/2 sum |al(y_k - g) + lam_k/mu|^2 (Eq. 16)
+    grad = 2 * A * (g - h) - mu * al * sum(al * (ys[k] - g) + lams[k] / mu for k in range(3))
+    assert np.abs(grad).max() < 1e-10
+
+
+def test_w_and_x_updates():
+    rng = np.random.default_rng(6)
+    mu = 100.0
+    for _ in range(10):
+        q = rng.choice([-1.0, 1.0], size=3)
+        x, lam = rng.standard_normal(3), rng.standard_normal(3)
+        w = admm.w_update(x, lam, q, mu)
+        assert abs(q @ w) < 1e-13
+        # brute force: minimise |w - (x - lam/mu)|^2 on the plane q.w = 0
+        t = x - lam / mu
+        kkt = np.block([[2 * np.eye(3), q[:, None]], [q[None, :], np.zeros((1, 1))]])
+        assert np.abs(np.linalg.solve(kkt, np.r_[2 * t, 0.0])[:3] - w).max() < 1e-12
+    hs, ls, ws = rng.standard_normal((3, 2))
+    xe = admm.x_update(hs.sum(), ls.sum(), ws.sum(), 2.0, mu)
+    # derivative of sum_h (x-h)^2/2 + lam (w - x) + mu/2 (w - x)^2 vanishes
+    deriv = sum((xe - hs[k]) - ls[k] - mu * (ws[k] - xe) for k in range(2))
+    assert abs(deriv) < 1e-10
+
+
+def test_admm_fixed_point_on_integrable_field():
+    v, f = meshgen.grid(9, 0.2, seed=2)
+    topo = mesh.build_topology(f, v.shape[0])
+    a = np.array([0.3, 0.9, 0.0]) / np.linalg.norm([0.3, 0.9])
+    h = np.tile(a, (f.shape[0], 1))
+    fs = admm.FaceADMM(v, f, topo, h).run(5)
+    assert np.abs(fs.g - h).max() < 1e-14 and np.abs(fs.lam).max() < 1e-12
+    es = admm.EdgeADMM(topo, gradient.edge_targets(v, topo, h)).run(5)
+    ell = v @ a
+    assert np.abs(es.x - (ell[topo.edges[:, 1]] - ell[topo.edges[:, 0]])).max() < 1e-13
+
+
+def test_converged_admm_integrates_to_poisson(bumpy3):
+    """Face and edge ADMM run to convergence, integrated in breadth-first
+    order, reproduce the face and edge Poisson distances."""
+    v, f = bumpy3
+    src = [23]
+    for form in ("face", "edge"):
+        r = pipeline.heat_method(v, f, src, form=form)
+        if form == "face":
+            st = admm.FaceADMM(v, f, r.topo, r.h).run(6000, 1e-13, 1e-13)
+            d = integrate.integrate_face(v, r.topo, st.g, r.level, r.parent, src)
+        else:
+            Z = gradient.edge_targets(v, r.topo, r.h)
+            st = admm.EdgeADMM(r.topo, Z).run(6000, 1e-13)
+            d = integrate.integrate_edge(r.topo, st.x, r.level, r.parent, src)
+        mean, mx = metrics.parity(d, r.d)
+        assert mx < 1e-8, (form, mean, mx)
+
+
+def test_admm_residuals_decrease(bumpy3):
+    v, f = bumpy3
+    r = pipeline.heat_method(v, f, [0], form="edge")
+    ea = admm.EdgeADMM(r.topo, gradient.edge_targets(v, r.topo, r.h))
+    s10 = ea.run(10)
+    s200 = ea.run(200)
+    assert s200.r_primal < s10.r_primal and s200.r_dual < s10.r_dual
+
+
+# ------------------------------------------------------ BFS / integration
+def test_bfs_levels_match_library_and_parent_rule():
+    v, f = meshgen.grid(12, 0.1, seed=8)
+    topo = mesh.build_topology(f, v.shape[0])
+    rp, col = mesh.vertex_adjacency(v.shape[0], topo.edges)
+    src = [5, 77]
+    lev, par = bfs.bfs_levels(v.shape[0], rp, col, src)
+    lev2, par2 = bfs.bfs_levels_vec(v.shape[0], rp, col, src)
+    G = sp.csr_matrix((np.ones(col.size), col, rp), shape=(v.shape[0],) * 2)
+    hops = shortest_path(G, unweighted=True, indices=src, directed=False).min(axis=0)
+    assert np.array_equal(lev, hops.astype(np.int64))
+    assert np.array_equal(lev, lev2) and np.array_equal(par, par2)
+    for j in range(v.shape[0]):
+        if lev[j] > 0:
+            nb = col[rp[j]:rp[j + 1]]
+            assert par[j] == nb[lev[nb] == lev[j] - 1].min()
+
+
+def test_integration_exact_for_exact_fields():
+    v, f = meshgen.icosphere(3)
+    topo = mesh.build_topology(f, v.shape[0])
+    rp, col = mesh.vertex_adjacency(v.shape[0], topo.edges)
+    src = [9]
+    lev, par = bfs.bfs_levels_vec(v.shape[0], rp, col, src)
+    d = np.random.default_rng(0).standard_normal(v.shape[0])
+    d -= d[9]
+    x = d[topo.edges[:, 1]] - d[topo.edges[:, 0]]
+    assert np.abs(integrate.integrate_edge(topo, x, lev, par, src) - d).max() < 1e-12
+    g = gradient.face_gradients(v, f, d)
+    assert np.abs(integrate.integrate_face(v, topo, g, lev, par, src) - d).max() < 1e-12
+
+
+def test_unreachable_component_is_infinite():
+    v1, f1 = meshgen.icosphere(1)
+    v = np.concatenate([v1, v1 + 5.0])
+    f = np.concatenate([f1, f1 + v1.shape[0]])
+    r = pipeline.heat_method(v, f, [0])
+    assert np.all(np.isfinite(r.d[:v1.shape[0]])) and np.all(np.isinf(r.d[v1.shape[0]:]))
+    assert np.all(r.level[v1.shape[0]:] == -1)
