@@ -1,0 +1,196 @@
+/*
+ * hgeo -- the parallel heat method for geodesic distance on triangle meshes
+ * (Tao, Zhang, Deng, Fang, Peng, He: "Parallel and Scalable Heat Methods for
+ * Geodesic Distance Computation", arXiv 1812.06060), as a C ABI over HIP
+ * kernels for AMD Instinct MI355X (gfx950).
+ *
+ * Pipeline of one solve (Algorithm 1 of the paper):
+ *   1. breadth-first vertex sets D_i from the sources and the pairing of each
+ *      vertex with a neighbour one set closer (Eq. 6, Sec. 3.3);
+ *   2. heat diffusion (A - t L_c) u = u_0 (Eq. 4) by sweep iterations of the
+ *      update Eq. 7, in FP64 with a per-vertex binary exponent so that u
+ *      never underflows;
+ *   3. face-wise normalisation h = -grad u / |grad u| (Eq. 3), plus the edge
+ *      targets of Eq. 18 for the edge form;
+ *   4. ADMM optimisation of integrable gradients: face form (Sec. 3.2,
+ *      Eqs. 9-16) or edge form (Sec. 4.1, Eqs. 19-21), FP32;
+ *   5. integration of the optimised gradients along the pairing (Eq. 17 and
+ *      Sec. 4), FP32 with compensated (double-float) summation.
+ *
+ * Conventions shared by every entry point:
+ *   - Vertex, face and edge arrays passed in or out are in the caller's
+ *     order: vertices and faces as given to hg_mesh_create, edges in the
+ *     canonical order = unique undirected edges sorted by (min id, max id).
+ *     The orientation halfedge of an edge runs from its smaller to its larger
+ *     vertex id; an edge difference is x_e = d(larger) - d(smaller).
+ *   - Source lists are HOST int32 arrays of vertex ids (duplicates ignored).
+ *   - Every other array argument named *_dev is a DEVICE pointer on the
+ *     current HIP device, caller-owned; the library only reads or writes it.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     on it; an entry point returns after its results are written (it waits
+ *     on the stream to read convergence flags).
+ *   - Errors are reported by status code; hg_last_error() returns a
+ *     thread-local message for the last failing call.  No C++ exception
+ *     crosses the ABI.  A failed call leaves existing meshes usable.
+ */
+#ifndef HGEO_H
+#define HGEO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hg_mesh_s* hg_mesh_t;
+
+typedef enum {
+    HG_OK = 0,
+    HG_E_INVALID_ARG = 1,   /* null pointer, bad size, source out of range, ... */
+    HG_E_BAD_MESH = 2,      /* index out of range, degenerate face, non-manifold
+                               edge, inconsistent orientation */
+    HG_E_OOM = 3,           /* device allocation failed */
+    HG_E_NOT_CONVERGED = 4, /* iteration cap reached; results are still written */
+    HG_E_DEVICE = 5         /* a HIP call failed */
+} hg_status;
+
+enum { HG_FORM_FACE = 0, HG_FORM_EDGE = 1 };
+
+/* Solve options.  hg_opts_default() fills the defaults listed here. */
+typedef struct {
+    int32_t formulation;    /* HG_FORM_EDGE (default) or HG_FORM_FACE */
+    double m;               /* t = m * hbar^2 when the solve's t <= 0
+                               (Eq. 27, hbar = mean edge length); default 1 */
+    double tol_u;           /* diffusion: stop when the largest relative change
+                               of u over one sweep is <= tol_u; default 1e-11 */
+    double tol_admm;        /* ADMM: stop when the primal and dual residuals
+                               are <= tol_admm in the form's scale (see
+                               hg_geodesic_solve); default 2e-6 */
+    int32_t max_sweeps;     /* diffusion sweep cap; default 100000 */
+    int32_t max_admm;       /* ADMM iteration cap; default 50000 */
+    double mu;              /* ADMM penalty (the paper's 100) */
+    int32_t check_every;    /* iterations between convergence checks; 32 */
+    int32_t diffusion_schedule; /* 0 = auto, 1 = global Jacobi sweeps,
+                                   2 = LDS-tiled patch sweeps */
+    int32_t inner_sweeps;   /* patch schedule: sweeps per global pass; 0 = auto */
+    int32_t reserved[8];
+} hg_opts;
+
+/* Per-solve report. */
+typedef struct {
+    int32_t bfs_depth;      /* largest breadth-first level reached */
+    int32_t sweeps;         /* diffusion sweeps performed (all schedules) */
+    int32_t passes;         /* diffusion global passes (= sweeps for Jacobi) */
+    int32_t admm_iters;     /* ADMM iterations performed */
+    double res_u;           /* final largest relative sweep change of u */
+    double res_primal;      /* final ADMM primal residual (form's scale) */
+    double res_dual;        /* final ADMM dual residual (form's scale) */
+    double t;               /* diffusion time used */
+    float ms_bfs, ms_diffusion, ms_normalize, ms_admm, ms_integrate, ms_total;
+    uint64_t bytes_alg;     /* algorithmic HBM bytes of the solve's kernels */
+    uint64_t workspace_bytes; /* device bytes held for this mesh's queries */
+    int32_t converged_u, converged_admm;
+    /* average device time of one diffusion-pass kernel and of one ADMM
+       iteration kernel, from HIP events around back-to-back launches on the
+       solve's stream, and the algorithmic HBM bytes one such launch moves */
+    float ms_pass_kernel, ms_admm_kernel;
+    uint64_t bytes_pass_kernel, bytes_admm_kernel;
+    int32_t reserved[8];
+} hg_info;
+
+/* Mesh statistics. */
+typedef struct {
+    int64_t nv, nf, ne, n_boundary_edges;
+    double hbar;            /* mean edge length (Eq. 27) */
+    double total_area;
+    int32_t max_valence;
+    int32_t n_patches;      /* LDS tiles of the patch diffusion schedule */
+    uint64_t mesh_bytes;    /* device bytes held by the mesh */
+    int32_t reserved[8];
+} hg_mesh_stats;
+
+/* Fill *opts with the defaults above. */
+hg_status hg_opts_default(hg_opts* opts);
+
+/*
+ * Build a resident device mesh (Sec. 3: manifold triangle mesh M=(V,E,F)).
+ *   xyz  : HOST float64[nv*3] vertex positions.
+ *   tri  : HOST int32[nf*3] counter-clockwise triangles (0-based ids).
+ * Validates indices, rejects degenerate faces, edges with more than two
+ * faces and inconsistently oriented neighbours (HG_E_BAD_MESH).  Computes on
+ * the GPU: face areas, cotangent weights theta_jk = (cot a + cot b)/2, lumped
+ * vertex areas A_j = (1/3) sum of incident face areas (Sec. 3.1), the mean
+ * edge length; builds the breadth-first/LDS-tile schedules' connectivity.
+ * The mesh owns its device memory until hg_mesh_destroy.
+ */
+hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf,
+                         void* stream, hg_mesh_t* out);
+void hg_mesh_destroy(hg_mesh_t mesh);
+hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* stats);
+
+/*
+ * Geodesic distance from a source set (Algorithm 1; several sources as in
+ * Sec. 5.2: all in D_0, u_0 = 1 at each, distance 0 at each).
+ *   src, nsrc : HOST int32 source vertex ids, nsrc >= 1.
+ *   t         : diffusion time; t <= 0 means m * hbar^2.
+ *   opts      : NULL = defaults.
+ *   d_dev     : DEVICE float32[nv] output distances (caller order);
+ *               vertices not connected to a source get +inf.
+ *   info      : optional report.
+ * ADMM stopping scale: face form as in Sec. 3.2, |r_p| <= |M|_F tol and
+ * |r_d| <= |M|_F tol; edge form rms(r_p) <= tol*hbar and
+ * rms(r_d)/mu <= tol*hbar over the 3|F| copies.
+ * Returns HG_E_NOT_CONVERGED (results written) if a cap was hit.
+ */
+hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
+                            const hg_opts* opts, float* d_dev, void* stream, hg_info* info);
+
+/* ---- the individual steps, each running the same kernels as the solve ---- */
+
+/* Breadth-first sets (Eq. 6): level_dev[v] = hop distance to the source set
+ * (-1 if unreachable); parent_dev[v] = the neighbour with level one less and
+ * the smallest vertex id (-1 for sources and unreachable vertices).
+ * DEVICE int32[nv] outputs (either may be NULL). */
+hg_status hg_bfs(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
+                 int32_t* level_dev, int32_t* parent_dev, void* stream, int32_t* depth_out);
+
+/* Diffusion (Eq. 4 by sweeps of Eq. 7): logu_dev = DEVICE float64[nv], the
+ * natural log of u (-inf where u = 0).  Uses opts->tol_u / max_sweeps /
+ * diffusion_schedule; info receives sweeps, passes, res_u, t. */
+hg_status hg_diffuse(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
+                     const hg_opts* opts, double* logu_dev, void* stream, hg_info* info);
+
+/* Normalisation (Eq. 3) from DEVICE float64[nv] log u: h_dev = DEVICE
+ * float32[nf*3] unit vectors (0 where the gradient vanishes). */
+hg_status hg_normalize(hg_mesh_t mesh, const double* logu_dev, float* h_dev, void* stream);
+
+/* Edge-form ADMM (Sec. 4.1) from DEVICE float32[nf*3] normalised field h:
+ * x_dev = DEVICE float32[ne] edge differences after `iters` iterations
+ * (iters <= 0: run to opts->tol_admm / max_admm). */
+hg_status hg_admm_edge(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts,
+                       float* x_dev, void* stream, hg_info* info);
+
+/* Face-form ADMM (Sec. 3.2): g_dev = DEVICE float32[nf*3] gradients. */
+hg_status hg_admm_face(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts,
+                       float* g_dev, void* stream, hg_info* info);
+
+/* Integration along the breadth-first pairing (Sec. 3.3 / Sec. 4) of edge
+ * differences x_dev (float32[ne]) or face gradients g_dev (float32[nf*3]),
+ * d_dev = DEVICE float32[nv]. */
+hg_status hg_integrate_edge(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
+                            const float* x_dev, float* d_dev, void* stream);
+hg_status hg_integrate_face(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
+                            const float* g_dev, float* d_dev, void* stream);
+
+/* Canonical edge list: DEVICE int32[ne*2] (smaller id, larger id). */
+hg_status hg_mesh_edges(hg_mesh_t mesh, int32_t* edges_dev, void* stream);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* hg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGEO_H */

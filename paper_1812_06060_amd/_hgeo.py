@@ -1,0 +1,293 @@
+"""ctypes binding of libhgeo.so (the C ABI of include/hgeo.h).
+
+Argument marshalling only: every step of the geodesic pipeline runs in the
+library's HIP kernels.  torch supplies device memory and streams.  The
+binding refuses to run when the compiled library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgeo.so")
+
+HG_OK, HG_E_INVALID_ARG, HG_E_BAD_MESH, HG_E_OOM, HG_E_NOT_CONVERGED, HG_E_DEVICE = range(6)
+FORM_FACE, FORM_EDGE = 0, 1
+_STATUS = {0: "HG_OK", 1: "HG_E_INVALID_ARG", 2: "HG_E_BAD_MESH", 3: "HG_E_OOM",
+           4: "HG_E_NOT_CONVERGED", 5: "HG_E_DEVICE"}
+
+
+class HgeoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.msg = msg
+
+
+class NotConverged(HgeoError):
+    pass
+
+
+class Opts(C.Structure):
+    _fields_ = [
+        ("formulation", C.c_int32), ("m", C.c_double), ("tol_u", C.c_double),
+        ("tol_admm", C.c_double), ("max_sweeps", C.c_int32), ("max_admm", C.c_int32),
+        ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
+        ("inner_sweeps", C.c_int32), ("reserved", C.c_int32 * 8),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("bfs_depth", C.c_int32), ("sweeps", C.c_int32), ("passes", C.c_int32),
+        ("admm_iters", C.c_int32), ("res_u", C.c_double), ("res_primal", C.c_double),
+        ("res_dual", C.c_double), ("t", C.c_double),
+        ("ms_bfs", C.c_float), ("ms_diffusion", C.c_float), ("ms_normalize", C.c_float),
+        ("ms_admm", C.c_float), ("ms_integrate", C.c_float), ("ms_total", C.c_float),
+        ("bytes_alg", C.c_uint64), ("workspace_bytes", C.c_uint64),
+        ("converged_u", C.c_int32), ("converged_admm", C.c_int32),
+        ("ms_pass_kernel", C.c_float), ("ms_admm_kernel", C.c_float),
+        ("bytes_pass_kernel", C.c_uint64), ("bytes_admm_kernel", C.c_uint64),
+        ("reserved", C.c_int32 * 8),
+    ]
+
+    def as_dict(self):
+        return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_ if k != "reserved"}
+
+
+class MeshStats(C.Structure):
+    _fields_ = [
+        ("nv", C.c_int64), ("nf", C.c_int64), ("ne", C.c_int64), ("n_boundary_edges", C.c_int64),
+        ("hbar", C.c_double), ("total_area", C.c_double), ("max_valence", C.c_int32),
+        ("n_patches", C.c_int32), ("mesh_bytes", C.c_uint64), ("reserved", C.c_int32 * 8),
+    ]
+
+
+# (name, argtypes)
+_P = C.c_void_p
+_API = {
+    "hg_opts_default": [C.POINTER(Opts)],
+    "hg_mesh_create": [_P, C.c_int64, _P, C.c_int64, _P, C.POINTER(_P)],
+    "hg_mesh_destroy": [_P],
+    "hg_mesh_get_stats": [_P, C.POINTER(MeshStats)],
+    "hg_geodesic_solve": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_bfs": [_P, _P, C.c_int32, _P, _P, _P, C.POINTER(C.c_int32)],
+    "hg_diffuse": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_normalize": [_P, _P, _P, _P],
+    "hg_admm_edge": [_P, _P, C.c_int32, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_admm_face": [_P, _P, C.c_int32, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_integrate_edge": [_P, _P, C.c_int32, _P, _P, _P],
+    "hg_integrate_face": [_P, _P, C.c_int32, _P, _P, _P],
+    "hg_mesh_edges": [_P, _P, _P],
+    "hg_last_error": [],
+}
+EXPORTED = tuple(_API)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhgeo.so and declare its prototypes (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1812_06060_amd.build`")
+    lib = C.CDLL(path)
+    for name, args in _API.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        if name == "hg_last_error":
+            fn.restype = C.c_char_p
+        elif name == "hg_mesh_destroy":
+            fn.restype = None
+        else:
+            fn.restype = C.c_int
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st == HG_OK:
+        return
+    msg = _lib.hg_last_error().decode()
+    if st == HG_E_NOT_CONVERGED:
+        raise NotConverged(st, msg)
+    raise HgeoError(st, msg)
+
+
+def default_opts(**kw) -> Opts:
+    lib = load_library()
+    o = Opts()
+    lib.hg_opts_default(C.byref(o))
+    form = kw.pop("formulation", None)
+    if form is not None:
+        o.formulation = {"face": FORM_FACE, "edge": FORM_EDGE}.get(form, form)
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("hgeo needs a ROCm GPU (torch.cuda is not available)")
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _src_array(sources):
+    a = np.ascontiguousarray(np.atleast_1d(np.asarray(sources, dtype=np.int32)))
+    return a, a.ctypes.data_as(C.c_void_p), C.c_int32(a.size)
+
+
+def _dptr(t, dtype, numel):
+    torch = _torch()
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"expected a contiguous CUDA {dtype} tensor with {numel} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveInfo:
+    raw: dict
+
+    def __getattr__(self, k):
+        try:
+            return self.raw[k]
+        except KeyError:
+            raise AttributeError(k)
+
+
+class Mesh:
+    """A resident device mesh (hg_mesh_create)."""
+
+    def __init__(self, verts, tris, stream=None):
+        load_library()
+        _torch()
+        v = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
+        f = np.ascontiguousarray(np.asarray(tris, dtype=np.int32))
+        if v.ndim != 2 or v.shape[1] != 3 or f.ndim != 2 or f.shape[1] != 3:
+            raise ValueError("verts must be [V,3] and tris [F,3]")
+        h = C.c_void_p()
+        _check(_lib.hg_mesh_create(v.ctypes.data_as(C.c_void_p), v.shape[0],
+                                   f.ctypes.data_as(C.c_void_p), f.shape[0], _stream(stream), C.byref(h)))
+        self._h = h
+        st = MeshStats()
+        _check(_lib.hg_mesh_get_stats(self._h, C.byref(st)))
+        self.nv, self.nf, self.ne = st.nv, st.nf, st.ne
+        self.hbar = st.hbar
+        self.total_area = st.total_area
+        self.stats = {k: getattr(st, k) for k, _ in st._fields_ if k != "reserved"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hg_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ whole solve
+    def solve(self, sources, t: float = 0.0, opts: Opts | None = None, out=None, stream=None,
+              raise_on_nonconvergence: bool = True):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.nv, dtype=torch.float32, device="cuda")
+        a, p, n = _src_array(sources)
+        info = Info()
+        st = _lib.hg_geodesic_solve(self._h, p, n, float(t), C.byref(opts) if opts else None,
+                                    _dptr(out, torch.float32, self.nv), _stream(stream), C.byref(info))
+        if st != HG_E_NOT_CONVERGED or raise_on_nonconvergence:
+            _check(st)
+        return out, SolveInfo(info.as_dict())
+
+    # ---------------------------------------------------------------- stages
+    def edges(self, stream=None):
+        torch = _torch()
+        out = torch.empty((self.ne, 2), dtype=torch.int32, device="cuda")
+        _check(_lib.hg_mesh_edges(self._h, _dptr(out, torch.int32, 2 * self.ne), _stream(stream)))
+        return out
+
+    def bfs(self, sources, stream=None):
+        torch = _torch()
+        lev = torch.empty(self.nv, dtype=torch.int32, device="cuda")
+        par = torch.empty(self.nv, dtype=torch.int32, device="cuda")
+        a, p, n = _src_array(sources)
+        depth = C.c_int32()
+        _check(_lib.hg_bfs(self._h, p, n, _dptr(lev, torch.int32, self.nv), _dptr(par, torch.int32, self.nv),
+                           _stream(stream), C.byref(depth)))
+        return lev, par, depth.value
+
+    def diffuse(self, sources, t: float = 0.0, opts: Opts | None = None, stream=None,
+                raise_on_nonconvergence: bool = True):
+        torch = _torch()
+        out = torch.empty(self.nv, dtype=torch.float64, device="cuda")
+        a, p, n = _src_array(sources)
+        info = Info()
+        st = _lib.hg_diffuse(self._h, p, n, float(t), C.byref(opts) if opts else None,
+                             _dptr(out, torch.float64, self.nv), _stream(stream), C.byref(info))
+        if st != HG_E_NOT_CONVERGED or raise_on_nonconvergence:
+            _check(st)
+        return out, SolveInfo(info.as_dict())
+
+    def normalize(self, logu, stream=None):
+        torch = _torch()
+        h = torch.empty((self.nf, 3), dtype=torch.float32, device="cuda")
+        _check(_lib.hg_normalize(self._h, _dptr(logu, torch.float64, self.nv),
+                                 _dptr(h, torch.float32, 3 * self.nf), _stream(stream)))
+        return h
+
+    def admm_edge(self, h, iters: int = 0, opts: Opts | None = None, stream=None):
+        torch = _torch()
+        x = torch.empty(self.ne, dtype=torch.float32, device="cuda")
+        info = Info()
+        st = _lib.hg_admm_edge(self._h, _dptr(h, torch.float32, 3 * self.nf), int(iters),
+                               C.byref(opts) if opts else None, _dptr(x, torch.float32, self.ne),
+                               _stream(stream), C.byref(info))
+        _check(st)
+        return x, SolveInfo(info.as_dict())
+
+    def admm_face(self, h, iters: int = 0, opts: Opts | None = None, stream=None):
+        torch = _torch()
+        g = torch.empty((self.nf, 3), dtype=torch.float32, device="cuda")
+        info = Info()
+        st = _lib.hg_admm_face(self._h, _dptr(h, torch.float32, 3 * self.nf), int(iters),
+                               C.byref(opts) if opts else None, _dptr(g, torch.float32, 3 * self.nf),
+                               _stream(stream), C.byref(info))
+        _check(st)
+        return g, SolveInfo(info.as_dict())
+
+    def integrate_edge(self, sources, x, stream=None):
+        torch = _torch()
+        d = torch.empty(self.nv, dtype=torch.float32, device="cuda")
+        a, p, n = _src_array(sources)
+        _check(_lib.hg_integrate_edge(self._h, p, n, _dptr(x, torch.float32, self.ne),
+                                      _dptr(d, torch.float32, self.nv), _stream(stream)))
+        return d
+
+    def integrate_face(self, sources, g, stream=None):
+        torch = _torch()
+        d = torch.empty(self.nv, dtype=torch.float32, device="cuda")
+        a, p, n = _src_array(sources)
+        _check(_lib.hg_integrate_face(self._h, p, n, _dptr(g, torch.float32, 3 * self.nf),
+                                      _dptr(d, torch.float32, self.nv), _stream(stream)))
+        return d

@@ -1,0 +1,389 @@
+// C ABI of the hgeo library (declared in include/hgeo.h): argument checks,
+// conversion of errors to status codes, and the order of the stages of one
+// solve (Algorithm 1 of the paper).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hgeo_internal.h"
+
+namespace hg {
+
+static thread_local std::string g_last_error;
+
+size_t Mesh::Work::bytes() const {
+    return level.bytes() + parent.bytes() + pslot.bytes() + frontier_a.bytes() + frontier_b.bytes() +
+           counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
+           h.bytes() + sumz.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
+           shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
+           src.bytes();
+}
+
+uint64_t Mesh::mesh_bytes() const {
+    return px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
+           row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
+           tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() + ebar.bytes() +
+           halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes();
+}
+
+Mesh::~Mesh() {
+    if (w.pinned) (void)hipHostFree(w.pinned);
+}
+
+static hg_status fail(hg_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+static hg_status guarded(F&& fn) {
+    try {
+        g_last_error.clear();
+        return fn();
+    } catch (const Error& e) {
+        return fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(HG_E_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(HG_E_DEVICE, e.what());
+    } catch (...) {
+        return fail(HG_E_DEVICE, "unknown error");
+    }
+}
+
+static std::vector<int32_t> map_sources(const Mesh& m, const int32_t* src, int32_t nsrc) {
+    if (!src || nsrc <= 0) throw Error{HG_E_INVALID_ARG, "empty source list"};
+    std::vector<int32_t> out;
+    out.reserve(nsrc);
+    for (int32_t i = 0; i < nsrc; ++i) {
+        if (src[i] < 0 || src[i] >= m.nv) throw Error{HG_E_INVALID_ARG, "source index out of range"};
+        out.push_back(m.iperm_v_host[src[i]]);
+    }
+    return out;
+}
+
+static hg_opts resolve_opts(const hg_opts* o) {
+    hg_opts r;
+    hg_opts_default(&r);
+    if (o) r = *o;
+    if (r.formulation != HG_FORM_FACE && r.formulation != HG_FORM_EDGE)
+        throw Error{HG_E_INVALID_ARG, "formulation must be HG_FORM_FACE or HG_FORM_EDGE"};
+    if (!(r.mu > 0.0)) throw Error{HG_E_INVALID_ARG, "mu must be positive"};
+    if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
+        throw Error{HG_E_INVALID_ARG, "iteration caps must be positive"};
+    return r;
+}
+
+static double resolve_t(const Mesh& m, double t, const hg_opts& o) {
+    if (t > 0.0 && std::isfinite(t)) return t;
+    double mm = (o.m > 0.0 && std::isfinite(o.m)) ? o.m : 1.0;
+    return mm * m.hbar * m.hbar;
+}
+
+static void ensure_pinned(Mesh& m) {
+    if (!m.w.pinned) HG_CHECK_HIP(hipHostMalloc(&m.w.pinned, 8 * sizeof(double), hipHostMallocDefault));
+}
+
+struct StageTimer {
+    hipStream_t s;
+    hipEvent_t ev[8];
+    int n = 0;
+    explicit StageTimer(hipStream_t st) : s(st) {
+        for (auto& e : ev) HG_CHECK_HIP(hipEventCreate(&e));
+    }
+    ~StageTimer() {
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+    void mark() { HG_CHECK_HIP(hipEventRecord(ev[n++], s)); }
+    float ms(int a, int b) {
+        float r = 0.f;
+        HG_CHECK_HIP(hipEventSynchronize(ev[b]));
+        HG_CHECK_HIP(hipEventElapsedTime(&r, ev[a], ev[b]));
+        return r;
+    }
+};
+
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" {
+
+hg_status hg_opts_default(hg_opts* o) {
+    if (!o) return HG_E_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->formulation = HG_FORM_EDGE;
+    o->m = 1.0;
+    o->tol_u = 1e-11;
+    o->tol_admm = 2e-6;
+    o->max_sweeps = 100000;
+    o->max_admm = 50000;
+    o->mu = 100.0;
+    o->check_every = 32;
+    o->diffusion_schedule = 0;
+    o->inner_sweeps = 0;
+    return HG_OK;
+}
+
+const char* hg_last_error(void) { return g_last_error.c_str(); }
+
+hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, void* stream,
+                         hg_mesh_t* out) {
+    return guarded([&]() -> hg_status {
+        if (!xyz || !tri || !out) return fail(HG_E_INVALID_ARG, "null argument");
+        *out = nullptr;
+        hipStream_t s = (hipStream_t)stream;
+        HostTopo T;
+        build_topology(xyz, nv, tri, nf, 1024, T);
+        auto* m = new Mesh();
+        try {
+            HG_CHECK_HIP(hipGetDevice(&m->device));
+            m->nv = T.nv;
+            m->nf = T.nf;
+            m->ne = T.ne;
+            m->nbnd = T.nbnd;
+            m->max_valence = T.max_valence;
+            m->iperm_v_host = T.iperm_v;
+            m->px.upload(T.px, s);
+            m->py.upload(T.py, s);
+            m->pz.upload(T.pz, s);
+            m->perm_v.upload(T.perm_v, s);
+            m->perm_f.upload(T.perm_f, s);
+            m->perm_e.upload(T.perm_e, s);
+            m->row_ptr.upload(T.row_ptr, s);
+            m->col.upload(T.col, s);
+            m->csr_edge.upload(T.csr_edge, s);
+            m->tri.upload(T.tri, s);
+            m->fslot.upload(T.fslot, s);
+            m->fsign.upload(T.fsign, s);
+            m->ev.upload(T.ev, s);
+            m->ef.upload(T.ef, s);
+            m->patch_size = T.patch_size;
+            m->n_patches = (int)(T.halo_ptr.size() - 1);
+            m->max_halo = T.max_halo;
+            m->max_ell_width = T.max_ell_width;
+            m->halo_ptr.upload(T.halo_ptr, s);
+            m->halo_idx.upload(T.halo_idx, s);
+            m->ell_ptr.upload(T.ell_ptr, s);
+            m->lnb.upload(T.lnb, s);
+            m->ell_width.upload(T.ell_width, s);
+            ensure_pinned(*m);
+            geometry_init(*m, s);
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = reinterpret_cast<hg_mesh_t>(m);
+        return HG_OK;
+    });
+}
+
+void hg_mesh_destroy(hg_mesh_t mesh) { delete reinterpret_cast<Mesh*>(mesh); }
+
+hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* st) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !st) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        std::memset(st, 0, sizeof(*st));
+        st->nv = m->nv;
+        st->nf = m->nf;
+        st->ne = m->ne;
+        st->n_boundary_edges = m->nbnd;
+        st->hbar = m->hbar;
+        st->total_area = m->total_area;
+        st->max_valence = m->max_valence;
+        st->n_patches = m->n_patches;
+        st->mesh_bytes = m->mesh_bytes();
+        return HG_OK;
+    });
+}
+
+hg_status hg_mesh_edges(hg_mesh_t mesh, int32_t* edges_dev, void* stream) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !edges_dev) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        edges_to_user(*m, edges_dev, s);
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        return HG_OK;
+    });
+}
+
+hg_status hg_bfs(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, int32_t* level_dev, int32_t* parent_dev,
+                 void* stream, int32_t* depth_out) {
+    return guarded([&]() -> hg_status {
+        if (!mesh) return fail(HG_E_INVALID_ARG, "null mesh");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        auto si = map_sources(*m, src, nsrc);
+        int depth = run_bfs(*m, si, s);
+        if (level_dev) scatter_vertices_to_user_i(*m, m->w.level.p, level_dev, false, s);
+        if (parent_dev) scatter_vertices_to_user_i(*m, m->w.parent.p, parent_dev, true, s);
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        if (depth_out) *depth_out = depth;
+        return HG_OK;
+    });
+}
+
+hg_status hg_diffuse(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
+                     double* logu_dev, void* stream, hg_info* info) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !logu_dev) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        hg_opts o = resolve_opts(opts);
+        auto si = map_sources(*m, src, nsrc);
+        double tt = resolve_t(*m, t, o);
+        int depth = run_bfs(*m, si, s);
+        DiffusionResult r = run_diffusion(*m, si, tt, o, s);
+        diffusion_logu(*m, s);
+        scatter_vertices_to_user_d(*m, m->w.logu.p, logu_dev, s);
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->bfs_depth = depth;
+            info->sweeps = r.sweeps;
+            info->passes = r.passes;
+            info->res_u = r.res;
+            info->t = tt;
+            info->converged_u = r.converged;
+        }
+        return r.converged ? HG_OK : fail(HG_E_NOT_CONVERGED, "diffusion sweep cap reached");
+    });
+}
+
+hg_status hg_normalize(hg_mesh_t mesh, const double* logu_dev, float* h_dev, void* stream) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !logu_dev || !h_dev) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        normalize_from_logu(*m, logu_dev, s);
+        scatter_faces_to_user(*m, m->w.h.p, h_dev, s);
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        return HG_OK;
+    });
+}
+
+static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts, float* out,
+                            void* stream, hg_info* info, int form) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !h_dev || !out) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        hg_opts o = resolve_opts(opts);
+        m->w.h.alloc((size_t)3 * m->nf);
+        gather_faces_to_internal(*m, h_dev, m->w.h.p, s);
+        AdmmResult r = form == HG_FORM_EDGE ? run_admm_edge(*m, iters, o, s) : run_admm_face(*m, iters, o, s);
+        if (form == HG_FORM_EDGE)
+            scatter_edges_to_user(*m, m->w.xe.p, out, s);
+        else
+            scatter_faces_to_user(*m, m->w.gf.p, out, s);
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->admm_iters = r.iters;
+            info->res_primal = r.rp;
+            info->res_dual = r.rd;
+            info->converged_admm = r.converged;
+        }
+        return r.converged ? HG_OK : fail(HG_E_NOT_CONVERGED, "ADMM iteration cap reached");
+    });
+}
+
+hg_status hg_admm_edge(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts, float* x_dev,
+                       void* stream, hg_info* info) {
+    return admm_stage(mesh, h_dev, iters, opts, x_dev, stream, info, HG_FORM_EDGE);
+}
+
+hg_status hg_admm_face(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts, float* g_dev,
+                       void* stream, hg_info* info) {
+    return admm_stage(mesh, h_dev, iters, opts, g_dev, stream, info, HG_FORM_FACE);
+}
+
+static hg_status integrate_stage(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, const float* in, float* d_dev,
+                                 void* stream, int form) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !in || !d_dev) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        auto si = map_sources(*m, src, nsrc);
+        int depth = run_bfs(*m, si, s);
+        if (form == HG_FORM_EDGE) {
+            m->w.xe.alloc(m->ne);
+            gather_edges_to_internal(*m, in, m->w.xe.p, s);
+        } else {
+            m->w.gf.alloc((size_t)3 * m->nf);
+            gather_faces_to_internal(*m, in, m->w.gf.p, s);
+        }
+        integrate(*m, form, depth, d_dev, s);
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        return HG_OK;
+    });
+}
+
+hg_status hg_integrate_edge(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, const float* x_dev, float* d_dev,
+                            void* stream) {
+    return integrate_stage(mesh, src, nsrc, x_dev, d_dev, stream, HG_FORM_EDGE);
+}
+
+hg_status hg_integrate_face(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, const float* g_dev, float* d_dev,
+                            void* stream) {
+    return integrate_stage(mesh, src, nsrc, g_dev, d_dev, stream, HG_FORM_FACE);
+}
+
+hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
+                            float* d_dev, void* stream, hg_info* info) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !d_dev) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        hg_opts o = resolve_opts(opts);
+        auto si = map_sources(*m, src, nsrc);
+        double tt = resolve_t(*m, t, o);
+        StageTimer tm(s);
+        tm.mark();
+        int depth = run_bfs(*m, si, s);
+        tm.mark();
+        DiffusionResult dr = run_diffusion(*m, si, tt, o, s);
+        tm.mark();
+        run_normalize(*m, s);
+        tm.mark();
+        AdmmResult ar = o.formulation == HG_FORM_EDGE ? run_admm_edge(*m, 0, o, s) : run_admm_face(*m, 0, o, s);
+        tm.mark();
+        integrate(*m, o.formulation, depth, d_dev, s);
+        tm.mark();
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->bfs_depth = depth;
+            info->sweeps = dr.sweeps;
+            info->passes = dr.passes;
+            info->admm_iters = ar.iters;
+            info->res_u = dr.res;
+            info->res_primal = ar.rp;
+            info->res_dual = ar.rd;
+            info->t = tt;
+            info->ms_bfs = tm.ms(0, 1);
+            info->ms_diffusion = tm.ms(1, 2);
+            info->ms_normalize = tm.ms(2, 3);
+            info->ms_admm = tm.ms(3, 4);
+            info->ms_integrate = tm.ms(4, 5);
+            info->ms_total = tm.ms(0, 5);
+            info->workspace_bytes = m->w.bytes();
+            info->converged_u = dr.converged;
+            info->converged_admm = ar.converged;
+            info->ms_pass_kernel = dr.timed_launches ? (float)(dr.kernel_ms / dr.timed_launches) : 0.f;
+            info->ms_admm_kernel = ar.timed_launches ? (float)(ar.kernel_ms / ar.timed_launches) : 0.f;
+            info->bytes_pass_kernel = dr.bytes_per_pass;
+            info->bytes_admm_kernel = ar.bytes_per_iter;
+            info->bytes_alg = dr.bytes_per_pass * (uint64_t)dr.passes + ar.bytes_per_iter * (uint64_t)ar.iters;
+        }
+        if (!dr.converged) return fail(HG_E_NOT_CONVERGED, "diffusion sweep cap reached");
+        if (!ar.converged) return fail(HG_E_NOT_CONVERGED, "ADMM iteration cap reached");
+        return HG_OK;
+    });
+}
+
+}  // extern "C"

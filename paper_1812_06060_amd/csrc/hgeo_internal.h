@@ -1,0 +1,233 @@
+// Internal structures of the hgeo library (not part of the C ABI).
+//
+// Device layout of a resident mesh.  Vertices are renumbered internally in
+// 3D Morton order so that one-ring neighbourhoods sit close in memory and
+// contiguous vertex ranges form compact surface patches; faces are sorted by
+// their smallest internal vertex and edges by their internal endpoints.  The
+// permutations back to the caller's order are kept on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hgeo.h"
+
+namespace hg {
+
+// Throwing helpers used inside the library; the C ABI converts to status.
+struct Error {
+    hg_status code;
+    std::string msg;
+};
+
+#define HG_CHECK_HIP(expr)                                                                  \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            throw ::hg::Error{_e == hipErrorOutOfMemory ? HG_E_OOM : HG_E_DEVICE,           \
+                              std::string(#expr) + ": " + hipGetErrorString(_e)};           \
+    } while (0)
+
+// A device buffer owned by the library.
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        if (count == n && p) return;
+        release();
+        if (count == 0) return;
+        HG_CHECK_HIP(hipMalloc(&p, count * sizeof(T)));
+        n = count;
+    }
+    void upload(const std::vector<T>& h, hipStream_t s) {
+        alloc(h.size());
+        if (!h.empty())
+            HG_CHECK_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// Face slot encoding: slot (f, k) refers to the edge (tri[k], tri[k+1]):
+//   fslot = (edge << 2) | (boundary << 1) | side,
+// side = which of the edge's two incident faces f is (0 or 1).
+__host__ __device__ inline int slot_edge(uint32_t s) { return (int)(s >> 2); }
+__host__ __device__ inline int slot_side(uint32_t s) { return (int)(s & 1u); }
+__host__ __device__ inline int slot_bnd(uint32_t s) { return (int)((s >> 1) & 1u); }
+
+// Host-side topology produced by build_topology().
+struct HostTopo {
+    int64_t nv = 0, nf = 0, ne = 0, nbnd = 0;
+    int max_valence = 0;
+    std::vector<int32_t> perm_v, iperm_v;   // internal -> caller, caller -> internal
+    std::vector<double> px, py, pz;         // positions, internal order
+    std::vector<int32_t> row_ptr, col, csr_edge;
+    std::vector<int32_t> tri;               // [nf*3] internal vertex ids
+    std::vector<int32_t> perm_f;            // internal face -> caller face
+    std::vector<uint32_t> fslot;            // [nf*3]
+    std::vector<uint8_t> fsign;             // bit k: slot k has sign +1 (Eq. 20)
+    std::vector<int32_t> ev;                // [ne*2] tail, head (internal ids)
+    std::vector<int32_t> ef;                // [ne*2] incident faces, -1 if none
+    std::vector<int32_t> perm_e;            // internal edge -> canonical edge
+    // patch tiles (contiguous internal vertex ranges) and their halos
+    int patch_size = 0;
+    std::vector<int32_t> halo_ptr, halo_idx;
+    std::vector<uint16_t> lnb;              // ELL local neighbour slots
+    std::vector<int32_t> ell_ptr;           // per patch: offset of its ELL block
+    std::vector<uint8_t> ell_width;         // per patch: ELL width
+    int max_halo = 0;
+    int max_ell_width = 0;
+};
+
+// Builds the host topology; throws Error{HG_E_BAD_MESH} on invalid input.
+void build_topology(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, int patch_size,
+                    HostTopo& out);
+
+struct Mesh {
+    int device = 0;
+    int64_t nv = 0, nf = 0, ne = 0, nbnd = 0;
+    int max_valence = 0;
+    double hbar = 0.0, total_area = 0.0;
+    std::vector<int32_t> iperm_v_host;      // caller id -> internal id (host copy)
+
+    DBuf<double> px, py, pz;
+    DBuf<int32_t> perm_v, perm_f, perm_e;
+    DBuf<int32_t> row_ptr, col, csr_edge;
+    DBuf<double> theta;                     // per CSR entry
+    DBuf<double> Av, sum_theta;             // per vertex
+    DBuf<int32_t> tri;
+    DBuf<uint32_t> fslot;
+    DBuf<uint8_t> fsign;
+    DBuf<double> farea;                     // per face (FP64)
+    DBuf<int32_t> ev, ef;
+    DBuf<float> ebar;                       // [ne*3] unit edge vectors (face form)
+
+    // patch tiles
+    int patch_size = 0, n_patches = 0, max_halo = 0, max_ell_width = 0;
+    DBuf<int32_t> halo_ptr, halo_idx, ell_ptr;
+    DBuf<uint16_t> lnb;
+    DBuf<uint8_t> ell_width;
+
+    // per-query workspace (kept between queries)
+    struct Work {
+        DBuf<int32_t> level, parent, pslot, frontier_a, frontier_b, counters;
+        DBuf<double> v0, v1, invD;          // diffusion mantissas, 1/(A + t sum theta)
+        DBuf<int32_t> e0, e1;               // diffusion exponents
+        DBuf<double> logu;
+        DBuf<float> h;                      // [nf*3] internal order
+        DBuf<float> sumz;                   // [ne] edge-form target sums
+        DBuf<float> z0, z1;                 // edge form: zeta [2*ne]; face form: z [2*ne*3]
+        DBuf<float> g0, g1;                 // face form gradients [nf*3]
+        DBuf<float> xe;                     // [ne] final edge differences (internal)
+        DBuf<float> gf;                     // [nf*3] final face gradients (internal)
+        DBuf<float> shi0, slo0, shi1, slo1; // integration double-float sums
+        DBuf<int32_t> jp0, jp1;             // pointer-jumping parents
+        DBuf<double> partial;               // reduction partials
+        DBuf<double> red_host_dummy;
+        double* pinned = nullptr;           // host pinned reduction results
+        DBuf<int32_t> src;
+        size_t bytes() const;
+    } w;
+
+    uint64_t mesh_bytes() const;
+    ~Mesh();
+};
+
+// ---- kernels / stage drivers (implemented in the .hip files) ----
+void geometry_init(Mesh& m, hipStream_t s);
+int run_bfs(Mesh& m, const std::vector<int32_t>& src_internal, hipStream_t s);
+struct DiffusionResult {
+    int sweeps = 0, passes = 0;
+    double res = 0.0;
+    bool converged = false;
+    double kernel_ms = 0.0;      // summed event time of the pass kernels
+    int timed_launches = 0;      // launches covered by kernel_ms
+    uint64_t bytes_per_pass = 0; // algorithmic HBM bytes of one pass kernel
+};
+DiffusionResult run_diffusion(Mesh& m, const std::vector<int32_t>& src_internal, double t,
+                              const hg_opts& o, hipStream_t s);
+void diffusion_logu(Mesh& m, hipStream_t s);                   // w.logu from (v, e)
+void run_normalize(Mesh& m, hipStream_t s);                    // w.h from (v, e)
+void normalize_from_logu(Mesh& m, const double* logu_user, hipStream_t s);
+struct AdmmResult {
+    int iters = 0;
+    double rp = 0.0, rd = 0.0;
+    bool converged = false;
+    double kernel_ms = 0.0;
+    int timed_launches = 0;
+    uint64_t bytes_per_iter = 0;
+};
+
+// Events around runs of back-to-back launches of one kernel (between two
+// convergence checks) give its average device time without per-launch events.
+struct RunTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool open = false;
+    RunTimer() {
+        HG_CHECK_HIP(hipEventCreate(&a));
+        HG_CHECK_HIP(hipEventCreate(&b));
+    }
+    ~RunTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void start(hipStream_t s) {
+        HG_CHECK_HIP(hipEventRecord(a, s));
+        open = true;
+    }
+    // closes the run; the caller synchronises the stream before reading
+    double stop(hipStream_t s) {
+        if (!open) return 0.0;
+        HG_CHECK_HIP(hipEventRecord(b, s));
+        HG_CHECK_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        HG_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
+        open = false;
+        return ms;
+    }
+};
+AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s);
+AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s);
+void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s);
+
+// permutation helpers
+void gather_faces_to_internal(Mesh& m, const float* user3, float* internal3, hipStream_t s);
+void scatter_faces_to_user(Mesh& m, const float* internal3, float* user3, hipStream_t s);
+void scatter_edges_to_user(Mesh& m, const float* internal, float* user, hipStream_t s);
+void gather_edges_to_internal(Mesh& m, const float* user, float* internal, hipStream_t s);
+void scatter_vertices_to_user_d(Mesh& m, const double* internal, double* user, hipStream_t s);
+void gather_vertices_to_internal_d(Mesh& m, const double* user, double* internal, hipStream_t s);
+void scatter_vertices_to_user_i(Mesh& m, const int32_t* internal, int32_t* user, bool map_values,
+                                hipStream_t s);
+void edges_to_user(Mesh& m, int32_t* edges_user, hipStream_t s);
+
+// reductions: sum or max of n doubles produced per block into w.partial
+double reduce_partials(Mesh& m, int nblocks, bool is_max, hipStream_t s);
+
+inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+// Blocks are dealt round-robin to the 8 XCDs of an MI355X; remap so that
+// each XCD processes one contiguous range of the index space (consecutive
+// blocks share halo cache lines in that XCD's L2).
+__device__ inline int xcd_block(int b, int nb) {
+    const int nx = 8;
+    int per = nb / nx, rem = nb % nx;
+    int x = b % nx, i = b / nx;
+    int start = x * per + (x < rem ? x : rem);
+    int idx = start + i;
+    return idx;
+}
+
+}  // namespace hg

@@ -1,0 +1,504 @@
+// Normalisation (Eq. 3), edge targets (Eq. 18) and the two ADMM solvers of
+// the gradient optimisation: face form (Sec. 3.2) and edge form (Sec. 4.1).
+//
+// Both solvers run the paper's iterations unchanged, with the state folded so
+// that one fused kernel per iteration suffices:
+//
+// Edge form.  Per face slot keep zeta = lambda + mu w (of the current
+// iteration); then x_e = (sum_h h_e + sum_slots zeta) / (|H_e| (1 + mu))
+// (Eq. 21), lambda = zeta - mu x, and the next W-update projects
+// x - lambda/mu = 2x - zeta/mu.  One iteration per face f and slot k:
+//     x_k   = (S_e + zeta_e0 + zeta_e1) / (|H_e| (1 + mu))
+//     w_f   = (I - q q^T/3)(2 x_f - zeta_f / mu)
+//     zeta' = zeta_f - mu x_f + mu w_f
+// Starting from zeta = mu * (mean target) reproduces the paper's
+// initialisation (lambda = 0, x = mean of targets).
+//
+// Face form.  Per auxiliary copy k of face i keep z = y + lambda/(mu alpha_i);
+// then q_k = g_i - lambda_k/(mu alpha_i) = 2 g_i - z_k, the Y-update gives
+// y_k, the new z_k = y_k + z_k - g_i, and the G-update is
+// g_i = (2 h_i + mu sum_k z_k) / (2 + mu |Y(i)|).  Each face computes its own
+// copies' Y-update (it reads the neighbour's g and z across the edge), so
+// one kernel per face performs Y, G and lambda updates.  z = h initially.
+//
+// g, z and zeta are double-buffered (Jacobi semantics, deterministic).
+// Residuals are those of the paper, recovered exactly from two consecutive
+// states (see k_resid_edge / k_resid_face).
+#include <cmath>
+
+#include "hgeo_internal.h"
+
+namespace hg {
+
+constexpr int kBlockA = 256;
+
+__device__ inline double block_sum2(double v) {
+    __shared__ double sh[kBlockA / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sh[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+        v = r;
+    }
+    __syncthreads();
+    return v;
+}
+
+// ------------------------------------------------------------ normalisation
+// h_f = -grad u / |grad u| from u = v 2^e; the three values are first scaled
+// by 2^-max(e) (the direction does not depend on the scale).  grad u is
+// proportional to sum_i u_i (n x e_i), n = (p1-p0)x(p2-p0), e_i the CCW edge
+// opposite corner i.
+__global__ void k_normalize(int nf, const int32_t* tri, const double* px, const double* py, const double* pz,
+                            const double* v, const int32_t* e, float* h) {
+    int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int id[3] = {tri[3 * f], tri[3 * f + 1], tri[3 * f + 2]};
+    double vv[3];
+    int ee[3];
+    int m = -0x7fffffff;
+    for (int k = 0; k < 3; ++k) {
+        vv[k] = v[id[k]];
+        ee[k] = e[id[k]];
+        if (vv[k] != 0.0) m = max(m, ee[k]);
+    }
+    double p[3][3];
+    for (int k = 0; k < 3; ++k) {
+        p[k][0] = px[id[k]];
+        p[k][1] = py[id[k]];
+        p[k][2] = pz[id[k]];
+    }
+    double a[3], b[3], n[3];
+    for (int c = 0; c < 3; ++c) {
+        a[c] = p[1][c] - p[0][c];
+        b[c] = p[2][c] - p[0][c];
+    }
+    n[0] = a[1] * b[2] - a[2] * b[1];
+    n[1] = a[2] * b[0] - a[0] * b[2];
+    n[2] = a[0] * b[1] - a[1] * b[0];
+    double g[3] = {0.0, 0.0, 0.0};
+    if (m != -0x7fffffff) {
+        for (int k = 0; k < 3; ++k) {
+            if (vv[k] == 0.0) continue;
+            double wk = ldexp(vv[k], ee[k] - m);
+            const double* pa = p[(k + 1) % 3];
+            const double* pb = p[(k + 2) % 3];
+            double ed[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
+            g[0] += wk * (n[1] * ed[2] - n[2] * ed[1]);
+            g[1] += wk * (n[2] * ed[0] - n[0] * ed[2]);
+            g[2] += wk * (n[0] * ed[1] - n[1] * ed[0]);
+        }
+    }
+    double nrm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    float hx = 0.f, hy = 0.f, hz = 0.f;
+    if (nrm > 0.0) {
+        hx = (float)(-g[0] / nrm);
+        hy = (float)(-g[1] / nrm);
+        hz = (float)(-g[2] / nrm);
+    }
+    h[3 * f] = hx;
+    h[3 * f + 1] = hy;
+    h[3 * f + 2] = hz;
+}
+
+// sum over the incident faces of h_f . (p_head - p_tail) (Eq. 18), per edge.
+__global__ void k_edge_targets(int ne, const int32_t* ev, const int32_t* ef, const double* px, const double* py,
+                               const double* pz, const float* h, float* sumz) {
+    int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    int a = ev[2 * e], b = ev[2 * e + 1];
+    double d[3] = {px[b] - px[a], py[b] - py[a], pz[b] - pz[a]};
+    double s = 0.0;
+    for (int q = 0; q < 2; ++q) {
+        int f = ef[2 * e + q];
+        if (f < 0) continue;
+        s += (double)h[3 * f] * d[0] + (double)h[3 * f + 1] * d[1] + (double)h[3 * f + 2] * d[2];
+    }
+    sumz[e] = (float)s;
+}
+
+void run_normalize(Mesh& m, hipStream_t s) {
+    m.w.h.alloc((size_t)3 * m.nf);
+    hipLaunchKernelGGL(k_normalize, dim3(grid_for(m.nf, kBlockA)), dim3(kBlockA), 0, s, (int)m.nf, m.tri.p, m.px.p,
+                       m.py.p, m.pz.p, m.w.v0.p, m.w.e0.p, m.w.h.p);
+    HG_CHECK_HIP(hipGetLastError());
+}
+
+// (v, e) from a caller log u, then normalise (stage entry point).
+__global__ void k_logu_to_ve(int nv, const int32_t* perm_v, const double* logu_user, double* v, int32_t* e) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    double l = logu_user[perm_v[j]];
+    if (!(l > -INFINITY)) {
+        v[j] = 0.0;
+        e[j] = 0;
+        return;
+    }
+    double ex = floor(l / 0.69314718055994530942);
+    e[j] = (int)ex;
+    v[j] = exp(l - ex * 0.69314718055994530942);
+}
+
+void normalize_from_logu(Mesh& m, const double* logu_user, hipStream_t s) {
+    m.w.v0.alloc(m.nv);
+    m.w.e0.alloc(m.nv);
+    hipLaunchKernelGGL(k_logu_to_ve, dim3(grid_for(m.nv, kBlockA)), dim3(kBlockA), 0, s, (int)m.nv, m.perm_v.p,
+                       logu_user, m.w.v0.p, m.w.e0.p);
+    HG_CHECK_HIP(hipGetLastError());
+    run_normalize(m, s);
+}
+
+// ---------------------------------------------------------------- edge form
+__global__ void k_zeta_init(int ne, const int32_t* ef, const float* sumz, float mu, float* zeta) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    float nh = ef[2 * e + 1] >= 0 ? 2.f : 1.f;
+    float z = mu * (sumz[e] / nh);
+    zeta[2 * e] = z;
+    zeta[2 * e + 1] = ef[2 * e + 1] >= 0 ? z : 0.f;
+}
+
+__device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1mu) {
+    // x_e = (S + z0 + z1) / (|H_e| (1 + mu)); a boundary edge has z1 = 0
+    return bnd ? (S + z0) * inv1mu : 0.5f * (S + z0 + z1) * inv1mu;
+}
+
+__global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const uint32_t* __restrict__ fslot,
+                                                       const uint8_t* __restrict__ fsign,
+                                                       const float* __restrict__ sumz,
+                                                       const float* __restrict__ zin, float* __restrict__ zout,
+                                                       float mu, float inv1mu) {
+    int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    uint32_t sl[3];
+    float x[3], zo[3];
+    for (int k = 0; k < 3; ++k) {
+        sl[k] = fslot[3 * f + k];
+        int e = slot_edge(sl[k]);
+        float2 zz = *reinterpret_cast<const float2*>(zin + 2 * e);
+        x[k] = edge_x(sumz[e], zz.x, zz.y, slot_bnd(sl[k]), inv1mu);
+        zo[k] = slot_side(sl[k]) ? zz.y : zz.x;
+    }
+    uint8_t sg = fsign[f];
+    float q[3], v[3];
+    float qv = 0.f;
+    for (int k = 0; k < 3; ++k) {
+        q[k] = (sg >> k) & 1 ? 1.f : -1.f;
+        v[k] = 2.f * x[k] - zo[k] / mu;
+        qv += q[k] * v[k];
+    }
+    qv *= (1.f / 3.f);
+    for (int k = 0; k < 3; ++k) {
+        float w = v[k] - qv * q[k];
+        zout[2 * slot_edge(sl[k]) + slot_side(sl[k])] = zo[k] + mu * (w - x[k]);
+    }
+}
+
+// r_p = w' - x' = (lambda' - lambda)/mu with lambda = zeta - mu x;
+// r_d = mu (x' - x).  partial = (sum r_p^2, sum r_d^2) per block.
+__global__ void k_resid_edge(int nf, const uint32_t* fslot, const float* sumz, const float* za, const float* zb,
+                             float mu, float inv1mu, double* partial) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    double rp = 0.0, rd = 0.0;
+    if (f < nf) {
+        for (int k = 0; k < 3; ++k) {
+            uint32_t sl = fslot[3 * f + k];
+            int e = slot_edge(sl), side = slot_side(sl), bnd = slot_bnd(sl);
+            float S = sumz[e];
+            float xa = edge_x(S, za[2 * e], za[2 * e + 1], bnd, inv1mu);
+            float xb = edge_x(S, zb[2 * e], zb[2 * e + 1], bnd, inv1mu);
+            double la = (double)za[2 * e + side] - (double)mu * xa;
+            double lb = (double)zb[2 * e + side] - (double)mu * xb;
+            double p = (lb - la) / mu;
+            double d = (double)mu * ((double)xb - (double)xa);
+            rp += p * p;
+            rd += d * d;
+        }
+    }
+    rp = block_sum2(rp);
+    rd = block_sum2(rd);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = rp;
+        partial[2 * blockIdx.x + 1] = rd;
+    }
+}
+
+__global__ void k_reduce_pairs(double* partial, int n) {
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    a = block_sum2(a);
+    b = block_sum2(b);
+    if (threadIdx.x == 0) {
+        partial[2 * n] = a;
+        partial[2 * n + 1] = b;
+    }
+}
+
+__global__ void k_edge_x(int ne, const uint32_t* dummy, const int32_t* ef, const float* sumz, const float* z,
+                         float inv1mu, float* x) {
+    (void)dummy;
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    int bnd = ef[2 * e + 1] < 0;
+    x[e] = edge_x(sumz[e], z[2 * e], z[2 * e + 1], bnd, inv1mu);
+}
+
+static void reduce_pair(Mesh& m, int nblocks, hipStream_t s, double& a, double& b) {
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlockA), 0, s, m.w.partial.p, nblocks);
+    HG_CHECK_HIP(hipGetLastError());
+    HG_CHECK_HIP(
+        hipMemcpyAsync(m.w.pinned, m.w.partial.p + 2 * nblocks, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HG_CHECK_HIP(hipStreamSynchronize(s));
+    a = m.w.pinned[0];
+    b = m.w.pinned[1];
+}
+
+AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s) {
+    const int nf = (int)m.nf, ne = (int)m.ne;
+    auto& w = m.w;
+    w.sumz.alloc(ne);
+    w.z0.alloc((size_t)2 * ne);
+    w.z1.alloc((size_t)2 * ne);
+    w.xe.alloc(ne);
+    const float mu = (float)o.mu, inv1mu = 1.0f / (1.0f + mu);
+    const int gf = grid_for(nf, kBlockA), ge = grid_for(ne, kBlockA);
+    if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
+    hipLaunchKernelGGL(k_edge_targets, dim3(ge), dim3(kBlockA), 0, s, ne, m.ev.p, m.ef.p, m.px.p, m.py.p, m.pz.p,
+                       w.h.p, w.sumz.p);
+    hipLaunchKernelGGL(k_zeta_init, dim3(ge), dim3(kBlockA), 0, s, ne, m.ef.p, w.sumz.p, mu, w.z0.p);
+    HG_CHECK_HIP(hipGetLastError());
+    AdmmResult r;
+    const bool fixed = iters > 0;
+    const int cap = fixed ? iters : o.max_admm;
+    const int check = std::max(1, o.check_every);
+    const double scale = sqrt(3.0 * (double)nf) * m.hbar * o.tol_admm;
+    float* za = w.z0.p;
+    float* zb = w.z1.p;
+    // algorithmic bytes of one iteration: fslot + sign per face, the zeta pair
+    // and target sum per edge read once, one zeta written per face slot
+    r.bytes_per_iter = (uint64_t)13 * nf + (uint64_t)12 * ne + (uint64_t)12 * nf;
+    RunTimer rt;
+    int run_len = 0;
+    for (int it = 1; it <= cap; ++it) {
+        if (!rt.open) {
+            rt.start(s);
+            run_len = 0;
+        }
+        hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.fsign.p, w.sumz.p, za, zb,
+                           mu, inv1mu);
+        HG_CHECK_HIP(hipGetLastError());
+        ++run_len;
+        r.iters = it;
+        const bool want = !fixed ? ((it % check) == 0 || it == cap) : (it == cap);
+        if (want) {
+            r.kernel_ms += rt.stop(s);
+            r.timed_launches += run_len;
+            hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, w.sumz.p, za, zb, mu,
+                               inv1mu, w.partial.p);
+            double a, b;
+            reduce_pair(m, gf, s, a, b);
+            r.rp = sqrt(a);
+            r.rd = sqrt(b);
+            if (!fixed && r.rp <= scale && r.rd <= scale * o.mu) {
+                r.converged = true;
+                std::swap(za, zb);
+                break;
+            }
+        }
+        std::swap(za, zb);
+    }
+    // normalise the reported residuals to the stopping scale: rms / hbar
+    r.rp = r.rp / (sqrt(3.0 * (double)nf) * m.hbar);
+    r.rd = r.rd / (sqrt(3.0 * (double)nf) * m.hbar * o.mu);
+    if (fixed) r.converged = true;
+    hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, w.sumz.p, za, inv1mu, w.xe.p);
+    HG_CHECK_HIP(hipGetLastError());
+    if (za != w.z0.p)
+        HG_CHECK_HIP(hipMemcpyAsync(w.z0.p, za, (size_t)2 * ne * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return r;
+}
+
+// ---------------------------------------------------------------- face form
+// z buffer layout: [2*ne][3], copy (e, side).
+__global__ void k_face_init(int nf, int ne, const int32_t* ef, const float* h, float* g, float* z) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nf) {
+        g[3 * i] = h[3 * i];
+        g[3 * i + 1] = h[3 * i + 1];
+        g[3 * i + 2] = h[3 * i + 2];
+    }
+    if (i < ne) {
+        for (int s = 0; s < 2; ++s) {
+            int f = ef[2 * i + s];
+            float* zz = z + 3 * (2 * i + s);
+            if (f >= 0) {
+                zz[0] = h[3 * f];
+                zz[1] = h[3 * f + 1];
+                zz[2] = h[3 * f + 2];
+            } else {
+                zz[0] = zz[1] = zz[2] = 0.f;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* __restrict__ fslot,
+                                                       const int32_t* __restrict__ ef,
+                                                       const float* __restrict__ ebar,
+                                                       const double* __restrict__ farea,
+                                                       const float* __restrict__ h, const float* __restrict__ gin,
+                                                       const float* __restrict__ zin, float* __restrict__ gout,
+                                                       float* __restrict__ zout, float mu) {
+    int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const float g0 = gin[3 * f], g1 = gin[3 * f + 1], g2 = gin[3 * f + 2];
+    const float Af = (float)farea[f];
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+    int cnt = 0;
+    for (int k = 0; k < 3; ++k) {
+        uint32_t sl = fslot[3 * f + k];
+        if (slot_bnd(sl)) continue;
+        int e = slot_edge(sl), side = slot_side(sl);
+        int nb = ef[2 * e + (side ^ 1)];
+        const float* zo = zin + 3 * (2 * e + side);
+        const float* zn = zin + 3 * (2 * e + (side ^ 1));
+        float qo0 = 2.f * g0 - zo[0], qo1 = 2.f * g1 - zo[1], qo2 = 2.f * g2 - zo[2];
+        float qn0 = 2.f * gin[3 * nb] - zn[0];
+        float qn1 = 2.f * gin[3 * nb + 1] - zn[1];
+        float qn2 = 2.f * gin[3 * nb + 2] - zn[2];
+        float e0 = ebar[3 * e], e1 = ebar[3 * e + 1], e2 = ebar[3 * e + 2];
+        float An = (float)farea[nb];
+        float sdot = e0 * (qn0 - qo0) + e1 * (qn1 - qo1) + e2 * (qn2 - qo2);
+        float c = An / (Af + An) * sdot;
+        // y_own = q_own + A_nb/(A_own + A_nb) e (e.(q_nb - q_own)); z' = y + z - g
+        float z0n = qo0 + c * e0 + zo[0] - g0;
+        float z1n = qo1 + c * e1 + zo[1] - g1;
+        float z2n = qo2 + c * e2 + zo[2] - g2;
+        float* zw = zout + 3 * (2 * e + side);
+        zw[0] = z0n;
+        zw[1] = z1n;
+        zw[2] = z2n;
+        acc0 += z0n;
+        acc1 += z1n;
+        acc2 += z2n;
+        ++cnt;
+    }
+    const float den = 1.f / (2.f + mu * (float)cnt);
+    gout[3 * f] = (2.f * h[3 * f] + mu * acc0) * den;
+    gout[3 * f + 1] = (2.f * h[3 * f + 1] + mu * acc1) * den;
+    gout[3 * f + 2] = (2.f * h[3 * f + 2] + mu * acc2) * den;
+}
+
+// Per copy k of face i: r_p = alpha (y' - g') = alpha ((z' - g') - (z - g)),
+// r_d = mu A_i (g' - g).  partial = (sum |r_p|^2, sum |r_d|^2).
+__global__ void k_resid_face(int nf, const uint32_t* fslot, const double* farea, const float* ga, const float* gb,
+                             const float* za, const float* zb, float mu, double* partial) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    double rp = 0.0, rd = 0.0;
+    if (f < nf) {
+        double A = farea[f];
+        double al = sqrt(A);
+        for (int k = 0; k < 3; ++k) {
+            uint32_t sl = fslot[3 * f + k];
+            if (slot_bnd(sl)) continue;
+            int c = 2 * slot_edge(sl) + slot_side(sl);
+            for (int d = 0; d < 3; ++d) {
+                double p = al * (((double)zb[3 * c + d] - gb[3 * f + d]) - ((double)za[3 * c + d] - ga[3 * f + d]));
+                double q = (double)mu * A * ((double)gb[3 * f + d] - ga[3 * f + d]);
+                rp += p * p;
+                rd += q * q;
+            }
+        }
+    }
+    rp = block_sum2(rp);
+    rd = block_sum2(rd);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = rp;
+        partial[2 * blockIdx.x + 1] = rd;
+    }
+}
+
+// |M|_F^2 = sum over copies of the face area
+__global__ void k_normM(int nf, const uint32_t* fslot, const double* farea, double* partial) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0;
+    if (f < nf)
+        for (int k = 0; k < 3; ++k)
+            if (!slot_bnd(fslot[3 * f + k])) a += farea[f];
+    a = block_sum2(a);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = a;
+        partial[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s) {
+    const int nf = (int)m.nf, ne = (int)m.ne;
+    auto& w = m.w;
+    w.g0.alloc((size_t)3 * nf);
+    w.g1.alloc((size_t)3 * nf);
+    w.z0.alloc((size_t)6 * ne);
+    w.z1.alloc((size_t)6 * ne);
+    w.gf.alloc((size_t)3 * nf);
+    const float mu = (float)o.mu;
+    const int gf = grid_for(nf, kBlockA);
+    const int gi = grid_for(std::max(nf, ne), kBlockA);
+    if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
+    hipLaunchKernelGGL(k_face_init, dim3(gi), dim3(kBlockA), 0, s, nf, ne, m.ef.p, w.h.p, w.g0.p, w.z0.p);
+    hipLaunchKernelGGL(k_normM, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.farea.p, w.partial.p);
+    HG_CHECK_HIP(hipGetLastError());
+    double nm2, dummy;
+    reduce_pair(m, gf, s, nm2, dummy);
+    const double normM = sqrt(nm2);
+    AdmmResult r;
+    const bool fixed = iters > 0;
+    const int cap = fixed ? iters : o.max_admm;
+    const int check = std::max(1, o.check_every);
+    float *ga = w.g0.p, *gb = w.g1.p, *za = w.z0.p, *zb = w.z1.p;
+    // algorithmic bytes of one iteration: per face g, h, fslot, area read and
+    // g written; per edge ef, unit vector and both z copies read, z written
+    r.bytes_per_iter = (uint64_t)56 * nf + (uint64_t)68 * ne;
+    RunTimer rt;
+    int run_len = 0;
+    for (int it = 1; it <= cap; ++it) {
+        if (!rt.open) {
+            rt.start(s);
+            run_len = 0;
+        }
+        hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.ef.p, m.ebar.p, m.farea.p,
+                           w.h.p, ga, za, gb, zb, mu);
+        HG_CHECK_HIP(hipGetLastError());
+        ++run_len;
+        r.iters = it;
+        const bool want = !fixed ? ((it % check) == 0 || it == cap) : (it == cap);
+        if (want) {
+            r.kernel_ms += rt.stop(s);
+            r.timed_launches += run_len;
+            hipLaunchKernelGGL(k_resid_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.farea.p, ga, gb, za, zb,
+                               mu, w.partial.p);
+            double a, b;
+            reduce_pair(m, gf, s, a, b);
+            r.rp = sqrt(a) / normM;
+            r.rd = sqrt(b) / normM;
+            if (!fixed && r.rp <= o.tol_admm && r.rd <= o.tol_admm) {
+                r.converged = true;
+                std::swap(ga, gb);
+                std::swap(za, zb);
+                break;
+            }
+        }
+        std::swap(ga, gb);
+        std::swap(za, zb);
+    }
+    if (fixed) r.converged = true;
+    HG_CHECK_HIP(hipMemcpyAsync(w.gf.p, ga, (size_t)3 * nf * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return r;
+}
+
+}  // namespace hg

@@ -1,0 +1,145 @@
+// Breadth-first vertex sets D_i (Eq. 6) and the pairing of every vertex with
+// a neighbour one set closer to the sources (Sec. 3.3; Sec. 5.2 puts all
+// sources in D_0).  Level-synchronous frontier expansion: one launch per
+// level, frontier membership claimed with atomicCAS on the level array (the
+// levels are unique, so the result does not depend on timing); the pairing
+// is then chosen per vertex as the neighbour of level - 1 with the smallest
+// caller vertex id, which is deterministic.
+#include "hgeo_internal.h"
+
+namespace hg {
+
+constexpr int kBlockB = 256;
+
+__global__ void k_fill_i32(int n, int32_t* a, int32_t val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = val;
+}
+
+// counters[0..2]: frontier sizes (ring of three), counters[3]: depth
+__global__ void k_bfs_sources(int nsrc, const int32_t* src, int32_t* level, int32_t* frontier, int32_t* counters) {
+    if (blockIdx.x != 0) return;
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int i = 0; i < nsrc; ++i) {
+            int s = src[i];
+            if (level[s] < 0) {
+                level[s] = 0;
+                frontier[n++] = s;
+            }
+        }
+        counters[0] = n;
+        counters[1] = 0;
+        counters[2] = 0;
+        counters[3] = 0;
+    }
+}
+
+__global__ void k_bfs_expand(int L, const int32_t* row_ptr, const int32_t* col, int32_t* level,
+                             const int32_t* fin, int32_t* fout, int32_t* counters) {
+    const int cin = L % 3, cout = (L + 1) % 3, czero = (L + 2) % 3;
+    const int n = counters[cin];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counters[czero] = 0;
+        if (n > 0) counters[3] = L;   // deepest non-empty level so far
+    }
+    const int lane = threadIdx.x & 63;
+    const int stride = gridDim.x * blockDim.x;
+    constexpr int kCap = 16;
+    // the loop bound is uniform across a wavefront, so every lane reaches
+    // the shuffles below
+    for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        int i = base + lane;
+        int claimed[kCap];
+        int c = 0;
+        if (i < n) {
+            int v = fin[i];
+            for (int k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+                int u = col[k];
+                if (level[u] < 0 && atomicCAS(&level[u], -1, L + 1) == -1) {
+                    if (c < kCap) {
+                        claimed[c++] = u;
+                    } else {
+                        int pos = atomicAdd(&counters[cout], 1);
+                        fout[pos] = u;
+                    }
+                }
+            }
+        }
+        // wavefront prefix sum of the claim counts, one atomic per wavefront
+        int incl = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        int total = __shfl(incl, 63, 64);
+        int wbase = 0;
+        if (lane == 63 && total > 0) wbase = atomicAdd(&counters[cout], total);
+        wbase = __shfl(wbase, 63, 64);
+        int off = wbase + incl - c;
+        for (int q = 0; q < c; ++q) fout[off + q] = claimed[q];
+    }
+}
+
+__global__ void k_bfs_parent(int nv, const int32_t* row_ptr, const int32_t* col, const int32_t* level,
+                             const int32_t* perm_v, int32_t* parent, int32_t* pslot) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    int lj = level[j];
+    int best = -1, bslot = -1, bid = 0x7fffffff;
+    if (lj > 0) {
+        for (int k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
+            int u = col[k];
+            if (level[u] == lj - 1) {
+                int id = perm_v[u];
+                if (id < bid) {
+                    bid = id;
+                    best = u;
+                    bslot = k;
+                }
+            }
+        }
+    }
+    parent[j] = best;
+    pslot[j] = bslot;
+}
+
+int run_bfs(Mesh& m, const std::vector<int32_t>& src, hipStream_t s) {
+    const int nv = (int)m.nv;
+    auto& w = m.w;
+    w.level.alloc(nv);
+    w.parent.alloc(nv);
+    w.pslot.alloc(nv);
+    w.frontier_a.alloc(nv);
+    w.frontier_b.alloc(nv);
+    w.counters.alloc(8);
+    w.src.alloc(src.size());
+    HG_CHECK_HIP(hipMemcpyAsync(w.src.p, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, w.level.p, -1);
+    hipLaunchKernelGGL(k_bfs_sources, dim3(1), dim3(64), 0, s, (int)src.size(), w.src.p, w.level.p, w.frontier_a.p,
+                       w.counters.p);
+    HG_CHECK_HIP(hipGetLastError());
+    const int grid = std::max(1, std::min(grid_for(nv, kBlockB), 2048));
+    int32_t hc[4];
+    for (int L = 0;; ++L) {
+        int32_t* fin = (L % 2 == 0) ? w.frontier_a.p : w.frontier_b.p;
+        int32_t* fout = (L % 2 == 0) ? w.frontier_b.p : w.frontier_a.p;
+        hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(kBlockB), 0, s, L, m.row_ptr.p, m.col.p, w.level.p, fin,
+                           fout, w.counters.p);
+        HG_CHECK_HIP(hipGetLastError());
+        if ((L & 31) == 31) {
+            HG_CHECK_HIP(hipMemcpyAsync(hc, w.counters.p, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HG_CHECK_HIP(hipStreamSynchronize(s));
+            if (hc[(L + 1) % 3] == 0) break;
+        }
+        if (L > nv + 1) break;
+    }
+    hipLaunchKernelGGL(k_bfs_parent, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, m.row_ptr.p, m.col.p,
+                       w.level.p, m.perm_v.p, w.parent.p, w.pslot.p);
+    HG_CHECK_HIP(hipGetLastError());
+    HG_CHECK_HIP(hipMemcpyAsync(hc, w.counters.p, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HG_CHECK_HIP(hipStreamSynchronize(s));
+    return hc[3];   // deepest level whose frontier was non-empty
+}
+
+}  // namespace hg

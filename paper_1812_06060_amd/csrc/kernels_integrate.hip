@@ -1,0 +1,145 @@
+// Integration of the optimised gradients into distances (Sec. 3.3, Sec. 4).
+//
+// The paper fixes d = 0 at the sources and walks the breadth-first sets
+// D_1, D_2, ... in order: a vertex v_j takes the value of its partner v_k in
+// D_{i-1} plus the change along the edge (j, k) -- Eq. 17 for face gradients
+// (the mean of g_l . (p_j - p_k) over the faces containing the edge), or the
+// edge difference +-x_e for the edge form.  So d(v_j) is the sum of the
+// changes along the partner chain from v_j to its source.
+//
+// Here that sum is formed by pointer jumping: every vertex holds (s, p) =
+// (sum of changes to p, p), and one round replaces (s, p) by
+// (s + s[p], p[p]); after ceil(log2(depth)) rounds p is the source and s the
+// whole sum.  That needs ~log2(depth) launches instead of depth dependent
+// steps.  Sums are carried as FP32 double-float pairs (hi, lo) with
+// error-free two-sum, i.e. compensated summation; each edge change is formed
+// in FP64 from FP32 gradients and FP64 positions and split into (hi, lo).
+#include <cmath>
+
+#include "hgeo_internal.h"
+
+namespace hg {
+
+constexpr int kBlockI = 256;
+
+#pragma clang fp contract(off)
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+// (ah, al) + (bh, bl) in double-float arithmetic
+__device__ inline void df_add(float ah, float al, float bh, float bl, float& rh, float& rl) {
+    float s, e;
+    two_sum(ah, bh, s, e);
+    e += al + bl;
+    float h = s + e;
+    rl = e - (h - s);
+    rh = h;
+}
+
+// Per vertex: the change along the edge to its partner, and the jump state.
+__global__ void k_int_step(int nv, int form, const int32_t* level, const int32_t* parent, const int32_t* pslot,
+                           const int32_t* csr_edge, const int32_t* ev, const int32_t* ef, const float* xe,
+                           const float* g, const double* px, const double* py, const double* pz, float* shi,
+                           float* slo, int32_t* jp) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    int lj = level[j];
+    if (lj <= 0) {
+        shi[j] = lj == 0 ? 0.f : INFINITY;
+        slo[j] = 0.f;
+        jp[j] = lj == 0 ? j : -1;
+        return;
+    }
+    int k = parent[j];
+    int e = csr_edge[pslot[j]];
+    double step;
+    if (form == HG_FORM_EDGE) {
+        double x = (double)xe[e];
+        step = (ev[2 * e + 1] == j) ? x : -x;
+    } else {
+        double d0 = px[j] - px[k], d1 = py[j] - py[k], d2 = pz[j] - pz[k];
+        double acc = 0.0;
+        int n = 0;
+        for (int s = 0; s < 2; ++s) {
+            int f = ef[2 * e + s];
+            if (f < 0) continue;
+            acc += (double)g[3 * f] * d0 + (double)g[3 * f + 1] * d1 + (double)g[3 * f + 2] * d2;
+            ++n;
+        }
+        step = acc / (double)n;
+    }
+    float hi = (float)step;
+    shi[j] = hi;
+    slo[j] = (float)(step - (double)hi);
+    jp[j] = k;
+}
+
+__global__ void k_int_jump(int nv, const float* shi, const float* slo, const int32_t* jp, float* shi2, float* slo2,
+                           int32_t* jp2) {
+    int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    int p = jp[j];
+    if (p < 0 || jp[p] == p) {
+        // unreachable, a source, or already pointing at a source
+        shi2[j] = shi[j];
+        slo2[j] = slo[j];
+        jp2[j] = p;
+        return;
+    }
+    float h, l;
+    df_add(shi[j], slo[j], shi[p], slo[p], h, l);
+    shi2[j] = h;
+    slo2[j] = l;
+    jp2[j] = jp[p];
+}
+
+__global__ void k_int_out(int nv, const int32_t* perm_v, const int32_t* jp, const float* shi, const float* slo,
+                          float* d_user) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    float d;
+    if (jp[j] < 0) {
+        d = INFINITY;
+    } else {
+        int p = jp[j];
+        // s[j] holds the sum up to p (a source, d = 0); add p's own (zero) term
+        float h, l;
+        df_add(shi[j], slo[j], p == j ? 0.f : shi[p], p == j ? 0.f : slo[p], h, l);
+        d = h + l;
+    }
+    d_user[perm_v[j]] = d;
+}
+
+void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s) {
+    const int nv = (int)m.nv;
+    auto& w = m.w;
+    w.shi0.alloc(nv);
+    w.slo0.alloc(nv);
+    w.shi1.alloc(nv);
+    w.slo1.alloc(nv);
+    w.jp0.alloc(nv);
+    w.jp1.alloc(nv);
+    const int grid = grid_for(nv, kBlockI);
+    hipLaunchKernelGGL(k_int_step, dim3(grid), dim3(kBlockI), 0, s, nv, form, w.level.p, w.parent.p, w.pslot.p,
+                       m.csr_edge.p, m.ev.p, m.ef.p, w.xe.p, w.gf.p, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p,
+                       w.jp0.p);
+    HG_CHECK_HIP(hipGetLastError());
+    // after r rounds every vertex sums 2^r chain edges; sources stop the walk
+    int rounds = 0;
+    while ((1ll << rounds) < (long long)depth) ++rounds;
+    float *ha = w.shi0.p, *la = w.slo0.p, *hb = w.shi1.p, *lb = w.slo1.p;
+    int32_t *pa = w.jp0.p, *pb = w.jp1.p;
+    for (int r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(k_int_jump, dim3(grid), dim3(kBlockI), 0, s, nv, ha, la, pa, hb, lb, pb);
+        HG_CHECK_HIP(hipGetLastError());
+        std::swap(ha, hb);
+        std::swap(la, lb);
+        std::swap(pa, pb);
+    }
+    hipLaunchKernelGGL(k_int_out, dim3(grid), dim3(kBlockI), 0, s, nv, m.perm_v.p, pa, ha, la, d_user);
+    HG_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace hg

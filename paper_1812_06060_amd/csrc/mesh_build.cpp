@@ -1,0 +1,292 @@
+// Host-side connectivity of a triangle mesh for the hgeo library.
+//
+// Builds, in linear time (bucket sorts keyed by vertex id):
+//   * the internal vertex order (3D Morton order of the positions);
+//   * faces sorted by their smallest internal vertex;
+//   * unique edges, the orientation halfedge of each (from the smaller to the
+//     larger caller vertex id, Sec. 4.1), the incident faces, and per face
+//     slot the edge, the side and the integrability sign of Eq. 20;
+//   * the canonical (caller-facing) edge numbering;
+//   * the CSR one-ring adjacency used by the breadth-first sets (Eq. 6) and
+//     the diffusion sweeps (Eq. 7);
+//   * LDS tiles: contiguous internal vertex ranges with their halos and the
+//     tile-local neighbour slots of every vertex (ELL layout).
+// Geometry (areas, cotangent weights) is computed later on the GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "hgeo_internal.h"
+
+namespace hg {
+
+static inline uint64_t spread3(uint64_t x) {
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+static void bad(const std::string& msg) { throw Error{HG_E_BAD_MESH, msg}; }
+
+void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_t nf,
+                    int patch_size, HostTopo& T) {
+    if (nv <= 0 || nf <= 0) throw Error{HG_E_INVALID_ARG, "empty mesh"};
+    if (nv >= (1ll << 31) || 3 * nf >= (1ll << 31))
+        throw Error{HG_E_INVALID_ARG, "mesh too large for 32-bit element indices"};
+    T.nv = nv;
+    T.nf = nf;
+    // ---- validation of indices and degenerate faces
+    for (int64_t f = 0; f < nf; ++f) {
+        int32_t a = tri_in[3 * f], b = tri_in[3 * f + 1], c = tri_in[3 * f + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
+            bad("triangle " + std::to_string(f) + " has a vertex index out of range");
+        if (a == b || b == c || a == c) bad("triangle " + std::to_string(f) + " repeats a vertex");
+    }
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(xyz[i])) throw Error{HG_E_INVALID_ARG, "non-finite vertex position"};
+
+    // ---- Morton order of the vertices
+    double lo[3] = {xyz[0], xyz[1], xyz[2]}, hi[3] = {xyz[0], xyz[1], xyz[2]};
+    for (int64_t i = 0; i < nv; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], xyz[3 * i + c]);
+            hi[c] = std::max(hi[c], xyz[3 * i + c]);
+        }
+    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    std::vector<std::pair<uint64_t, int32_t>> mk(nv);
+    for (int64_t i = 0; i < nv; ++i) {
+        uint64_t q[3];
+        for (int c = 0; c < 3; ++c) {
+            double r = (xyz[3 * i + c] - lo[c]) / ext;
+            q[c] = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(r * 2097151.0)));
+        }
+        mk[i] = {spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2), (int32_t)i};
+    }
+    std::sort(mk.begin(), mk.end());
+    T.perm_v.resize(nv);
+    T.iperm_v.resize(nv);
+    T.px.resize(nv);
+    T.py.resize(nv);
+    T.pz.resize(nv);
+    for (int64_t i = 0; i < nv; ++i) {
+        int32_t u = mk[i].second;
+        T.perm_v[i] = u;
+        T.iperm_v[u] = (int32_t)i;
+        T.px[i] = xyz[3 * u];
+        T.py[i] = xyz[3 * u + 1];
+        T.pz[i] = xyz[3 * u + 2];
+    }
+    mk.clear();
+    mk.shrink_to_fit();
+
+    // ---- faces sorted (stably) by smallest internal vertex
+    std::vector<int32_t> cnt(nv + 1, 0);
+    auto fmin = [&](int64_t f) {
+        return std::min({T.iperm_v[tri_in[3 * f]], T.iperm_v[tri_in[3 * f + 1]], T.iperm_v[tri_in[3 * f + 2]]});
+    };
+    for (int64_t f = 0; f < nf; ++f) cnt[fmin(f) + 1]++;
+    for (int64_t i = 0; i < nv; ++i) cnt[i + 1] += cnt[i];
+    T.perm_f.assign(nf, 0);
+    for (int64_t f = 0; f < nf; ++f) T.perm_f[cnt[fmin(f)]++] = (int32_t)f;
+    T.tri.resize(3 * nf);
+    for (int64_t f = 0; f < nf; ++f) {
+        int32_t u = T.perm_f[f];
+        for (int k = 0; k < 3; ++k) T.tri[3 * f + k] = T.iperm_v[tri_in[3 * u + k]];
+    }
+
+    // ---- halfedges bucketed by smaller internal endpoint
+    const int64_t nh = 3 * nf;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t h = 0; h < nh; ++h) {
+        int32_t a = T.tri[h], b = T.tri[(h / 3) * 3 + (h % 3 + 1) % 3];
+        cnt[std::min(a, b) + 1]++;
+    }
+    for (int64_t i = 0; i < nv; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> hb(nh);
+    {
+        std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int64_t h = 0; h < nh; ++h) {
+            int32_t a = T.tri[h], b = T.tri[(h / 3) * 3 + (h % 3 + 1) % 3];
+            hb[pos[std::min(a, b)]++] = (int32_t)h;
+        }
+    }
+    auto hother = [&](int32_t h) {
+        int32_t a = T.tri[h], b = T.tri[(h / 3) * 3 + (h % 3 + 1) % 3];
+        return std::max(a, b);
+    };
+    // within a bucket: order by larger endpoint, then halfedge id
+    for (int64_t v = 0; v < nv; ++v) {
+        auto b0 = hb.begin() + cnt[v], b1 = hb.begin() + cnt[v + 1];
+        std::sort(b0, b1, [&](int32_t x, int32_t y) {
+            int32_t ox = hother(x), oy = hother(y);
+            return ox != oy ? ox < oy : x < y;
+        });
+    }
+    // unique edges
+    T.fslot.assign(nh, 0);
+    T.fsign.assign(nf, 0);
+    T.ev.clear();
+    T.ef.clear();
+    T.ev.reserve(nh);   // upper bound, trimmed below
+    T.ef.reserve(nh);
+    int64_t ne = 0, nbnd = 0;
+    for (int64_t i = 0; i < nh;) {
+        int32_t h0 = hb[i];
+        int32_t a0 = T.tri[h0], b0 = T.tri[(h0 / 3) * 3 + (h0 % 3 + 1) % 3];
+        int32_t lo_v = std::min(a0, b0), hi_v = std::max(a0, b0);
+        int64_t j = i + 1;
+        while (j < nh) {
+            int32_t h1 = hb[j];
+            int32_t a1 = T.tri[h1], b1 = T.tri[(h1 / 3) * 3 + (h1 % 3 + 1) % 3];
+            if (std::min(a1, b1) != lo_v || std::max(a1, b1) != hi_v) break;
+            ++j;
+        }
+        int64_t m = j - i;
+        if (m > 2) bad("non-manifold edge (more than two incident faces)");
+        // orientation halfedge: from the smaller to the larger caller id
+        int32_t tail = T.perm_v[lo_v] < T.perm_v[hi_v] ? lo_v : hi_v;
+        int32_t head = tail == lo_v ? hi_v : lo_v;
+        if (m == 2) {
+            int32_t h1 = hb[i + 1];
+            int32_t a1 = T.tri[h1];
+            if (a0 == a1) bad("inconsistently oriented faces share an edge");
+        } else {
+            ++nbnd;
+        }
+        T.ev.push_back(tail);
+        T.ev.push_back(head);
+        for (int64_t s = 0; s < 2; ++s) {
+            if (s < m) {
+                int32_t h = hb[i + s];
+                int32_t f = h / 3, k = h % 3;
+                T.ef.push_back(f);
+                T.fslot[h] = ((uint32_t)ne << 2) | ((m == 1 ? 1u : 0u) << 1) | (uint32_t)s;
+                if (T.tri[h] == tail) T.fsign[f] |= (uint8_t)(1u << k);
+            } else {
+                T.ef.push_back(-1);
+            }
+        }
+        ++ne;
+        i = j;
+    }
+    if (ne >= (1ll << 30)) throw Error{HG_E_INVALID_ARG, "too many edges"};
+    T.ne = ne;
+    T.nbnd = nbnd;
+    T.ev.shrink_to_fit();
+    T.ef.shrink_to_fit();
+    hb.clear();
+    hb.shrink_to_fit();
+
+    // ---- canonical edge numbering: sort by (min caller id, max caller id)
+    {
+        std::vector<int32_t> c2(nv + 1, 0);
+        auto umin = [&](int64_t e) { return std::min(T.perm_v[T.ev[2 * e]], T.perm_v[T.ev[2 * e + 1]]); };
+        auto umax = [&](int64_t e) { return std::max(T.perm_v[T.ev[2 * e]], T.perm_v[T.ev[2 * e + 1]]); };
+        for (int64_t e = 0; e < ne; ++e) c2[umin(e) + 1]++;
+        for (int64_t i = 0; i < nv; ++i) c2[i + 1] += c2[i];
+        std::vector<int32_t> order(ne);
+        std::vector<int32_t> pos(c2.begin(), c2.end() - 1);
+        for (int64_t e = 0; e < ne; ++e) order[pos[umin(e)]++] = (int32_t)e;
+        for (int64_t v = 0; v < nv; ++v)
+            std::sort(order.begin() + c2[v], order.begin() + c2[v + 1],
+                      [&](int32_t x, int32_t y) { return umax(x) < umax(y); });
+        T.perm_e.assign(ne, 0);
+        for (int64_t r = 0; r < ne; ++r) T.perm_e[order[r]] = (int32_t)r;
+    }
+
+    // ---- CSR adjacency in internal order, neighbours sorted by internal id
+    T.row_ptr.assign(nv + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+        T.row_ptr[T.ev[2 * e] + 1]++;
+        T.row_ptr[T.ev[2 * e + 1] + 1]++;
+    }
+    for (int64_t i = 0; i < nv; ++i) T.row_ptr[i + 1] += T.row_ptr[i];
+    T.col.assign(2 * ne, 0);
+    T.csr_edge.assign(2 * ne, 0);
+    {
+        std::vector<int32_t> pos(T.row_ptr.begin(), T.row_ptr.end() - 1);
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t a = T.ev[2 * e], b = T.ev[2 * e + 1];
+            T.col[pos[a]] = b;
+            T.csr_edge[pos[a]++] = (int32_t)e;
+            T.col[pos[b]] = a;
+            T.csr_edge[pos[b]++] = (int32_t)e;
+        }
+    }
+    int maxdeg = 0;
+    std::vector<std::pair<int32_t, int32_t>> tmp;
+    for (int64_t v = 0; v < nv; ++v) {
+        int32_t b = T.row_ptr[v], e = T.row_ptr[v + 1];
+        maxdeg = std::max(maxdeg, e - b);
+        tmp.clear();
+        for (int32_t k = b; k < e; ++k) tmp.push_back({T.col[k], T.csr_edge[k]});
+        std::sort(tmp.begin(), tmp.end());
+        for (int32_t k = b; k < e; ++k) {
+            T.col[k] = tmp[k - b].first;
+            T.csr_edge[k] = tmp[k - b].second;
+        }
+    }
+    T.max_valence = maxdeg;
+
+    // ---- LDS tiles: contiguous internal ranges, halos, ELL local slots
+    const int P = patch_size;
+    T.patch_size = P;
+    const int64_t np = (nv + P - 1) / P;
+    T.halo_ptr.assign(np + 1, 0);
+    T.halo_idx.clear();
+    T.ell_ptr.assign(np + 1, 0);
+    T.ell_width.assign(np, 0);
+    T.lnb.clear();
+    T.max_halo = 0;
+    T.max_ell_width = 0;
+    std::vector<int32_t> hmap;   // global -> halo slot for the current tile
+    std::vector<int32_t> halo;
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t v0 = p * P, v1 = std::min<int64_t>(nv, v0 + P);
+        halo.clear();
+        int width = 0;
+        for (int64_t v = v0; v < v1; ++v) {
+            width = std::max(width, T.row_ptr[v + 1] - T.row_ptr[v]);
+            for (int32_t k = T.row_ptr[v]; k < T.row_ptr[v + 1]; ++k) {
+                int32_t u = T.col[k];
+                if (u < v0 || u >= v1) halo.push_back(u);
+            }
+        }
+        std::sort(halo.begin(), halo.end());
+        halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+        if ((int64_t)P + (int64_t)halo.size() >= 65535)
+            throw Error{HG_E_BAD_MESH, "tile halo too large for 16-bit local slots"};
+        T.halo_idx.insert(T.halo_idx.end(), halo.begin(), halo.end());
+        T.halo_ptr[p + 1] = (int32_t)T.halo_idx.size();
+        T.max_halo = std::max<int>(T.max_halo, (int)halo.size());
+        T.ell_width[p] = (uint8_t)std::min(width, 255);
+        if (width > 255) throw Error{HG_E_BAD_MESH, "vertex valence above 255"};
+        T.max_ell_width = std::max(T.max_ell_width, width);
+        int64_t base = T.lnb.size();
+        T.ell_ptr[p] = (int32_t)base;
+        T.lnb.resize(base + (int64_t)width * P, (uint16_t)0xFFFF);
+        for (int64_t v = v0; v < v1; ++v) {
+            int i = (int)(v - v0);
+            int s = 0;
+            for (int32_t k = T.row_ptr[v]; k < T.row_ptr[v + 1]; ++k, ++s) {
+                int32_t u = T.col[k];
+                uint16_t l;
+                if (u >= v0 && u < v1) {
+                    l = (uint16_t)(u - v0);
+                } else {
+                    l = (uint16_t)(P + (std::lower_bound(halo.begin(), halo.end(), u) - halo.begin()));
+                }
+                T.lnb[base + (int64_t)s * P + i] = l;
+            }
+        }
+        if ((int64_t)T.lnb.size() >= (1ll << 31)) throw Error{HG_E_INVALID_ARG, "tile table too large"};
+    }
+    T.ell_ptr[np] = (int32_t)T.lnb.size();
+}
+
+}  // namespace hg

@@ -1,0 +1,140 @@
+"""Parity of the HIP path with the CPU oracle, stage by stage and end to end.
+
+Every GPU call goes through the C ABI (ctypes binding).  Tolerances:
+  * integers (BFS levels, pairing, edge list): bit-exact;
+  * log u (FP64 sweeps stopped at a relative change of 1e-12): 1e-8 absolute;
+  * h (FP32 output of FP64 arithmetic): 2e-6;
+  * ADMM after k iterations (FP32 vs FP64, same inputs): 2e-4 * hbar for edge
+    differences, 2e-4 for face gradients (unit scale);
+  * integration of given gradients (double-float sums): 1e-6 of the diameter;
+  * the whole solve: mean |d - d*| <= 1e-4 and max <= 1e-3 of the diameter
+    (the diameter read as max d*), d* the oracle's Poisson distance.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+from oracle import admm as oadmm
+from oracle import gradient as ograd
+from oracle import integrate as oint
+from oracle import metrics, pipeline
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def hg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_06060_amd as hg
+    hg.load_library()
+    return hg
+
+
+CASES = {
+    "grid64": lambda: meshgen.config_mesh("grid64"),
+    "bumpy4": lambda: meshgen.config_mesh("bumpy4"),
+    "sphere5": lambda: meshgen.config_mesh("sphere5"),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request, hg):
+    name = request.param
+    v, f, src = CASES[name]()
+    _say("mesh", name, "V", v.shape[0], "F", f.shape[0])
+    ref_face = pipeline.heat_method(v, f, src, form="face")
+    ref_edge = pipeline.heat_method(v, f, src, form="edge")
+    mesh = hg.Mesh(v, f)
+    yield name, v, f, src, mesh, ref_face, ref_edge
+    mesh.close()
+
+
+def test_mesh_stats_and_edges(case):
+    name, v, f, src, mesh, rf, re_ = case
+    _say(name, "edges")
+    assert mesh.nv == v.shape[0] and mesh.nf == f.shape[0] and mesh.ne == rf.topo.ne
+    assert abs(mesh.hbar - rf.hbar) <= 1e-14 * rf.hbar
+    e = mesh.edges().cpu().numpy()
+    assert np.array_equal(e, rf.topo.edges.astype(np.int32))
+
+
+def test_bfs_bit_exact(case):
+    name, v, f, src, mesh, rf, _ = case
+    _say(name, "bfs")
+    lev, par, depth = mesh.bfs(src)
+    assert np.array_equal(lev.cpu().numpy(), rf.level.astype(np.int32))
+    assert np.array_equal(par.cpu().numpy(), rf.parent.astype(np.int32))
+    assert depth == rf.level.max()
+
+
+def test_diffusion_logu(case, hg):
+    name, v, f, src, mesh, rf, _ = case
+    _say(name, "diffuse")
+    o = hg.default_opts(tol_u=1e-12)
+    logu, info = mesh.diffuse(src, 0.0, o)
+    assert info.converged_u and abs(info.t - rf.t) <= 1e-14 * rf.t
+    lu = logu.cpu().numpy()
+    assert np.abs(lu - rf.logu).max() < 1e-8
+
+
+def test_normalize(case):
+    name, v, f, src, mesh, rf, _ = case
+    _say(name, "normalize")
+    h = mesh.normalize(torch.from_numpy(rf.logu).cuda()).cpu().numpy()
+    assert np.abs(h - rf.h).max() < 2e-6
+
+
+@pytest.mark.parametrize("k", [1, 7, 40])
+def test_edge_admm_k_iterations(case, k):
+    name, v, f, src, mesh, rf, re_ = case
+    _say(name, "admm_edge", k)
+    h32 = re_.h.astype(np.float32)
+    x, info = mesh.admm_edge(torch.from_numpy(h32).cuda(), iters=k)
+    Z = ograd.edge_targets(v, re_.topo, h32.astype(np.float64))
+    ref = oadmm.EdgeADMM(re_.topo, Z).run(k)
+    assert info.admm_iters == k
+    assert np.abs(x.cpu().numpy() - ref.x).max() < 2e-4 * rf.hbar
+
+
+@pytest.mark.parametrize("k", [1, 7, 40])
+def test_face_admm_k_iterations(case, k):
+    name, v, f, src, mesh, rf, _ = case
+    _say(name, "admm_face", k)
+    h32 = rf.h.astype(np.float32)
+    g, info = mesh.admm_face(torch.from_numpy(h32).cuda(), iters=k)
+    ref = oadmm.FaceADMM(v, f, rf.topo, h32.astype(np.float64)).run(k)
+    assert np.abs(g.cpu().numpy() - ref.g).max() < 2e-4
+
+
+def test_integration(case):
+    name, v, f, src, mesh, rf, re_ = case
+    _say(name, "integrate")
+    diam = rf.d[np.isfinite(rf.d)].max()
+    # exact edge differences of the oracle distance, rounded to FP32
+    x = (re_.d[re_.topo.edges[:, 1]] - re_.d[re_.topo.edges[:, 0]]).astype(np.float32)
+    d = mesh.integrate_edge(src, torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = oint.integrate_edge(re_.topo, x.astype(np.float64), re_.level, re_.parent, src)
+    assert np.abs(d - ref).max() < 1e-6 * diam
+    g = ograd.face_gradients(v, f, rf.d).astype(np.float32)
+    d = mesh.integrate_face(src, torch.from_numpy(g).cuda()).cpu().numpy()
+    ref = oint.integrate_face(v, rf.topo, g.astype(np.float64), rf.level, rf.parent, src)
+    assert np.abs(d - ref).max() < 1e-6 * diam
+
+
+@pytest.mark.parametrize("form", ["edge", "face"])
+def test_solve_end_to_end(case, hg, form):
+    name, v, f, src, mesh, rf, re_ = case
+    _say(name, "solve", form)
+    ref = re_ if form == "edge" else rf
+    d, info = mesh.solve(src, 0.0, hg.default_opts(formulation=form))
+    mean, mx = metrics.parity(d.cpu().numpy(), ref.d)
+    _say(name, form, "sweeps", info.sweeps, "admm", info.admm_iters, "mean", mean, "max", mx)
+    assert info.converged_u and info.converged_admm
+    assert mean <= 1e-4 and mx <= 1e-3

@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every symbol include/hgeo.h declares, its
+structs match the binding, and host-side validation errors come back as
+status codes -- all without a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1812_06060_amd import _hgeo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgeo.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_hgeo.LIB_PATH):
+        from paper_1812_06060_amd import build
+        build.build(verbose=False)
+    return _hgeo.load_library()
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hg_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_hgeo.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", _hgeo.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, flags=re.M), n
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include "hgeo.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(hg_opts), sizeof(hg_info),'
+                   ' sizeof(hg_mesh_stats), offsetof(hg_info, bytes_alg), offsetof(hg_opts, mu));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [C.sizeof(_hgeo.Opts), C.sizeof(_hgeo.Info), C.sizeof(_hgeo.MeshStats),
+                   _hgeo.Info.bytes_alg.offset, _hgeo.Opts.mu.offset]
+
+
+def test_defaults(lib):
+    o = _hgeo.Opts()
+    assert lib.hg_opts_default(C.byref(o)) == 0
+    assert o.formulation == _hgeo.FORM_EDGE and o.mu == 100.0 and o.m == 1.0
+    assert lib.hg_opts_default(None) == _hgeo.HG_E_INVALID_ARG
+
+
+def _create(lib, v, f):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    h = C.c_void_p()
+    st = lib.hg_mesh_create(v.ctypes.data_as(C.c_void_p), v.shape[0], f.ctypes.data_as(C.c_void_p),
+                            f.shape[0], None, C.byref(h))
+    return st, lib.hg_last_error().decode()
+
+
+@pytest.mark.parametrize("tris, what", [
+    ([[0, 1, 5]], "out of range"),
+    ([[0, 1, 1]], "repeats"),
+    ([[0, 1, 2], [0, 1, 3]], "inconsistent"),
+    ([[0, 1, 2], [1, 0, 3], [0, 1, 4]], "non-manifold"),
+])
+def test_bad_meshes_rejected_before_any_device_work(lib, tris, what):
+    v = np.random.default_rng(0).standard_normal((5, 3))
+    st, msg = _create(lib, v, tris)
+    assert st == _hgeo.HG_E_BAD_MESH and what in msg
+
+
+def test_null_and_empty_arguments(lib):
+    h = C.c_void_p()
+    assert lib.hg_mesh_create(None, 3, None, 1, None, C.byref(h)) == _hgeo.HG_E_INVALID_ARG
+    v = np.zeros((3, 3))
+    f = np.zeros((0, 3), dtype=np.int32)
+    st, msg = _create(lib, v, f)
+    assert st == _hgeo.HG_E_INVALID_ARG and "empty" in msg
+    st, msg = _create(lib, np.full((3, 3), np.nan), [[0, 1, 2]])
+    assert st == _hgeo.HG_E_INVALID_ARG
