@@ -9,17 +9,19 @@ Sec. 5.2), written with the PSD stiffness K = -L_c as
 Exact solve (:func:`solve_log`).  For small t the solution decays by about
 e^-1 per ring of vertices, so on large meshes it leaves the FP64 range.  The
 paper does not say how it handles this.  The oracle solves the same linear
-system in bands of the potential psi_j = (shortest edge-path length from the
-sources to v_j)/sqrt(t), which bounds the decay of u from above: band b holds
-the vertices with psi in [b R, (b+1) R).  Band b is solved together with a
-margin of the next ``margin`` units of psi as the principal subsystem
-M_UU w = u_0|_U - M_UI u_I, with the already solved inner vertices I as data
-and zero beyond the margin, in plain FP64 after dividing by the largest inner
-value.  Principal submatrices of the M-matrix M are M-matrices: their LU with
-diagonal pivots and the right-hand side above involve no cancellation, so each
-band is accurate componentwise and relatively.  Cutting the system at the
-outer edge of the margin changes the band's values by a factor of order
-exp(-margin) or faster; margin = 60 puts that far below FP64 rounding.  One band (the
+system band by band over the breadth-first rings (hop distance to the
+sources).  For an M-matrix, u_j >= c_jk u_k with c_jk = t theta_jk / M_jj,
+so u falls by at most beta = max_jk ln(1/c_jk) nats per ring; bands of
+B = floor(300 / beta) rings therefore span at most 300 nats.  Band b (rings
+[bB, (b+1)B)) is solved together with the next B rings as the principal
+subsystem M_UU w = u_0|_U - M_UI u_I, with the already solved inner rings I
+as data and zero beyond, in plain FP64 after dividing by the largest inner
+value.  Principal submatrices of an M-matrix are M-matrices: their LU with
+diagonal pivots and the right-hand side above involve no cancellation, so
+each band is accurate componentwise and relatively.  Cutting the system B
+rings further out changes the band's values by a factor decaying like the
+Green's function over those rings (far below FP64 rounding for the B above;
+the pins check it against an independent 80-bit iteration).  One band (the
 whole mesh, no scaling) is the plain FP64 solve.  The result is log u.
 
 Reference iteration (:func:`gauss_seidel_bfs`): the paper's breadth-first
@@ -33,7 +35,6 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
-from scipy.sparse.csgraph import dijkstra
 
 
 def heat_matrix(K: sp.spmatrix, A: np.ndarray, t: float) -> sp.csr_matrix:
@@ -41,48 +42,58 @@ def heat_matrix(K: sp.spmatrix, A: np.ndarray, t: float) -> sp.csr_matrix:
     return (sp.diags(A) + t * K).tocsr()
 
 
-def edge_path_potential(verts, edges, sources, t: float) -> np.ndarray:
-    """psi_j = (shortest edge-path length from the source set)/sqrt(t)."""
-    nv = verts.shape[0]
-    w = np.linalg.norm(verts[edges[:, 0]] - verts[edges[:, 1]], axis=1)
-    G = sp.csr_matrix((np.concatenate([w, w]),
-                       (np.concatenate([edges[:, 0], edges[:, 1]]),
-                        np.concatenate([edges[:, 1], edges[:, 0]]))), shape=(nv, nv))
-    dist = dijkstra(G, directed=False, indices=np.asarray(sources), min_only=True)
-    return dist / np.sqrt(t)
+def hop_levels(M: sp.spmatrix, sources) -> np.ndarray:
+    """Breadth-first ring index of every vertex (hop distance to the source
+    set over the sparsity graph of M); -1 where unreachable."""
+    from scipy.sparse.csgraph import breadth_first_order
+    G = M.tocsr()
+    nv = G.shape[0]
+    lev = np.full(nv, -1, dtype=np.int64)
+    front = np.unique(np.asarray(sources, dtype=np.int64))
+    lev[front] = 0
+    indptr, indices = G.indptr, G.indices
+    i = 0
+    while front.size:
+        i += 1
+        nb = np.unique(np.concatenate([indices[indptr[v]:indptr[v + 1]] for v in front]))
+        nb = nb[lev[nb] < 0]
+        lev[nb] = i
+        front = nb
+    return lev
 
 
-def solve_log(M: sp.csr_matrix, sources, psi: np.ndarray | None = None,
-              band: float = 200.0, margin: float = 60.0) -> np.ndarray:
+def solve_log(M: sp.csr_matrix, sources, band_rings: int | None = None,
+              margin_rings: int | None = None) -> np.ndarray:
     """log u for M u = u_0 (u_0 = 1 at each source), marching outward over
-    bands of psi.  Unreachable vertices (psi = inf) get log u = -inf.  With
-    psi = None the whole mesh is one band (plain FP64)."""
+    bands of breadth-first rings.  Unreachable vertices get log u = -inf.
+    band_rings=None picks B = floor(300 / beta) (see the module text); the
+    margin defaults to B rings.  At t = m hbar^2 the truncation error falls by
+    about e^(-2 / sqrt(m)) per margin ring, so the default margin is ample for
+    m up to ~30."""
     nv = M.shape[0]
     sources = np.unique(np.asarray(sources, dtype=np.int64))
-    if psi is None:
-        psi = np.zeros(nv)
     M = M.tocsr()
+    lev = hop_levels(M, sources)
     out = np.full(nv, -np.inf)
-    reach = np.isfinite(psi)
-    if not reach.any():
-        return out
-    pmax = psi[reach].max()
-    nb = int(pmax // band) + 1
+    if band_rings is None:
+        C = M.tocoo()
+        off = C.row != C.col
+        c = np.abs(C.data[off]) / M.diagonal()[C.row[off]]
+        beta = float(np.log(1.0 / c[c > 0]).max()) if np.any(c > 0) else 1.0
+        band_rings = max(1, int(300.0 // beta))
+    B = int(band_rings)
+    G = int(margin_rings) if margin_rings is not None else B
+    depth = int(lev.max())
     u0 = np.zeros(nv)
     u0[sources] = 1.0
     solved = np.zeros(nv, dtype=bool)
-    for b in range(nb):
-        lo, hi = b * band, (b + 1) * band
-        U = np.flatnonzero(reach & (psi >= lo) & (psi < hi + margin))
-        core = reach & (psi >= lo) & (psi < hi)
-        if not core.any():
-            continue
+    for lo in range(0, depth + 1, B):
+        U = np.flatnonzero((lev >= lo) & (lev < lo + B + G))
+        core = (lev >= lo) & (lev < lo + B)
         MU = M[U]
         rows = MU.tocoo()
         known = solved[rows.col]
-        scale = 0.0
-        if known.any():
-            scale = out[rows.col[known]].max()
+        scale = out[rows.col[known]].max() if known.any() else 0.0
         rhs = np.zeros(U.size)
         src_in = u0[U] > 0
         if src_in.any():

@@ -4,7 +4,7 @@ Steps (Algorithm 1 of the paper, with the direct solves of the original
 heat method that the paper's iterations replace):
 
 1. assembly: cotangent stiffness K, lumped areas A, t = m h^2 (Eq. 27);
-2. diffusion: (diag(A) + t K) u = u_0 (Eq. 4) by range-safe sparse LU;
+2. diffusion: (diag(A) + t K) u = u_0 (Eq. 4) by range-safe banded sparse LU;
 3. normalisation: h_f = -grad u / |grad u| (Eq. 3);
 4. Poisson: face form K d = r, or the edge-form variant L_E d = b_E, with
    d = 0 at every source.
@@ -42,7 +42,7 @@ def prepare(verts, tris):
 
 
 def heat_method(verts, tris, sources, m: float = 1.0, t: float | None = None,
-                form: str = "face", gauge: bool = True) -> HeatResult:
+                form: str = "face", banded: bool = True) -> HeatResult:
     verts = np.asarray(verts, dtype=np.float64)
     tris = np.asarray(tris, dtype=np.int64)
     sources = np.unique(np.asarray(sources, dtype=np.int64))
@@ -50,12 +50,9 @@ def heat_method(verts, tris, sources, m: float = 1.0, t: float | None = None,
     if t is None or t <= 0:
         t = m * hbar * hbar
     M = diffusion.heat_matrix(K, A, t)
-    psi = diffusion.edge_path_potential(verts, topo.edges, sources, t)
-    if not gauge:
-        psi = np.where(np.isfinite(psi), 0.0, np.inf)
-    logu = diffusion.solve_log(M, sources, psi)
+    logu = diffusion.solve_log(M, sources, band_rings=None if banded else 10 ** 9)
     h = gradient.normalized_field(verts, tris, logu)
-    reach = np.isfinite(psi)
+    reach = np.isfinite(logu)
     if form == "face":
         d = poisson.poisson_face(verts, tris, h, sources, reach)
     elif form == "edge":

@@ -74,14 +74,36 @@ def test_bfs_bit_exact(case):
     assert depth == rf.level.max()
 
 
-def test_diffusion_logu(case, hg):
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_diffusion_logu(case, hg, schedule):
     name, v, f, src, mesh, rf, _ = case
-    _say(name, "diffuse")
-    o = hg.default_opts(tol_u=1e-12)
+    _say(name, "diffuse schedule", schedule)
+    o = hg.default_opts(tol_u=1e-12, diffusion_schedule=schedule)
     logu, info = mesh.diffuse(src, 0.0, o)
     assert info.converged_u and abs(info.t - rf.t) <= 1e-14 * rf.t
     lu = logu.cpu().numpy()
     assert np.abs(lu - rf.logu).max() < 1e-8
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_diffusion_beyond_fp64_range(hg, schedule):
+    """t = 1e-4 hbar^2 on a displaced level-5 sphere: u reaches ~e^-800,
+    far outside FP64; compared with the oracle's banded solve (pinned to an 80-bit Jacobi)."""
+    from oracle import assembly, diffusion, mesh as omesh
+    v, f, src = meshgen.config_mesh("bumpy5")
+    _say("bumpy5 m=1e-4 diffuse schedule", schedule)
+    topo = omesh.build_topology(f, v.shape[0])
+    K = assembly.cotan_stiffness(v, f)
+    A = assembly.lumped_areas(v, f)
+    t = 1e-4 * assembly.mean_edge_length(v, topo.edges) ** 2
+    ref = diffusion.solve_log(diffusion.heat_matrix(K, A, t), src)
+    assert ref.min() < -760          # below the smallest FP64 subnormal, e^-744
+    mesh = hg.Mesh(v, f)
+    logu, info = mesh.diffuse(src, t, hg.default_opts(tol_u=1e-12, diffusion_schedule=schedule))
+    lu = logu.cpu().numpy()
+    assert info.converged_u and np.all(np.isfinite(lu))
+    assert np.abs(lu - ref).max() < 1e-7 * np.abs(ref).max()
+    mesh.close()
 
 
 def test_normalize(case):

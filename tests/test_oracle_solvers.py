@@ -25,19 +25,17 @@ def bumpy3():
 
 
 # ------------------------------------------------------------ diffusion
-def test_diffusion_dense_solve_and_gauge(bumpy3):
+def test_diffusion_dense_solve_and_bands(bumpy3):
     v, f = bumpy3
     topo, K, A, t = _setup(v, f)
     M = diffusion.heat_matrix(K, A, t)
     src = [17]
     dense = np.linalg.solve(M.toarray(), np.eye(v.shape[0])[17])
-    l_plain = diffusion.solve_log(M, src)
-    l_band = diffusion.solve_log(M, src, diffusion.edge_path_potential(v, topo.edges, src, t), band=2.5, margin=30.0)
-    psi = diffusion.edge_path_potential(v, topo.edges, src, t)
-    l_gauge = diffusion.solve_log(M, src, psi)
-    assert np.abs(l_plain - np.log(dense)).max() < 1e-11
-    assert np.abs(l_gauge - np.log(dense)).max() < 1e-11
-    assert np.abs(l_band - np.log(dense)).max() < 1e-11
+    l_one = diffusion.solve_log(M, src, band_rings=10 ** 9)     # plain FP64, one band
+    l_band = diffusion.solve_log(M, src, band_rings=2, margin_rings=40)   # narrow bands
+    l_auto = diffusion.solve_log(M, src)
+    for l in (l_one, l_band, l_auto):
+        assert np.abs(l - np.log(dense)).max() < 1e-11
 
 
 def test_diffusion_mass_conservation_and_symmetry(bumpy3):
@@ -47,30 +45,48 @@ def test_diffusion_mass_conservation_and_symmetry(bumpy3):
     topo, K, A, t = _setup(v, f, m=2.0)
     M = diffusion.heat_matrix(K, A, t)
     for src in ([5], [5, 300, 511]):
-        psi = diffusion.edge_path_potential(v, topo.edges, src, t)
-        u = np.exp(diffusion.solve_log(M, src, psi))
+        u = np.exp(diffusion.solve_log(M, src, band_rings=3, margin_rings=40))
         assert abs((A * u).sum() - len(src)) < 1e-12 * len(src)
     a, b = 3, 600
-    ua = diffusion.solve_log(M, [a], diffusion.edge_path_potential(v, topo.edges, [a], t))
-    ub = diffusion.solve_log(M, [b], diffusion.edge_path_potential(v, topo.edges, [b], t))
+    ua = diffusion.solve_log(M, [a], band_rings=3, margin_rings=40)
+    ub = diffusion.solve_log(M, [b], band_rings=3, margin_rings=40)
     assert abs(ua[b] - ub[a]) < 1e-11
 
 
-def test_diffusion_extended_range_matches_plain_where_representable():
-    """The gauge route keeps componentwise relative accuracy where plain FP64
-    already represents u, and stays finite where plain FP64 underflows."""
-    v, f = meshgen.icosphere(6)
-    topo, K, A, t = _setup(v, f, m=0.01)      # tiny t: u spans ~e^-1200
+def _jacobi_longdouble(K, A, t, src, sweeps):
+    """Plain Jacobi sweeps of Eq. 7 in x87 80-bit floats (exponent range
+    e^-11355): an independent referee where FP64 cannot hold u."""
+    import scipy.sparse as sp
+    nv = A.size
+    T = (-(K - sp.diags(K.diagonal()))).tocsr()
+    rows = np.repeat(np.arange(nv), np.diff(T.indptr))
+    data = T.data.astype(np.longdouble)
+    D = (A + t * K.diagonal()).astype(np.longdouble)
+    u0 = np.zeros(nv, dtype=np.longdouble)
+    u0[src] = 1
+    u = np.zeros(nv, dtype=np.longdouble)
+    for _ in range(sweeps):
+        acc = np.zeros(nv, dtype=np.longdouble)
+        np.add.at(acc, rows, data * u[T.indices])
+        u = (u0 + np.longdouble(t) * acc) / D
+    return np.log(u).astype(np.float64)
+
+
+@pytest.mark.parametrize("m", [1e-4, 0.01])
+def test_diffusion_beyond_fp64_range_vs_80bit_jacobi(m):
+    """Where u leaves the FP64 range the banded solve matches an 80-bit
+    Jacobi iteration run to its fixed point."""
+    v, f = meshgen.icosphere(5)
+    v = meshgen.harmonic_displacement(v, seed=3)
+    topo, K, A, t = _setup(v, f, m=m)
     M = diffusion.heat_matrix(K, A, t)
     src = [0]
-    psi = diffusion.edge_path_potential(v, topo.edges, src, t)
-    lg = diffusion.solve_log(M, src, psi)
-    lp = diffusion.solve_log(M, src)
-    assert np.all(np.isfinite(lg))
-    ok = np.isfinite(lp) & (lp > -650)
-    assert ok.sum() > 0.3 * v.shape[0]
-    assert np.abs(lg[ok] - lp[ok]).max() < 1e-9
-    assert lg.min() < -700                      # a range plain FP64 cannot hold
+    lb = diffusion.solve_log(M, src)
+    lj = _jacobi_longdouble(K, A, t, src, 400 if m < 1e-3 else 1500)
+    if m < 1e-3:
+        assert lb.min() < -745          # below the smallest FP64 subnormal
+    assert np.all(np.isfinite(lb))
+    assert np.abs(lb - lj).max() < 1e-9 * np.abs(lj).max()
 
 
 def test_paper_iterations_converge_to_direct(bumpy3):
