@@ -25,7 +25,8 @@ uint64_t Mesh::mesh_bytes() const {
     return px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() + ebar.bytes() +
-           halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes();
+           tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
+           theta_ell.bytes();
 }
 
 Mesh::~Mesh() {
@@ -164,6 +165,7 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
             m->n_patches = (int)(T.halo_ptr.size() - 1);
             m->max_halo = T.max_halo;
             m->max_ell_width = T.max_ell_width;
+            m->tile_ptr.upload(T.tile_ptr, s);
             m->halo_ptr.upload(T.halo_ptr, s);
             m->halo_idx.upload(T.halo_idx, s);
             m->ell_ptr.upload(T.ell_ptr, s);

@@ -1,10 +1,12 @@
 // Internal structures of the hgeo library (not part of the C ABI).
 //
-// Device layout of a resident mesh.  Vertices are renumbered internally in
-// 3D Morton order so that one-ring neighbourhoods sit close in memory and
-// contiguous vertex ranges form compact surface patches; faces are sorted by
-// their smallest internal vertex and edges by their internal endpoints.  The
-// permutations back to the caller's order are kept on the device.
+// Device layout of a resident mesh.  Vertices are renumbered internally tile
+// by tile: tiles are connected patches of at most 1024 vertices grown
+// breadth-first from seeds taken in 3D Morton order, so one-ring
+// neighbourhoods sit close in memory and every tile is a compact surface
+// patch; faces are sorted by their smallest internal vertex and edges by
+// their internal endpoints.  The permutations back to the caller's order are
+// kept on the device.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -81,8 +83,9 @@ struct HostTopo {
     std::vector<int32_t> ev;                // [ne*2] tail, head (internal ids)
     std::vector<int32_t> ef;                // [ne*2] incident faces, -1 if none
     std::vector<int32_t> perm_e;            // internal edge -> canonical edge
-    // patch tiles (contiguous internal vertex ranges) and their halos
+    // tiles (contiguous internal vertex ranges) and their halos
     int patch_size = 0;
+    std::vector<int32_t> tile_ptr;          // [n_tiles+1] first internal vertex
     std::vector<int32_t> halo_ptr, halo_idx;
     std::vector<uint16_t> lnb;              // ELL local neighbour slots
     std::vector<int32_t> ell_ptr;           // per patch: offset of its ELL block
@@ -116,9 +119,10 @@ struct Mesh {
 
     // patch tiles
     int patch_size = 0, n_patches = 0, max_halo = 0, max_ell_width = 0;
-    DBuf<int32_t> halo_ptr, halo_idx, ell_ptr;
+    DBuf<int32_t> tile_ptr, halo_ptr, halo_idx, ell_ptr;
     DBuf<uint16_t> lnb;
     DBuf<uint8_t> ell_width;
+    DBuf<double> theta_ell;                 // theta in the tiles' ELL layout
 
     // per-query workspace (kept between queries)
     struct Work {
@@ -159,6 +163,9 @@ struct DiffusionResult {
 DiffusionResult run_diffusion(Mesh& m, const std::vector<int32_t>& src_internal, double t,
                               const hg_opts& o, hipStream_t s);
 void diffusion_logu(Mesh& m, hipStream_t s);                   // w.logu from (v, e)
+void build_theta_ell(Mesh& m, hipStream_t s);
+bool patch_supported(const Mesh& m);
+DiffusionResult run_diffusion_patch(Mesh& m, double t, const hg_opts& o, int inner, hipStream_t s);
 void run_normalize(Mesh& m, hipStream_t s);                    // w.h from (v, e)
 void normalize_from_logu(Mesh& m, const double* logu_user, hipStream_t s);
 struct AdmmResult {

@@ -124,6 +124,11 @@ __global__ void k_diff_logu(int nv, const double* v, const int32_t* e, double* l
     logu[j] = x > 0.0 ? log(x) + (double)e[j] * 0.69314718055994530942 : -INFINITY;
 }
 
+static DiffusionResult run_diffusion_jacobi(Mesh& m, double t, const hg_opts& o, hipStream_t s);
+
+// Schedule choice: LDS-tiled passes (default when every tile's valence fits)
+// or plain global Jacobi sweeps.  Both start from u = 1 at the sources and 0
+// elsewhere and stop on the largest relative change of u.
 DiffusionResult run_diffusion(Mesh& m, const std::vector<int32_t>& src, double t, const hg_opts& o,
                               hipStream_t s) {
     (void)src;   // sources are the level-0 vertices of the preceding BFS
@@ -135,10 +140,23 @@ DiffusionResult run_diffusion(Mesh& m, const std::vector<int32_t>& src, double t
     w.e1.alloc(nv);
     w.invD.alloc(nv);
     const int grid = grid_for(nv, kBlockD);
-    if ((int)w.partial.n < grid + 8) w.partial.alloc((size_t)grid + 8);
     hipLaunchKernelGGL(k_diff_init, dim3(grid), dim3(kBlockD), 0, s, nv, t, m.Av.p, m.sum_theta.p, w.level.p,
                        w.invD.p, w.v0.p, w.e0.p);
     HG_CHECK_HIP(hipGetLastError());
+    const bool patch = o.diffusion_schedule == 2 || (o.diffusion_schedule == 0 && patch_supported(m));
+    if (patch) {
+        if (!patch_supported(m)) throw Error{HG_E_INVALID_ARG, "tiled schedule needs valence <= 16"};
+        const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : 32;
+        return run_diffusion_patch(m, t, o, inner, s);
+    }
+    return run_diffusion_jacobi(m, t, o, s);
+}
+
+static DiffusionResult run_diffusion_jacobi(Mesh& m, double t, const hg_opts& o, hipStream_t s) {
+    const int nv = (int)m.nv;
+    auto& w = m.w;
+    const int grid = grid_for(nv, kBlockD);
+    if ((int)w.partial.n < grid + 8) w.partial.alloc((size_t)grid + 8);
     DiffusionResult r;
     const int check = std::max(1, o.check_every);
     double* va = w.v0.p;

@@ -1,0 +1,304 @@
+// LDS-tiled diffusion sweeps for (A - t L_c) u = u_0 (Eq. 4, update Eq. 7).
+//
+// A tile is a connected patch of at most 1024 vertices (a contiguous range
+// of internal vertex ids) plus its halo (the outside one-ring).  One launch =
+// one global pass: every workgroup loads its tile and halo into LDS once,
+// performs `inner` Jacobi sweeps of the tile with the halo held fixed, and
+// writes the tile back.  Information therefore crosses a whole tile per HBM
+// pass instead of one ring, which is what a relative-accuracy solve of a
+// field that decays by ~e^-1 per ring needs (the number of plain sweeps grows
+// with the breadth-first depth of the mesh).  The fixed point is unchanged:
+// when every tile is converged for its converged halo, Eq. 7 holds
+// everywhere.  Reads come from one copy of (v, e) and writes go to the other,
+// so the result does not depend on workgroup timing.
+//
+// Range: during a pass every vertex j carries a reference exponent R_j and
+// LDS holds u_j 2^-R_j.  R_j starts at the exponent of u_j (none if u_j = 0)
+// and is raised by a max-plus relaxation, R_j >= R_k + floor(log2 c_jk) - 2
+// over the tile's edges, so that every rescaled weight c_jk 2^(R_k - R_j)
+// is at most 8: a vertex whose stored value is stale by many binades, or one
+// the front reaches during this pass, can then grow only by a bounded factor
+// per sweep, for any t.  The rescaling is by exact powers of two, so
+// rounding is that of FP64 on u_j 2^-R_j.
+
+// Coefficients c_jk = t theta_jk / (A_j + t sum_k theta_jk) and the LDS
+// slots of the neighbours stay in registers for the whole pass; the
+// tile-local neighbour table is in ELL layout (slot-major, coalesced).
+#include <climits>
+#include <cmath>
+
+#include "hgeo_internal.h"
+
+namespace hg {
+
+constexpr int kTile = 1024;    // vertices per tile at most (mesh_create uses the same)
+constexpr int kThreads = 256;  // 4 vertices per thread
+constexpr int kPer = kTile / kThreads;
+
+__device__ inline double blk_max(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int i = 1; i < kThreads / 64; ++i) r = fmax(r, sh[i]);
+    return r;
+}
+constexpr int kNone = -(1 << 30);   // "no reference exponent yet"
+
+template <int MAXW>
+__global__ void __launch_bounds__(kThreads) k_patch_pass(
+    int n_tiles, double t, const int32_t* __restrict__ tile_ptr, const int32_t* __restrict__ halo_ptr,
+    const int32_t* __restrict__ halo_idx, const int32_t* __restrict__ ell_ptr,
+    const uint8_t* __restrict__ ell_width, const uint16_t* __restrict__ lnb, const double* __restrict__ theta_ell,
+    const double* __restrict__ invD, const int32_t* __restrict__ level, const double* __restrict__ vin,
+    const int32_t* __restrict__ ein, double* __restrict__ vout, int32_t* __restrict__ eout, int inner,
+    double* __restrict__ partial) {
+    extern __shared__ double lds[];
+    __shared__ double shd[kThreads / 64];
+    const int p = xcd_block(blockIdx.x, gridDim.x);
+    const int v0 = tile_ptr[p];
+    const int np = tile_ptr[p + 1] - v0;
+    const int h0 = halo_ptr[p], nh = halo_ptr[p + 1] - h0;
+    const int ntot = kTile + nh;
+    double* cur = lds;
+    double* nxt = lds + ntot;
+    int* R = reinterpret_cast<int*>(lds + 2 * ntot);
+    const int tid = threadIdx.x;
+
+    // 1. coefficients c_jk = t theta_jk / (A_j + t sum theta) into registers,
+    //    with floor(log2 |c_jk|) for the exponent relaxation below
+    const int W = ell_width[p];
+    const int eb = ell_ptr[p];
+    double c[kPer][MAXW];
+    uint16_t l[kPer][MAXW];
+    double b[kPer];
+    int Rown[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        int i = tid + q * kThreads;
+        const bool in = i < np;
+        double id = in ? invD[v0 + i] : 0.0;
+        b[q] = id;
+#pragma unroll
+        for (int s = 0; s < MAXW; ++s) {
+            bool ok = in && (s < W);
+            uint16_t li = ok ? lnb[eb + s * kTile + i] : (uint16_t)0xFFFF;
+            ok = ok && li != 0xFFFF;
+            l[q][s] = ok ? li : (uint16_t)0;   // padding reads slot 0 with weight 0
+            const double th = ok ? theta_ell[eb + s * kTile + i] : 0.0;
+            c[q][s] = ok ? t * th * id : 0.0;
+        }
+    }
+
+    // 2. reference exponents: own exponent for non-zero values (and the
+    //    source term's for sources), "none" otherwise; halo keeps its own
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        int i = tid + q * kThreads;
+        int r = kNone;
+        if (i < np) {
+            int g = v0 + i;
+            if (vin[g] != 0.0) r = ein[g];
+            if (level[g] == 0) r = max(r, ilogb(b[q]));
+        }
+        Rown[q] = r;
+        R[i] = r;
+    }
+    for (int i = tid; i < nh; i += kThreads) {
+        int g = halo_idx[h0 + i];
+        R[kTile + i] = vin[g] != 0.0 ? ein[g] : kNone;
+    }
+    __syncthreads();
+    // 3. max-plus relaxation R_j = max(R_j, R_k + floor(log2 |c_jk|) - 2) over
+    //    the tile (halo fixed).  Every weight c_jk 2^(R_k - R_j) is then <= 8,
+    //    so no value can overflow within the pass.  The least fixed point is
+    //    unique (all edge weights are negative), so the in-place, any-order
+    //    updates give the same R every time; it is reached within np rounds.
+    for (int round = 0; round < kTile; ++round) {
+        int changed = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            int i = tid + q * kThreads;
+            if (i >= np) continue;
+            int r = Rown[q];
+#pragma unroll
+            for (int s = 0; s < MAXW; ++s) {
+                if (c[q][s] == 0.0) continue;
+                int rk = R[l[q][s]];
+                if (rk == kNone) continue;
+                r = max(r, rk + ilogb(c[q][s]) - 2);
+            }
+            if (r != Rown[q]) {
+                Rown[q] = r;
+                R[i] = r;
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    // 4. values and weights relative to the reference exponents
+    double vstart[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        int i = tid + q * kThreads;
+        const int rj = Rown[q];
+        const bool live = i < np && rj != kNone;
+        double x = 0.0;
+        if (live) {
+            int g = v0 + i;
+            double v = vin[g];
+            if (v != 0.0) x = ldexp(v, ein[g] - rj);
+            b[q] = level[g] == 0 ? ldexp(b[q], -rj) : 0.0;
+        } else {
+            b[q] = 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < MAXW; ++s) {
+            int rk = R[l[q][s]];
+            c[q][s] = (live && c[q][s] != 0.0 && rk != kNone) ? ldexp(c[q][s], rk - rj) : 0.0;
+        }
+        vstart[q] = x;
+        cur[i] = x;   // slots np..kTile-1 of a short tile stay 0
+    }
+    for (int i = tid; i < nh; i += kThreads) {
+        int g = halo_idx[h0 + i];
+        double v = vin[g];
+        cur[kTile + i] = v;   // the halo's reference exponent is its own
+        nxt[kTile + i] = v;
+    }
+    __syncthreads();
+
+    // 5. inner Jacobi sweeps in LDS
+    for (int it = 0; it < inner; ++it) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            int i = tid + q * kThreads;
+            double acc = b[q];
+#pragma unroll
+            for (int s = 0; s < MAXW; ++s) acc = fma(c[q][s], cur[l[q][s]], acc);
+            if (i < np) nxt[i] = acc;
+        }
+        __syncthreads();
+        double* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+
+    // 6. write back renormalised; largest relative change over the pass
+    //    (a non-finite value would be a bug: report it as not converged)
+    double res = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        int i = tid + q * kThreads;
+        if (i >= np) continue;
+        const int g = v0 + i;
+        double x = cur[i];
+        if (!isfinite(x)) {
+            vout[g] = 0.0;
+            eout[g] = 0;
+            res = 1e300;
+        } else if (x == 0.0) {
+            vout[g] = 0.0;
+            eout[g] = 0;
+            if (level[g] >= 0) res = 1.0;
+        } else {
+            int ex = ilogb(x);
+            vout[g] = ldexp(x, -ex);
+            eout[g] = Rown[q] + ex;
+            res = fmax(res, vstart[q] == 0.0 ? 1.0 : fabs(x - vstart[q]) / fabs(x));
+        }
+    }
+    res = blk_max(res, shd);
+    if (tid == 0) partial[blockIdx.x] = res;
+}
+
+// theta in the tiles' ELL layout, gathered from the CSR rows (same order);
+// one workgroup per tile.
+__global__ void k_theta_ell(const int32_t* tile_ptr, const int32_t* row_ptr, const double* theta,
+                            const int32_t* ell_ptr, const uint8_t* ell_width, double* theta_ell) {
+    const int p = blockIdx.x;
+    const int v0 = tile_ptr[p], np = tile_ptr[p + 1] - v0;
+    const int W = ell_width[p], eb = ell_ptr[p];
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        int v = v0 + i;
+        int k0 = row_ptr[v], deg = row_ptr[v + 1] - k0;
+        for (int s = 0; s < W; ++s) theta_ell[eb + s * kTile + i] = s < deg ? theta[k0 + s] : 0.0;
+    }
+}
+
+void build_theta_ell(Mesh& m, hipStream_t s) {
+    if (m.patch_size != kTile) throw Error{HG_E_DEVICE, "tile size mismatch"};
+    m.theta_ell.alloc(m.lnb.n);
+    hipLaunchKernelGGL(k_theta_ell, dim3(m.n_patches), dim3(256), 0, s, m.tile_ptr.p, m.row_ptr.p, m.theta.p,
+                       m.ell_ptr.p, m.ell_width.p, m.theta_ell.p);
+    HG_CHECK_HIP(hipGetLastError());
+}
+
+static size_t patch_lds_bytes(const Mesh& m) { return (size_t)(kTile + m.max_halo) * (8 + 8 + 4); }
+
+// valence within the register tables, LDS within 64 KiB
+bool patch_supported(const Mesh& m) {
+    return m.max_ell_width <= 16 && m.patch_size == kTile && patch_lds_bytes(m) <= 65536;
+}
+
+// Runs patch passes until the largest relative change over a pass is <= tol.
+DiffusionResult run_diffusion_patch(Mesh& m, double t, const hg_opts& o, int inner, hipStream_t s) {
+    const int nv = (int)m.nv;
+    auto& w = m.w;
+    const int nt = m.n_patches;
+    if ((int)w.partial.n < nt + 8) w.partial.alloc((size_t)nt + 8);
+    const size_t lds = patch_lds_bytes(m);
+    DiffusionResult r;
+    // algorithmic bytes of one pass: tile tables (ELL slots + theta), halo
+    // list, 1/D and level, (v, e) read for tile and halo, (v, e) written
+    r.bytes_per_pass = (uint64_t)m.lnb.n * (2 + 8) + (uint64_t)m.halo_idx.n * (4 + 16) +
+                       (uint64_t)nv * (8 + 4 + 12 + 12) + (uint64_t)nt * 17;
+    double* va = w.v0.p;
+    double* vb = w.v1.p;
+    int32_t* ea = w.e0.p;
+    int32_t* eb = w.e1.p;
+    const int check = std::max(1, o.check_every / std::max(1, inner / 4));
+    RunTimer rt;
+    int run_len = 0;
+    const int max_passes = std::max(1, o.max_sweeps / std::max(1, inner));
+    for (int it = 1; it <= max_passes; ++it) {
+        if (!rt.open) {
+            rt.start(s);
+            run_len = 0;
+        }
+#define HG_PATCH_ARGS                                                                                             \
+    dim3(nt), dim3(kThreads), lds, s, nt, t, m.tile_ptr.p, m.halo_ptr.p, m.halo_idx.p, m.ell_ptr.p,        \
+        m.ell_width.p, m.lnb.p, m.theta_ell.p, w.invD.p, w.level.p, va, ea, vb, eb, inner, w.partial.p
+        if (m.max_ell_width <= 6)
+            hipLaunchKernelGGL(k_patch_pass<6>, HG_PATCH_ARGS);
+        else if (m.max_ell_width <= 8)
+            hipLaunchKernelGGL(k_patch_pass<8>, HG_PATCH_ARGS);
+        else
+            hipLaunchKernelGGL(k_patch_pass<16>, HG_PATCH_ARGS);
+#undef HG_PATCH_ARGS
+        HG_CHECK_HIP(hipGetLastError());
+        ++run_len;
+        std::swap(va, vb);
+        std::swap(ea, eb);
+        r.passes = it;
+        r.sweeps = it * inner;
+        if ((it % check) == 0 || it == max_passes) {
+            r.kernel_ms += rt.stop(s);
+            r.timed_launches += run_len;
+            r.res = reduce_partials(m, nt, true, s);
+            if (r.res <= o.tol_u) {
+                r.converged = true;
+                break;
+            }
+        }
+    }
+    if (va != w.v0.p) {
+        HG_CHECK_HIP(hipMemcpyAsync(w.v0.p, va, (size_t)nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HG_CHECK_HIP(hipMemcpyAsync(w.e0.p, ea, (size_t)nv * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    return r;
+}
+
+}  // namespace hg

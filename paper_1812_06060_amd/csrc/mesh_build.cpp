@@ -1,7 +1,9 @@
 // Host-side connectivity of a triangle mesh for the hgeo library.
 //
 // Builds, in linear time (bucket sorts keyed by vertex id):
-//   * the internal vertex order (3D Morton order of the positions);
+//   * tiles: connected patches of at most patch_size vertices, grown
+//     breadth-first from seeds taken in 3D Morton order of the positions;
+//     the internal vertex order is tile-major;
 //   * faces sorted by their smallest internal vertex;
 //   * unique edges, the orientation halfedge of each (from the smaller to the
 //     larger caller vertex id, Sec. 4.1), the incident faces, and per face
@@ -9,8 +11,8 @@
 //   * the canonical (caller-facing) edge numbering;
 //   * the CSR one-ring adjacency used by the breadth-first sets (Eq. 6) and
 //     the diffusion sweeps (Eq. 7);
-//   * LDS tiles: contiguous internal vertex ranges with their halos and the
-//     tile-local neighbour slots of every vertex (ELL layout).
+//   * per tile: its halo (outside one-ring) and the tile-local neighbour
+//     slots of every vertex (ELL layout).
 // Geometry (areas, cotangent weights) is computed later on the GPU.
 #include <algorithm>
 #include <cmath>
@@ -68,13 +70,61 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
         mk[i] = {spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2), (int32_t)i};
     }
     std::sort(mk.begin(), mk.end());
+
+    // ---- tiles: breadth-first region growing over the caller's one-ring
+    // adjacency, seeded at the first unassigned vertex in Morton order; each
+    // tile is connected and holds at most patch_size vertices.  The internal
+    // vertex order is tile-major, breadth-first inside a tile.
+    const int P = patch_size;
+    std::vector<int32_t> order_v;
+    order_v.reserve(nv);
+    T.tile_ptr.clear();
+    {
+        std::vector<int32_t> deg(nv + 1, 0);
+        for (int64_t f = 0; f < nf; ++f)
+            for (int k = 0; k < 3; ++k) deg[tri_in[3 * f + k] + 1] += 2;
+        for (int64_t i = 0; i < nv; ++i) deg[i + 1] += deg[i];
+        std::vector<int32_t> adj(deg[nv]);
+        std::vector<int32_t> pos(deg.begin(), deg.end() - 1);
+        for (int64_t f = 0; f < nf; ++f)
+            for (int k = 0; k < 3; ++k) {
+                int32_t a = tri_in[3 * f + k], b = tri_in[3 * f + (k + 1) % 3];
+                adj[pos[a]++] = b;
+                adj[pos[b]++] = a;
+            }
+        std::vector<int32_t> assigned(nv, -1);
+        std::vector<int32_t> queue;
+        queue.reserve(P);
+        int32_t tile = 0;
+        for (int64_t r = 0; r < nv; ++r) {
+            int32_t seed = mk[r].second;
+            if (assigned[seed] >= 0) continue;
+            T.tile_ptr.push_back((int32_t)order_v.size());
+            queue.clear();
+            queue.push_back(seed);
+            assigned[seed] = tile;
+            for (size_t qi = 0; qi < queue.size() && (int)queue.size() < P; ++qi) {
+                int32_t x = queue[qi];
+                for (int32_t k = deg[x]; k < deg[x + 1] && (int)queue.size() < P; ++k) {
+                    int32_t y = adj[k];
+                    if (assigned[y] < 0) {
+                        assigned[y] = tile;
+                        queue.push_back(y);
+                    }
+                }
+            }
+            order_v.insert(order_v.end(), queue.begin(), queue.end());
+            ++tile;
+        }
+        T.tile_ptr.push_back((int32_t)order_v.size());
+    }
     T.perm_v.resize(nv);
     T.iperm_v.resize(nv);
     T.px.resize(nv);
     T.py.resize(nv);
     T.pz.resize(nv);
     for (int64_t i = 0; i < nv; ++i) {
-        int32_t u = mk[i].second;
+        int32_t u = order_v[i];
         T.perm_v[i] = u;
         T.iperm_v[u] = (int32_t)i;
         T.px[i] = xyz[3 * u];
@@ -233,10 +283,9 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
     }
     T.max_valence = maxdeg;
 
-    // ---- LDS tiles: contiguous internal ranges, halos, ELL local slots
-    const int P = patch_size;
+    // ---- LDS tiles: halos and ELL local slots of the tiles built above
     T.patch_size = P;
-    const int64_t np = (nv + P - 1) / P;
+    const int64_t np = (int64_t)T.tile_ptr.size() - 1;
     T.halo_ptr.assign(np + 1, 0);
     T.halo_idx.clear();
     T.ell_ptr.assign(np + 1, 0);
@@ -247,7 +296,7 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
     std::vector<int32_t> hmap;   // global -> halo slot for the current tile
     std::vector<int32_t> halo;
     for (int64_t p = 0; p < np; ++p) {
-        int64_t v0 = p * P, v1 = std::min<int64_t>(nv, v0 + P);
+        int64_t v0 = T.tile_ptr[p], v1 = T.tile_ptr[p + 1];
         halo.clear();
         int width = 0;
         for (int64_t v = v0; v < v1; ++v) {
