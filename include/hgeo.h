@@ -64,17 +64,25 @@ typedef struct {
                                (Eq. 27, hbar = mean edge length); default 1 */
     double tol_u;           /* diffusion: stop when the largest relative change
                                of u over one sweep is <= tol_u; default 1e-11 */
-    double tol_admm;        /* ADMM: stop when the primal and dual residuals
-                               are <= tol_admm in the form's scale (see
-                               hg_geodesic_solve); default 2e-6 */
+    double tol_admm;        /* ADMM stopping tolerance, default 1e-5.  In
+                               hg_geodesic_solve: stop when the estimated
+                               remaining change of the integrated distance
+                               field is <= tol_admm * max d.  In the ADMM step
+                               entry points: stop when the primal and dual
+                               residuals are <= tol_admm (scales below). */
     int32_t max_sweeps;     /* diffusion sweep cap; default 100000 */
     int32_t max_admm;       /* ADMM iteration cap; default 50000 */
-    double mu;              /* ADMM penalty (the paper's 100) */
+    double mu;              /* ADMM penalty (the paper uses 100); default 0 =
+                               auto: max(30, depth/2) in hg_geodesic_solve
+                               (depth = breadth-first depth of the query),
+                               100 in the ADMM step entry points */
     int32_t check_every;    /* iterations between convergence checks; 32 */
     int32_t diffusion_schedule; /* 0 = auto, 1 = global Jacobi sweeps,
                                    2 = LDS-tiled patch sweeps */
     int32_t inner_sweeps;   /* patch schedule: sweeps per global pass; 0 = auto */
-    int32_t reserved[8];
+    double relax;           /* ADMM over-relaxation alpha in (0, 2); default
+                               1.8; 1 = the paper's iteration */
+    int32_t reserved[6];
 } hg_opts;
 
 /* Per-solve report. */
@@ -138,9 +146,12 @@ hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* stats);
  *   d_dev     : DEVICE float32[nv] output distances (caller order);
  *               vertices not connected to a source get +inf.
  *   info      : optional report.
- * ADMM stopping scale: face form as in Sec. 3.2, |r_p| <= |M|_F tol and
- * |r_d| <= |M|_F tol; edge form rms(r_p) <= tol*hbar and
- * rms(r_d)/mu <= tol*hbar over the 3|F| copies.
+ * ADMM stops on the distance field: every check_every (>= 64) iterations the
+ * current gradients are integrated; with delta the largest change of d since
+ * the previous check and r the ratio of the last two changes, it stops when
+ * delta r / (1 - r) <= tol_admm max d.  info reports the paper's residuals
+ * at the end: face form |r_p|/|M|_F and |r_d|/|M|_F (Sec. 3.2); edge form
+ * rms(r_p)/hbar and rms(r_d)/(mu hbar) over the 3|F| copies.
  * Returns HG_E_NOT_CONVERGED (results written) if a cap was hit.
  */
 hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,

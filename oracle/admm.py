@@ -27,6 +27,14 @@ iteration:
 
 initialised with lambda = 0, x_e = mean of its targets, w_f = Z_f.
 Residuals r_p = W - RX, r_d = mu R dX.
+
+Over-relaxation (optional, relax = alpha = 1 is the paper's iteration): the
+standard over-relaxed ADMM of Boyd et al. (the ADMM survey the paper cites,
+Sec. 3.4.3) replaces, in the second update and the dual update, the first
+block's output by its mix with the previous second-block value:
+y_hat = alpha y + (1 - alpha) S g (face form), w_hat = alpha w + (1 - alpha) R x
+(edge form).  It has the same fixed points; alpha in (1, 2) typically
+converges faster.
 """
 from __future__ import annotations
 
@@ -77,8 +85,9 @@ class FaceADMMState:
 
 
 class FaceADMM:
-    def __init__(self, verts, tris, topo, h, mu: float = 100.0):
+    def __init__(self, verts, tris, topo, h, mu: float = 100.0, relax: float = 1.0):
         self.mu = mu
+        self.relax = relax
         area, _, _ = face_geometry(verts, tris)
         interior = np.flatnonzero(topo.edge_nfaces == 2)
         self.faces = topo.edge_faces[interior].reshape(-1)          # f(k) per copy
@@ -100,12 +109,13 @@ class FaceADMM:
         q = s.g[self.faces] - s.lam / (mu * al)[:, None]
         y = np.empty_like(q)
         y[0::2], y[1::2] = y_update(q[0::2], q[1::2], self.ebar, A[0::2], A[1::2])
-        acc = y + s.lam / (mu * al)[:, None]
+        yh = self.relax * y + (1.0 - self.relax) * s.g[self.faces]
+        acc = yh + s.lam / (mu * al)[:, None]
         tot = np.zeros((self.nf, 3))
         for c in range(3):
             tot[:, c] = np.bincount(self.faces, weights=acc[:, c], minlength=self.nf)
         g = g_update(self.h, tot, self.count, mu)
-        lam = s.lam + mu * al[:, None] * (y - g[self.faces])
+        lam = s.lam + mu * al[:, None] * (yh - g[self.faces])
         r_p = np.linalg.norm(al[:, None] * (y - g[self.faces]))
         r_d = np.linalg.norm(mu * A[:, None] * (g - s.g)[self.faces])
         return FaceADMMState(g=g, y=y, lam=lam, iters=s.iters + 1, r_primal=r_p, r_dual=r_d)
@@ -131,8 +141,9 @@ class EdgeADMMState:
 
 
 class EdgeADMM:
-    def __init__(self, topo, Z, mu: float = 100.0):
+    def __init__(self, topo, Z, mu: float = 100.0, relax: float = 1.0):
         self.mu = mu
+        self.relax = relax
         self.topo = topo
         self.Z = np.asarray(Z, dtype=np.float64)                     # [F, 3]
         self.q = topo.face_signs.astype(np.float64)                  # [F, 3]
@@ -150,9 +161,10 @@ class EdgeADMM:
     def step(self, s: EdgeADMMState) -> EdgeADMMState:
         mu, q = self.mu, self.q
         w = w_update(s.x[self.fe], s.lam, q, mu)
+        wh = self.relax * w + (1.0 - self.relax) * s.x[self.fe]
         x = x_update(self._sum_to_edges(self.Z), self._sum_to_edges(s.lam),
-                     self._sum_to_edges(w), self.nH, mu)
-        lam = s.lam + mu * (w - x[self.fe])
+                     self._sum_to_edges(wh), self.nH, mu)
+        lam = s.lam + mu * (wh - x[self.fe])
         r_p = np.linalg.norm(w - x[self.fe])
         r_d = np.linalg.norm(mu * (x - s.x)[self.fe])
         return EdgeADMMState(x=x, w=w, lam=lam, iters=s.iters + 1, r_primal=r_p, r_dual=r_d)

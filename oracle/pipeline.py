@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import assembly, bfs, diffusion, gradient, mesh, poisson
+from . import assembly, bfs, diffusion, gradient, mesh, multigrid, poisson
 
 
 @dataclass
@@ -50,16 +50,30 @@ def heat_method(verts, tris, sources, m: float = 1.0, t: float | None = None,
     if t is None or t <= 0:
         t = m * hbar * hbar
     M = diffusion.heat_matrix(K, A, t)
-    logu = diffusion.solve_log(M, sources, band_rings=None if banded else 10 ** 9)
+    large = verts.shape[0] > 200000
+    if not banded:
+        logu = diffusion.solve_log(M, sources, band_rings=10 ** 9)
+    elif large:
+        logu = diffusion.solve_log(M, sources, band_rings=40, margin_rings=40)
+    else:
+        logu = diffusion.solve_log(M, sources)
     h = gradient.normalized_field(verts, tris, logu)
     reach = np.isfinite(logu)
+    rp, col = mesh.vertex_adjacency(verts.shape[0], topo.edges)
+    Ps = multigrid.subdivision_prolongations(verts.shape[0], rp, col) if large else []
     if form == "face":
-        d = poisson.poisson_face(verts, tris, h, sources, reach)
+        if Ps and reach.all():
+            d, _, _ = multigrid.dirichlet_solve_mg(K, poisson.face_rhs(verts, tris, h), sources, Ps)
+        else:
+            d = poisson.poisson_face(verts, tris, h, sources, reach)
     elif form == "edge":
-        d = poisson.poisson_edge(verts, tris, topo, h, sources, reach)
+        if Ps and reach.all():
+            L, bE = poisson.edge_system(verts, tris, topo, h)
+            d, _, _ = multigrid.dirichlet_solve_mg(L, bE, sources, Ps)
+        else:
+            d = poisson.poisson_edge(verts, tris, topo, h, sources, reach)
     else:
         raise ValueError(form)
-    rp, col = mesh.vertex_adjacency(verts.shape[0], topo.edges)
     level, parent = bfs.bfs_levels_vec(verts.shape[0], rp, col, sources)
     return HeatResult(t=t, hbar=hbar, logu=logu, h=h, d=d, level=level,
                       parent=parent, topo=topo)

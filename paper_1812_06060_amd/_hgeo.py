@@ -37,7 +37,7 @@ class Opts(C.Structure):
         ("formulation", C.c_int32), ("m", C.c_double), ("tol_u", C.c_double),
         ("tol_admm", C.c_double), ("max_sweeps", C.c_int32), ("max_admm", C.c_int32),
         ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
-        ("inner_sweeps", C.c_int32), ("reserved", C.c_int32 * 8),
+        ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("reserved", C.c_int32 * 6),
     ]
 
 

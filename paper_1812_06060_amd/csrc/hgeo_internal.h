@@ -11,6 +11,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -138,6 +139,7 @@ struct Mesh {
         DBuf<float> gf;                     // [nf*3] final face gradients (internal)
         DBuf<float> shi0, slo0, shi1, slo1; // integration double-float sums
         DBuf<int32_t> jp0, jp1;             // pointer-jumping parents
+        DBuf<float> dprev;                  // distance at the previous ADMM check
         DBuf<double> partial;               // reduction partials
         DBuf<double> red_host_dummy;
         double* pinned = nullptr;           // host pinned reduction results
@@ -205,9 +207,39 @@ struct RunTimer {
         return ms;
     }
 };
-AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s);
-AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s);
+// iters > 0: exactly that many iterations.  Otherwise run to convergence:
+// with depth >= 0 (the breadth-first depth of the query) by the change of the
+// integrated distance field (DistStop), else by the paper's residuals.
+AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1);
+AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1);
 void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s);
+// integrates the given state (edge differences xe or face gradients g) and
+// returns max |d - d_prev| (inf on the first call) and max |d|; d_prev <- d
+void dist_change(Mesh& m, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
+                 double& delta, double& dmax);
+
+// Stopping rule on the distance field: with delta_k the largest change of d
+// between two checks and r = delta_k / delta_{k-1} < 1, the remaining change
+// of a geometrically converging iteration is at most delta_k r / (1 - r);
+// stop once that is <= tol * max|d|, or once delta_k itself is at the FP32
+// rounding floor (<= tol * max|d| / 20).
+struct DistStop {
+    bool first = true;
+    double prev = 0.0;
+    bool update(double delta, double dmax, double tol) {
+        bool done = false;
+        if (!first && std::isfinite(delta)) {
+            if (std::isfinite(prev) && prev > 0.0 && delta < prev) {
+                double r = delta / prev;
+                done = delta * r / (1.0 - r) <= tol * dmax;
+            }
+            if (delta <= 0.05 * tol * dmax) done = true;
+        }
+        first = false;
+        prev = delta;
+        return done;
+    }
+};
 
 // permutation helpers
 void gather_faces_to_internal(Mesh& m, const float* user3, float* internal3, hipStream_t s);

@@ -1,8 +1,10 @@
 // Normalisation (Eq. 3), edge targets (Eq. 18) and the two ADMM solvers of
 // the gradient optimisation: face form (Sec. 3.2) and edge form (Sec. 4.1).
 //
-// Both solvers run the paper's iterations unchanged, with the state folded so
-// that one fused kernel per iteration suffices:
+// Both solvers run the paper's iterations, optionally over-relaxed with
+// alpha (the standard over-relaxed ADMM of the ADMM survey the paper cites;
+// alpha = 1 is the paper's iteration, the fixed point does not depend on it),
+// with the state folded so that one fused kernel per iteration suffices:
 //
 // Edge form.  Per face slot keep zeta = lambda + mu w (of the current
 // iteration); then x_e = (sum_h h_e + sum_slots zeta) / (|H_e| (1 + mu))
@@ -10,13 +12,14 @@
 // x - lambda/mu = 2x - zeta/mu.  One iteration per face f and slot k:
 //     x_k   = (S_e + zeta_e0 + zeta_e1) / (|H_e| (1 + mu))
 //     w_f   = (I - q q^T/3)(2 x_f - zeta_f / mu)
-//     zeta' = zeta_f - mu x_f + mu w_f
+//     zeta' = zeta_f + mu alpha (w_f - x_f)
+// (zeta = lambda + mu w_hat with w_hat = alpha w + (1 - alpha) x.)
 // Starting from zeta = mu * (mean target) reproduces the paper's
 // initialisation (lambda = 0, x = mean of targets).
 //
 // Face form.  Per auxiliary copy k of face i keep z = y + lambda/(mu alpha_i);
 // then q_k = g_i - lambda_k/(mu alpha_i) = 2 g_i - z_k, the Y-update gives
-// y_k, the new z_k = y_k + z_k - g_i, and the G-update is
+// y_k, the new z_k = z_k + alpha (y_k - g_i), and the G-update is
 // g_i = (2 h_i + mu sum_k z_k) / (2 + mu |Y(i)|).  Each face computes its own
 // copies' Y-update (it reads the neighbour's g and z across the edge), so
 // one kernel per face performs Y, G and lambda updates.  z = h initially.
@@ -170,7 +173,7 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const uint32_t* _
                                                        const uint8_t* __restrict__ fsign,
                                                        const float* __restrict__ sumz,
                                                        const float* __restrict__ zin, float* __restrict__ zout,
-                                                       float mu, float inv1mu) {
+                                                       float mu, float inv1mu, float mu_relax) {
     int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     uint32_t sl[3];
@@ -193,14 +196,14 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const uint32_t* _
     qv *= (1.f / 3.f);
     for (int k = 0; k < 3; ++k) {
         float w = v[k] - qv * q[k];
-        zout[2 * slot_edge(sl[k]) + slot_side(sl[k])] = zo[k] + mu * (w - x[k]);
+        zout[2 * slot_edge(sl[k]) + slot_side(sl[k])] = zo[k] + mu_relax * (w - x[k]);
     }
 }
 
-// r_p = w' - x' = (lambda' - lambda)/mu with lambda = zeta - mu x;
-// r_d = mu (x' - x).  partial = (sum r_p^2, sum r_d^2) per block.
+// r_p = w' - x' with w' = x + (zeta' - zeta)/(mu alpha) (from the zeta
+// update), r_d = mu (x' - x).  partial = (sum r_p^2, sum r_d^2) per block.
 __global__ void k_resid_edge(int nf, const uint32_t* fslot, const float* sumz, const float* za, const float* zb,
-                             float mu, float inv1mu, double* partial) {
+                             float mu, float inv1mu, float mu_relax, double* partial) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     double rp = 0.0, rd = 0.0;
     if (f < nf) {
@@ -210,9 +213,8 @@ __global__ void k_resid_edge(int nf, const uint32_t* fslot, const float* sumz, c
             float S = sumz[e];
             float xa = edge_x(S, za[2 * e], za[2 * e + 1], bnd, inv1mu);
             float xb = edge_x(S, zb[2 * e], zb[2 * e + 1], bnd, inv1mu);
-            double la = (double)za[2 * e + side] - (double)mu * xa;
-            double lb = (double)zb[2 * e + side] - (double)mu * xb;
-            double p = (lb - la) / mu;
+            double wn = (double)xa + ((double)zb[2 * e + side] - (double)za[2 * e + side]) / mu_relax;
+            double p = wn - (double)xb;
             double d = (double)mu * ((double)xb - (double)xa);
             rp += p * p;
             rd += d * d;
@@ -259,14 +261,14 @@ static void reduce_pair(Mesh& m, int nblocks, hipStream_t s, double& a, double& 
     b = m.w.pinned[1];
 }
 
-AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s) {
+AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth) {
     const int nf = (int)m.nf, ne = (int)m.ne;
     auto& w = m.w;
     w.sumz.alloc(ne);
     w.z0.alloc((size_t)2 * ne);
     w.z1.alloc((size_t)2 * ne);
     w.xe.alloc(ne);
-    const float mu = (float)o.mu, inv1mu = 1.0f / (1.0f + mu);
+    const float mu = (float)o.mu, inv1mu = 1.0f / (1.0f + mu), mu_relax = (float)(o.mu * o.relax);
     const int gf = grid_for(nf, kBlockA), ge = grid_for(ne, kBlockA);
     if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
     hipLaunchKernelGGL(k_edge_targets, dim3(ge), dim3(kBlockA), 0, s, ne, m.ev.p, m.ef.p, m.px.p, m.py.p, m.pz.p,
@@ -275,9 +277,9 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s) {
     HG_CHECK_HIP(hipGetLastError());
     AdmmResult r;
     const bool fixed = iters > 0;
+    const bool monitor = !fixed && depth >= 0;
     const int cap = fixed ? iters : o.max_admm;
-    const int check = std::max(1, o.check_every);
-    const double scale = sqrt(3.0 * (double)nf) * m.hbar * o.tol_admm;
+    const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
     float* za = w.z0.p;
     float* zb = w.z1.p;
     // algorithmic bytes of one iteration: fslot + sign per face, the zeta pair
@@ -285,38 +287,54 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s) {
     r.bytes_per_iter = (uint64_t)13 * nf + (uint64_t)12 * ne + (uint64_t)12 * nf;
     RunTimer rt;
     int run_len = 0;
+    DistStop stop;
+    // residuals as rms over the 3|F| copies, r_p / hbar and r_d / (mu hbar)
+    auto residuals = [&](const float* prev, const float* cur) {
+        hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, w.sumz.p, prev, cur, mu,
+                           inv1mu, mu_relax, w.partial.p);
+        double a, b;
+        reduce_pair(m, gf, s, a, b);
+        r.rp = sqrt(a) / (sqrt(3.0 * (double)nf) * m.hbar);
+        r.rd = sqrt(b) / (sqrt(3.0 * (double)nf) * m.hbar * o.mu);
+    };
     for (int it = 1; it <= cap; ++it) {
         if (!rt.open) {
             rt.start(s);
             run_len = 0;
         }
         hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.fsign.p, w.sumz.p, za, zb,
-                           mu, inv1mu);
+                           mu, inv1mu, mu_relax);
         HG_CHECK_HIP(hipGetLastError());
         ++run_len;
         r.iters = it;
-        const bool want = !fixed ? ((it % check) == 0 || it == cap) : (it == cap);
-        if (want) {
+        std::swap(za, zb);   // za is now the current state, zb the previous
+        const bool want = (it % check) == 0 || it == cap;
+        if (!fixed && want) {
             r.kernel_ms += rt.stop(s);
             r.timed_launches += run_len;
-            hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, w.sumz.p, za, zb, mu,
-                               inv1mu, w.partial.p);
-            double a, b;
-            reduce_pair(m, gf, s, a, b);
-            r.rp = sqrt(a);
-            r.rd = sqrt(b);
-            if (!fixed && r.rp <= scale && r.rd <= scale * o.mu) {
+            bool done;
+            if (monitor) {
+                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, w.sumz.p, za,
+                                   inv1mu, w.xe.p);
+                double delta, dmax;
+                dist_change(m, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax);
+                done = stop.update(delta, dmax, o.tol_admm);
+            } else {
+                residuals(zb, za);
+                done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;
+            }
+            if (done) {
                 r.converged = true;
-                std::swap(za, zb);
                 break;
             }
         }
-        std::swap(za, zb);
     }
-    // normalise the reported residuals to the stopping scale: rms / hbar
-    r.rp = r.rp / (sqrt(3.0 * (double)nf) * m.hbar);
-    r.rd = r.rd / (sqrt(3.0 * (double)nf) * m.hbar * o.mu);
+    if (rt.open) {
+        r.kernel_ms += rt.stop(s);
+        r.timed_launches += run_len;
+    }
     if (fixed) r.converged = true;
+    if (r.iters > 0) residuals(zb, za);
     hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, w.sumz.p, za, inv1mu, w.xe.p);
     HG_CHECK_HIP(hipGetLastError());
     if (za != w.z0.p)
@@ -354,7 +372,7 @@ __global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* _
                                                        const double* __restrict__ farea,
                                                        const float* __restrict__ h, const float* __restrict__ gin,
                                                        const float* __restrict__ zin, float* __restrict__ gout,
-                                                       float* __restrict__ zout, float mu) {
+                                                       float* __restrict__ zout, float mu, float relax) {
     int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     const float g0 = gin[3 * f], g1 = gin[3 * f + 1], g2 = gin[3 * f + 2];
@@ -376,10 +394,10 @@ __global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* _
         float An = (float)farea[nb];
         float sdot = e0 * (qn0 - qo0) + e1 * (qn1 - qo1) + e2 * (qn2 - qo2);
         float c = An / (Af + An) * sdot;
-        // y_own = q_own + A_nb/(A_own + A_nb) e (e.(q_nb - q_own)); z' = y + z - g
-        float z0n = qo0 + c * e0 + zo[0] - g0;
-        float z1n = qo1 + c * e1 + zo[1] - g1;
-        float z2n = qo2 + c * e2 + zo[2] - g2;
+        // y_own = q_own + A_nb/(A_own + A_nb) e (e.(q_nb - q_own)); z' = z + alpha (y - g)
+        float z0n = zo[0] + relax * (qo0 + c * e0 - g0);
+        float z1n = zo[1] + relax * (qo1 + c * e1 - g1);
+        float z2n = zo[2] + relax * (qo2 + c * e2 - g2);
         float* zw = zout + 3 * (2 * e + side);
         zw[0] = z0n;
         zw[1] = z1n;
@@ -395,10 +413,11 @@ __global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* _
     gout[3 * f + 2] = (2.f * h[3 * f + 2] + mu * acc2) * den;
 }
 
-// Per copy k of face i: r_p = alpha (y' - g') = alpha ((z' - g') - (z - g)),
-// r_d = mu A_i (g' - g).  partial = (sum |r_p|^2, sum |r_d|^2).
+// Per copy k of face i: r_p = sqrt(A_i) (y' - g') with y' = g + (z' - z)/alpha
+// (from the z update), r_d = mu A_i (g' - g).
+// partial = (sum |r_p|^2, sum |r_d|^2).
 __global__ void k_resid_face(int nf, const uint32_t* fslot, const double* farea, const float* ga, const float* gb,
-                             const float* za, const float* zb, float mu, double* partial) {
+                             const float* za, const float* zb, float mu, float relax, double* partial) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     double rp = 0.0, rd = 0.0;
     if (f < nf) {
@@ -409,7 +428,8 @@ __global__ void k_resid_face(int nf, const uint32_t* fslot, const double* farea,
             if (slot_bnd(sl)) continue;
             int c = 2 * slot_edge(sl) + slot_side(sl);
             for (int d = 0; d < 3; ++d) {
-                double p = al * (((double)zb[3 * c + d] - gb[3 * f + d]) - ((double)za[3 * c + d] - ga[3 * f + d]));
+                double yn = (double)ga[3 * f + d] + ((double)zb[3 * c + d] - (double)za[3 * c + d]) / relax;
+                double p = al * (yn - (double)gb[3 * f + d]);
                 double q = (double)mu * A * ((double)gb[3 * f + d] - ga[3 * f + d]);
                 rp += p * p;
                 rd += q * q;
@@ -438,7 +458,18 @@ __global__ void k_normM(int nf, const uint32_t* fslot, const double* farea, doub
     }
 }
 
-AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s) {
+static void face_residuals(Mesh& m, int gf, const float* gprev, const float* gcur, const float* zprev,
+                           const float* zcur, float mu, double relax, double normM, hipStream_t s, AdmmResult& r) {
+    hipLaunchKernelGGL(k_resid_face, dim3(gf), dim3(kBlockA), 0, s, (int)m.nf, m.fslot.p, m.farea.p, gprev, gcur, zprev,
+                       zcur, mu, (float)relax, m.w.partial.p);
+    HG_CHECK_HIP(hipGetLastError());
+    double a, b;
+    reduce_pair(m, gf, s, a, b);
+    r.rp = sqrt(a) / normM;
+    r.rd = sqrt(b) / normM;
+}
+
+AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth) {
     const int nf = (int)m.nf, ne = (int)m.ne;
     auto& w = m.w;
     w.g0.alloc((size_t)3 * nf);
@@ -458,45 +489,53 @@ AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s) {
     const double normM = sqrt(nm2);
     AdmmResult r;
     const bool fixed = iters > 0;
+    const bool monitor = !fixed && depth >= 0;
     const int cap = fixed ? iters : o.max_admm;
-    const int check = std::max(1, o.check_every);
+    const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
     float *ga = w.g0.p, *gb = w.g1.p, *za = w.z0.p, *zb = w.z1.p;
     // algorithmic bytes of one iteration: per face g, h, fslot, area read and
     // g written; per edge ef, unit vector and both z copies read, z written
     r.bytes_per_iter = (uint64_t)56 * nf + (uint64_t)68 * ne;
     RunTimer rt;
     int run_len = 0;
+    DistStop stop;
     for (int it = 1; it <= cap; ++it) {
         if (!rt.open) {
             rt.start(s);
             run_len = 0;
         }
         hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.ef.p, m.ebar.p, m.farea.p,
-                           w.h.p, ga, za, gb, zb, mu);
+                           w.h.p, ga, za, gb, zb, mu, (float)o.relax);
         HG_CHECK_HIP(hipGetLastError());
         ++run_len;
         r.iters = it;
-        const bool want = !fixed ? ((it % check) == 0 || it == cap) : (it == cap);
-        if (want) {
+        std::swap(ga, gb);   // (ga, za) is now the current state, (gb, zb) the previous
+        std::swap(za, zb);
+        const bool want = (it % check) == 0 || it == cap;
+        if (!fixed && want) {
             r.kernel_ms += rt.stop(s);
             r.timed_launches += run_len;
-            hipLaunchKernelGGL(k_resid_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.farea.p, ga, gb, za, zb,
-                               mu, w.partial.p);
-            double a, b;
-            reduce_pair(m, gf, s, a, b);
-            r.rp = sqrt(a) / normM;
-            r.rd = sqrt(b) / normM;
-            if (!fixed && r.rp <= o.tol_admm && r.rd <= o.tol_admm) {
+            bool done;
+            if (monitor) {
+                double delta, dmax;
+                dist_change(m, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax);
+                done = stop.update(delta, dmax, o.tol_admm);
+            } else {
+                face_residuals(m, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
+                done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;
+            }
+            if (done) {
                 r.converged = true;
-                std::swap(ga, gb);
-                std::swap(za, zb);
                 break;
             }
         }
-        std::swap(ga, gb);
-        std::swap(za, zb);
+    }
+    if (rt.open) {
+        r.kernel_ms += rt.stop(s);
+        r.timed_launches += run_len;
     }
     if (fixed) r.converged = true;
+    if (r.iters > 0) face_residuals(m, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
     HG_CHECK_HIP(hipMemcpyAsync(w.gf.p, ga, (size_t)3 * nf * sizeof(float), hipMemcpyDeviceToDevice, s));
     return r;
 }

@@ -14,6 +14,9 @@
 // steps.  Sums are carried as FP32 double-float pairs (hi, lo) with
 // error-free two-sum, i.e. compensated summation; each edge change is formed
 // in FP64 from FP32 gradients and FP64 positions and split into (hi, lo).
+//
+// The same integration also serves as the ADMM stopping monitor: the change
+// of the whole distance field between two checks (see dist_change).
 #include <cmath>
 
 #include "hgeo_internal.h"
@@ -95,24 +98,21 @@ __global__ void k_int_jump(int nv, const float* shi, const float* slo, const int
     jp2[j] = jp[p];
 }
 
+// d = s (the partner chain ends at a source, where d = 0); +inf if unreached
 __global__ void k_int_out(int nv, const int32_t* perm_v, const int32_t* jp, const float* shi, const float* slo,
                           float* d_user) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nv) return;
-    float d;
-    if (jp[j] < 0) {
-        d = INFINITY;
-    } else {
-        int p = jp[j];
-        // s[j] holds the sum up to p (a source, d = 0); add p's own (zero) term
-        float h, l;
-        df_add(shi[j], slo[j], p == j ? 0.f : shi[p], p == j ? 0.f : slo[p], h, l);
-        d = h + l;
-    }
-    d_user[perm_v[j]] = d;
+    d_user[perm_v[j]] = jp[j] < 0 ? INFINITY : shi[j] + slo[j];
 }
 
-void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s) {
+struct IntSums {
+    float* hi;
+    float* lo;
+    int32_t* jp;
+};
+
+static IntSums integrate_sums(Mesh& m, int form, int depth, const float* xe, const float* g, hipStream_t s) {
     const int nv = (int)m.nv;
     auto& w = m.w;
     w.shi0.alloc(nv);
@@ -123,8 +123,7 @@ void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s) {
     w.jp1.alloc(nv);
     const int grid = grid_for(nv, kBlockI);
     hipLaunchKernelGGL(k_int_step, dim3(grid), dim3(kBlockI), 0, s, nv, form, w.level.p, w.parent.p, w.pslot.p,
-                       m.csr_edge.p, m.ev.p, m.ef.p, w.xe.p, w.gf.p, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p,
-                       w.jp0.p);
+                       m.csr_edge.p, m.ev.p, m.ef.p, xe, g, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p, w.jp0.p);
     HG_CHECK_HIP(hipGetLastError());
     // after r rounds every vertex sums 2^r chain edges; sources stop the walk
     int rounds = 0;
@@ -138,8 +137,80 @@ void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s) {
         std::swap(la, lb);
         std::swap(pa, pb);
     }
-    hipLaunchKernelGGL(k_int_out, dim3(grid), dim3(kBlockI), 0, s, nv, m.perm_v.p, pa, ha, la, d_user);
+    return IntSums{ha, la, pa};
+}
+
+void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s) {
+    IntSums r = integrate_sums(m, form, depth, m.w.xe.p, m.w.gf.p, s);
+    hipLaunchKernelGGL(k_int_out, dim3(grid_for(m.nv, kBlockI)), dim3(kBlockI), 0, s, (int)m.nv, m.perm_v.p, r.jp,
+                       r.hi, r.lo, d_user);
     HG_CHECK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- distance monitor
+__device__ inline double blk_max2(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = fmax(r, sh[i]);
+    return r;
+}
+
+// partial[2b] = max |d - dprev|, partial[2b+1] = max |d| over reached
+// vertices of block b; dprev <- d.
+__global__ void k_dist_delta(int nv, const int32_t* jp, const float* shi, const float* slo, float* dprev,
+                             int first, double* partial) {
+    __shared__ double sh[kBlockI / 64];
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double dl = 0.0, mx = 0.0;
+    if (j < nv && jp[j] >= 0) {
+        float d = shi[j] + slo[j];
+        dl = first ? INFINITY : fabs((double)d - (double)dprev[j]);
+        mx = fabs((double)d);
+        dprev[j] = d;
+    }
+    dl = blk_max2(dl, sh);
+    mx = blk_max2(mx, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = dl;
+        partial[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+__global__ void k_reduce_pairs_max(double* partial, int n) {
+    __shared__ double sh[kBlockI / 64];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a = fmax(a, partial[2 * i]);
+        b = fmax(b, partial[2 * i + 1]);
+    }
+    a = blk_max2(a, sh);
+    b = blk_max2(b, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * n] = a;
+        partial[2 * n + 1] = b;
+    }
+}
+
+void dist_change(Mesh& m, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
+                 double& delta, double& dmax) {
+    const int nv = (int)m.nv;
+    auto& w = m.w;
+    w.dprev.alloc(nv);
+    const int grid = grid_for(nv, kBlockI);
+    if ((int)w.partial.n < 2 * grid + 8) w.partial.alloc((size_t)2 * grid + 8);
+    IntSums r = integrate_sums(m, form, depth, xe, g, s);
+    hipLaunchKernelGGL(k_dist_delta, dim3(grid), dim3(kBlockI), 0, s, nv, r.jp, r.hi, r.lo, w.dprev.p,
+                       first ? 1 : 0, w.partial.p);
+    hipLaunchKernelGGL(k_reduce_pairs_max, dim3(1), dim3(kBlockI), 0, s, w.partial.p, grid);
+    HG_CHECK_HIP(hipGetLastError());
+    HG_CHECK_HIP(hipMemcpyAsync(w.pinned, w.partial.p + 2 * grid, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HG_CHECK_HIP(hipStreamSynchronize(s));
+    delta = w.pinned[0];
+    dmax = w.pinned[1];
 }
 
 }  // namespace hg

@@ -113,25 +113,30 @@ def test_normalize(case):
     assert np.abs(h - rf.h).max() < 2e-6
 
 
+PARAMS = [(100.0, 1.0), (30.0, 1.8)]   # the paper's (mu, alpha) and the defaults
+
+
+@pytest.mark.parametrize("mu, relax", PARAMS)
 @pytest.mark.parametrize("k", [1, 7, 40])
-def test_edge_admm_k_iterations(case, k):
+def test_edge_admm_k_iterations(case, hg, k, mu, relax):
     name, v, f, src, mesh, rf, re_ = case
-    _say(name, "admm_edge", k)
+    _say(name, "admm_edge", k, mu, relax)
     h32 = re_.h.astype(np.float32)
-    x, info = mesh.admm_edge(torch.from_numpy(h32).cuda(), iters=k)
+    x, info = mesh.admm_edge(torch.from_numpy(h32).cuda(), iters=k, opts=hg.default_opts(mu=mu, relax=relax))
     Z = ograd.edge_targets(v, re_.topo, h32.astype(np.float64))
-    ref = oadmm.EdgeADMM(re_.topo, Z).run(k)
+    ref = oadmm.EdgeADMM(re_.topo, Z, mu, relax).run(k)
     assert info.admm_iters == k
     assert np.abs(x.cpu().numpy() - ref.x).max() < 2e-4 * rf.hbar
 
 
+@pytest.mark.parametrize("mu, relax", PARAMS)
 @pytest.mark.parametrize("k", [1, 7, 40])
-def test_face_admm_k_iterations(case, k):
+def test_face_admm_k_iterations(case, hg, k, mu, relax):
     name, v, f, src, mesh, rf, _ = case
-    _say(name, "admm_face", k)
+    _say(name, "admm_face", k, mu, relax)
     h32 = rf.h.astype(np.float32)
-    g, info = mesh.admm_face(torch.from_numpy(h32).cuda(), iters=k)
-    ref = oadmm.FaceADMM(v, f, rf.topo, h32.astype(np.float64)).run(k)
+    g, info = mesh.admm_face(torch.from_numpy(h32).cuda(), iters=k, opts=hg.default_opts(mu=mu, relax=relax))
+    ref = oadmm.FaceADMM(v, f, rf.topo, h32.astype(np.float64), mu, relax).run(k)
     assert np.abs(g.cpu().numpy() - ref.g).max() < 2e-4
 
 
@@ -150,12 +155,13 @@ def test_integration(case):
     assert np.abs(d - ref).max() < 1e-6 * diam
 
 
+@pytest.mark.parametrize("mu, relax", PARAMS)
 @pytest.mark.parametrize("form", ["edge", "face"])
-def test_solve_end_to_end(case, hg, form):
+def test_solve_end_to_end(case, hg, form, mu, relax):
     name, v, f, src, mesh, rf, re_ = case
-    _say(name, "solve", form)
+    _say(name, "solve", form, mu, relax)
     ref = re_ if form == "edge" else rf
-    d, info = mesh.solve(src, 0.0, hg.default_opts(formulation=form))
+    d, info = mesh.solve(src, 0.0, hg.default_opts(formulation=form, mu=mu, relax=relax))
     mean, mx = metrics.parity(d.cpu().numpy(), ref.d)
     _say(name, form, "sweeps", info.sweeps, "admm", info.admm_iters, "mean", mean, "max", mx)
     assert info.converged_u and info.converged_admm

@@ -305,19 +305,21 @@ def test_admm_fixed_point_on_integrable_field():
     assert np.abs(es.x - (ell[topo.edges[:, 1]] - ell[topo.edges[:, 0]])).max() < 1e-13
 
 
-def test_converged_admm_integrates_to_poisson(bumpy3):
+@pytest.mark.parametrize("mu, alpha", [(100.0, 1.0), (30.0, 1.8)])
+def test_converged_admm_integrates_to_poisson(bumpy3, mu, alpha):
     """Face and edge ADMM run to convergence, integrated in breadth-first
-    order, reproduce the face and edge Poisson distances."""
+    order, reproduce the face and edge Poisson distances (with and without
+    over-relaxation: same fixed point)."""
     v, f = bumpy3
     src = [23]
     for form in ("face", "edge"):
         r = pipeline.heat_method(v, f, src, form=form)
         if form == "face":
-            st = admm.FaceADMM(v, f, r.topo, r.h).run(6000, 1e-13, 1e-13)
+            st = admm.FaceADMM(v, f, r.topo, r.h, mu, alpha).run(6000, 1e-13, 1e-13)
             d = integrate.integrate_face(v, r.topo, st.g, r.level, r.parent, src)
         else:
             Z = gradient.edge_targets(v, r.topo, r.h)
-            st = admm.EdgeADMM(r.topo, Z).run(6000, 1e-13)
+            st = admm.EdgeADMM(r.topo, Z, mu, alpha).run(6000, 1e-13)
             d = integrate.integrate_edge(r.topo, st.x, r.level, r.parent, src)
         mean, mx = metrics.parity(d, r.d)
         assert mx < 1e-8, (form, mean, mx)
