@@ -50,6 +50,23 @@ def _mesh(level: int, cache_dir: str | None):
     return v, f, s
 
 
+def _measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    record (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a
+    1 GiB copy), or None when the kernel's source changed since then."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["src"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["src_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(sample_level: int, full_nv: int):
     """The oracle (FP64 heat method, edge-form Poisson) on a smaller mesh of
     the same family; solves/s scaled to the full vertex count linearly (a
@@ -77,6 +94,8 @@ def main():
     ap.add_argument("--cache", default=os.environ.get("HGEO_MESH_CACHE", "/tmp/hgeo_mesh_cache"))
     ap.add_argument("--cpu-sample-level", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run 5 device-to-device copies of 1 GiB (scale for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solve is a single-GPU kernel pipeline "
@@ -87,6 +106,15 @@ def main():
     import paper_1812_06060_amd as hg
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    if args.copy_calib:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 5}))
+        return
 
     t0 = time.perf_counter()
     v, f, src = _mesh(args.level, args.cache)
@@ -131,6 +159,8 @@ def main():
         kms = float(np.mean([i.ms_admm_kernel for i in infos]))
         kbytes = infos[-1].bytes_admm_kernel
     achieved = kbytes / (kms * 1e-3) / 1e9
+    kname = "k_patch_pass" if name == "diffusion pass" else ("k_admm_edge" if args.form == "edge" else "k_admm_face")
+    traffic = _measured_traffic(kname)
     last = infos[-1]
     result = {
         "metric": METRIC,
@@ -154,7 +184,7 @@ def main():
                                 "integrate": last.ms_integrate},
                    "mesh_create_s": t_create},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_kernel_ms": kms, "alg_bytes_per_launch": int(kbytes)},
         "alg_hbm_gbs_whole_solve": last.bytes_alg / (last.ms_total * 1e-3) / 1e9,
     }
