@@ -38,7 +38,7 @@ converges faster.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 
@@ -82,10 +82,21 @@ class FaceADMMState:
     iters: int = 0
     r_primal: float = np.inf
     r_dual: float = np.inf
+    kappa: list = field(default_factory=list)   # per source path (Eq. 24)
 
 
 class FaceADMM:
-    def __init__(self, verts, tris, topo, h, mu: float = 100.0, relax: float = 1.0):
+    """Face-form ADMM.  `paths` (from :func:`source_paths`) adds the
+    constraint of Eq. 24 for each path S: a group of copies y_j of the
+    gradient of the face f_j chosen on each path edge, weighted by
+    alpha = sqrt(A_{f_j}) like every copy, constrained to
+    sum_j e_j . y_j = 0 (e_j the edge vector along the path).  Its Y-type
+    update is the weighted projection
+    y_j = q_j - (c / A_j) e_j,  c = sum_j e_j . q_j / sum_j |e_j|^2 / A_j,
+    q_j = g_{f_j} - kappa_j / (mu alpha_j); the G-update of a face counts
+    these copies among Y(i), and kappa_j += mu alpha_j (y_j - g_{f_j})."""
+
+    def __init__(self, verts, tris, topo, h, mu: float = 100.0, relax: float = 1.0, paths=()):
         self.mu = mu
         self.relax = relax
         area, _, _ = face_geometry(verts, tris)
@@ -97,12 +108,16 @@ class FaceADMM:
         self.alpha = np.sqrt(self.A)
         self.h = np.asarray(h, dtype=np.float64)
         self.nf = tris.shape[0]
-        self.count = np.bincount(self.faces, minlength=self.nf).astype(np.float64)
+        self.paths = [(p["face"], p["vec"], area[p["face"]]) for p in paths]
+        pf = np.concatenate([f for f, _, _ in self.paths]) if self.paths else np.zeros(0, dtype=np.int64)
+        self.count = (np.bincount(self.faces, minlength=self.nf)
+                      + np.bincount(pf, minlength=self.nf)).astype(np.float64)
         self.normM = np.sqrt(self.A.sum())
 
     def init(self) -> FaceADMMState:
         return FaceADMMState(g=self.h.copy(), y=self.h[self.faces].copy(),
-                             lam=np.zeros((self.faces.size, 3)))
+                             lam=np.zeros((self.faces.size, 3)),
+                             kappa=[np.zeros((f.size, 3)) for f, _, _ in self.paths])
 
     def step(self, s: FaceADMMState) -> FaceADMMState:
         mu, al, A = self.mu, self.alpha, self.A
@@ -114,11 +129,22 @@ class FaceADMM:
         tot = np.zeros((self.nf, 3))
         for c in range(3):
             tot[:, c] = np.bincount(self.faces, weights=acc[:, c], minlength=self.nf)
+        yhs = []
+        for (f, vec, Ap), kap in zip(self.paths, s.kappa):
+            ap = np.sqrt(Ap)
+            qp = s.g[f] - kap / (mu * ap)[:, None]
+            cc = np.sum(vec * qp) / np.sum(np.sum(vec * vec, axis=1) / Ap)
+            yp = qp - (cc / Ap)[:, None] * vec
+            yph = self.relax * yp + (1.0 - self.relax) * s.g[f]
+            np.add.at(tot, f, yph + kap / (mu * ap)[:, None])
+            yhs.append(yph)
         g = g_update(self.h, tot, self.count, mu)
         lam = s.lam + mu * al[:, None] * (yh - g[self.faces])
+        kappa = [kap + mu * np.sqrt(Ap)[:, None] * (yph - g[f])
+                 for (f, _, Ap), kap, yph in zip(self.paths, s.kappa, yhs)]
         r_p = np.linalg.norm(al[:, None] * (y - g[self.faces]))
         r_d = np.linalg.norm(mu * A[:, None] * (g - s.g)[self.faces])
-        return FaceADMMState(g=g, y=y, lam=lam, iters=s.iters + 1, r_primal=r_p, r_dual=r_d)
+        return FaceADMMState(g=g, y=y, lam=lam, iters=s.iters + 1, r_primal=r_p, r_dual=r_d, kappa=kappa)
 
     def run(self, iters: int, eps1: float = 0.0, eps2: float = 0.0, state=None):
         s = self.init() if state is None else state
@@ -138,10 +164,78 @@ class EdgeADMMState:
     iters: int = 0
     r_primal: float = np.inf
     r_dual: float = np.inf
+    kappa: list = field(default_factory=list)   # per source path (Eq. 25)
+
+
+def source_paths(verts, tris, topo, sources):
+    """Edge paths between sources for the constraints of Eqs. 24-25
+    (Sec. 5.2): from one source to each of the other sources, shortest in
+    edge count.  Read as: a breadth-first tree grown from the first source
+    alone (pairing rule of :mod:`oracle.bfs`, smallest-index neighbour one
+    set closer), the path to another source is its tree path; a source the
+    tree does not reach (another connected component) starts a new tree
+    from itself, the first such source in the list.  Duplicates are dropped.
+
+    Returns a list of paths, each a dict of arrays in path order (from the
+    tree's root towards the source):
+      edge  int64 edge ids, sign +1 where the path runs from the edge's
+      smaller to its larger vertex id (the orientation halfedge) else -1,
+      face  the face whose counter-clockwise boundary runs the edge in the
+            path's direction (the only face of a boundary edge) -- the face
+            whose gradient copy enters Eq. 24,
+      vec   the edge vector in the path's direction (FP64)."""
+    from .bfs import bfs_levels_vec
+    from .mesh import vertex_adjacency
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    row_ptr, col = vertex_adjacency(topo.nv, topo.edges)
+    key = topo.edges[:, 0] * topo.nv + topo.edges[:, 1]      # sorted: edges are unique-sorted
+    src = list(dict.fromkeys(int(s) for s in np.asarray(sources).reshape(-1)))
+    paths = []
+    todo = src
+    while len(todo) > 1:
+        root = todo[0]
+        level, parent = bfs_levels_vec(topo.nv, row_ptr, col, [root])
+        rest = []
+        for s in todo[1:]:
+            if level[s] < 0:
+                rest.append(s)
+                continue
+            steps = []
+            v = s
+            while parent[v] >= 0:
+                steps.append((int(parent[v]), v))
+                v = int(parent[v])
+            steps.reverse()
+            e = np.array([np.searchsorted(key, min(a, b) * topo.nv + max(a, b)) for a, b in steps], dtype=np.int64)
+            sign = np.array([1.0 if a < b else -1.0 for a, b in steps])
+            face = np.empty(len(steps), dtype=np.int64)
+            for k, (a, b) in enumerate(steps):
+                cand = [f for f in topo.edge_faces[e[k]] if f >= 0]
+                face[k] = cand[0]
+                for f in cand:
+                    t = tris[f]
+                    if any(t[i] == a and t[(i + 1) % 3] == b for i in range(3)):
+                        face[k] = f
+            vec = np.array([verts[b] - verts[a] for a, b in steps]).reshape(-1, 3)
+            paths.append({"edge": e, "sign": sign, "face": face, "vec": vec})
+        todo = rest
+    return paths
 
 
 class EdgeADMM:
-    def __init__(self, topo, Z, mu: float = 100.0, relax: float = 1.0):
+    """Edge-form ADMM.  `paths` (from :func:`source_paths`) adds the
+    constraint of Eq. 25 for each path S: one more group of copies
+    v_S = (x_e, e in S) constrained to s . v_S = 0 (s the path signs), with
+    its own duals kappa_S.  Its W-type update is the projection
+    v_S = (I - s s^T / |S|)(x_S - kappa_S / mu); the X-update of an edge on
+    n paths gains those copies,
+    x_e = (sum_faces (h_e + lambda + mu w) + sum_paths (kappa + mu v))
+          / (|H_e| (1 + mu) + mu n),
+    and kappa_S += mu (v_S - x_S).  With paths the iteration converges to
+    the integrable field with equal distance at every source."""
+
+    def __init__(self, topo, Z, mu: float = 100.0, relax: float = 1.0, paths=()):
         self.mu = mu
         self.relax = relax
         self.topo = topo
@@ -150,24 +244,37 @@ class EdgeADMM:
         self.fe = topo.face_edges                                    # [F, 3]
         self.ne = topo.ne
         self.nH = topo.edge_nfaces.astype(np.float64)
+        self.paths = [(p["edge"], p["sign"]) for p in paths]
+        self.npath = np.zeros(self.ne)
+        for e, _ in self.paths:
+            np.add.at(self.npath, e, 1.0)
 
     def _sum_to_edges(self, vals):
         return np.bincount(self.fe.reshape(-1), weights=vals.reshape(-1), minlength=self.ne)
 
     def init(self) -> EdgeADMMState:
         x = self._sum_to_edges(self.Z) / self.nH
-        return EdgeADMMState(x=x, w=self.Z.copy(), lam=np.zeros_like(self.Z))
+        return EdgeADMMState(x=x, w=self.Z.copy(), lam=np.zeros_like(self.Z),
+                             kappa=[np.zeros(e.size) for e, _ in self.paths])
 
     def step(self, s: EdgeADMMState) -> EdgeADMMState:
-        mu, q = self.mu, self.q
+        mu, q, a = self.mu, self.q, self.relax
         w = w_update(s.x[self.fe], s.lam, q, mu)
-        wh = self.relax * w + (1.0 - self.relax) * s.x[self.fe]
-        x = x_update(self._sum_to_edges(self.Z), self._sum_to_edges(s.lam),
-                     self._sum_to_edges(wh), self.nH, mu)
+        wh = a * w + (1.0 - a) * s.x[self.fe]
+        num = self._sum_to_edges(self.Z) + self._sum_to_edges(s.lam) + mu * self._sum_to_edges(wh)
+        vhs = []
+        for (e, sg), kap in zip(self.paths, s.kappa):
+            t = s.x[e] - kap / mu
+            v = t - (sg @ t) / e.size * sg
+            vh = a * v + (1.0 - a) * s.x[e]
+            np.add.at(num, e, kap + mu * vh)
+            vhs.append(vh)
+        x = num / (self.nH * (1.0 + mu) + mu * self.npath)
         lam = s.lam + mu * (wh - x[self.fe])
+        kappa = [kap + mu * (vh - x[e]) for (e, _), kap, vh in zip(self.paths, s.kappa, vhs)]
         r_p = np.linalg.norm(w - x[self.fe])
         r_d = np.linalg.norm(mu * (x - s.x)[self.fe])
-        return EdgeADMMState(x=x, w=w, lam=lam, iters=s.iters + 1, r_primal=r_p, r_dual=r_d)
+        return EdgeADMMState(x=x, w=w, lam=lam, iters=s.iters + 1, r_primal=r_p, r_dual=r_d, kappa=kappa)
 
     def run(self, iters: int, tol: float = 0.0, state=None):
         s = self.init() if state is None else state
