@@ -73,16 +73,24 @@ typedef struct {
     int32_t max_sweeps;     /* diffusion sweep cap; default 100000 */
     int32_t max_admm;       /* ADMM iteration cap; default 50000 */
     double mu;              /* ADMM penalty (the paper uses 100); default 0 =
-                               auto: max(30, depth/2) in hg_geodesic_solve
-                               (depth = breadth-first depth of the query),
-                               100 in the ADMM step entry points */
+                               auto: max(30, depth/2, 1.5 L) in
+                               hg_geodesic_solve (depth = breadth-first depth
+                               of the query, L = edges on the longest source
+                               path, 0 without path constraints), 100 in the
+                               ADMM step entry points */
     int32_t check_every;    /* iterations between convergence checks; 32 */
     int32_t diffusion_schedule; /* 0 = auto, 1 = global Jacobi sweeps,
                                    2 = LDS-tiled patch sweeps */
     int32_t inner_sweeps;   /* patch schedule: sweeps per global pass; 0 = auto */
     double relax;           /* ADMM over-relaxation alpha in (0, 2); default
                                1.8; 1 = the paper's iteration */
-    int32_t reserved[6];
+    int32_t source_paths;   /* several sources: 1 (default) adds the
+                               constraints of Eqs. 24-25 (Sec. 5.2) along a
+                               shortest edge path from the first source of
+                               each connected component to each other source
+                               in it, so that the optimised field gives every
+                               source the same distance; 0 = without them */
+    int32_t reserved[5];
 } hg_opts;
 
 /* Per-solve report. */
@@ -104,7 +112,9 @@ typedef struct {
        solve's stream, and the algorithmic HBM bytes one such launch moves */
     float ms_pass_kernel, ms_admm_kernel;
     uint64_t bytes_pass_kernel, bytes_admm_kernel;
-    int32_t reserved[8];
+    int32_t n_paths;        /* source paths constrained (Eqs. 24-25) */
+    int32_t path_edges;     /* total edges over those paths */
+    int32_t reserved[6];
 } hg_info;
 
 /* Mesh statistics. */
@@ -139,7 +149,10 @@ hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* stats);
 
 /*
  * Geodesic distance from a source set (Algorithm 1; several sources as in
- * Sec. 5.2: all in D_0, u_0 = 1 at each, distance 0 at each).
+ * Sec. 5.2: all in D_0, u_0 = 1 at each, distance 0 at each, and with
+ * opts->source_paths the path constraints of Eqs. 24-25 in the ADMM; the
+ * paths come from a breadth-first search grown from the first source of
+ * each component alone, which adds one search of that depth to the query).
  *   src, nsrc : HOST int32 source vertex ids, nsrc >= 1.
  *   t         : diffusion time; t <= 0 means m * hbar^2.
  *   opts      : NULL = defaults.
@@ -178,13 +191,18 @@ hg_status hg_normalize(hg_mesh_t mesh, const double* logu_dev, float* h_dev, voi
 
 /* Edge-form ADMM (Sec. 4.1) from DEVICE float32[nf*3] normalised field h:
  * x_dev = DEVICE float32[ne] edge differences after `iters` iterations
- * (iters <= 0: run to opts->tol_admm / max_admm). */
-hg_status hg_admm_edge(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts,
-                       float* x_dev, void* stream, hg_info* info);
+ * (iters <= 0: run to opts->tol_admm / max_admm).  src/nsrc: HOST source
+ * ids or NULL/0; with two or more distinct sources and opts->source_paths
+ * the constraints of Eq. 25 are added (paths as in hg_geodesic_solve). */
+hg_status hg_admm_edge(hg_mesh_t mesh, const float* h_dev, const int32_t* src, int32_t nsrc, int32_t iters,
+                       const hg_opts* opts, float* x_dev, void* stream, hg_info* info);
 
-/* Face-form ADMM (Sec. 3.2): g_dev = DEVICE float32[nf*3] gradients. */
-hg_status hg_admm_face(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts,
-                       float* g_dev, void* stream, hg_info* info);
+/* Face-form ADMM (Sec. 3.2): g_dev = DEVICE float32[nf*3] gradients; with
+ * sources as above, the constraints of Eq. 24 on the gradient of the face
+ * whose counter-clockwise boundary runs each path edge in the path's
+ * direction (the only face of a boundary edge). */
+hg_status hg_admm_face(hg_mesh_t mesh, const float* h_dev, const int32_t* src, int32_t nsrc, int32_t iters,
+                       const hg_opts* opts, float* g_dev, void* stream, hg_info* info);
 
 /* Integration along the breadth-first pairing (Sec. 3.3 / Sec. 4) of edge
  * differences x_dev (float32[ne]) or face gradients g_dev (float32[nf*3]),

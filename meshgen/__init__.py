@@ -206,6 +206,20 @@ def random_sources(nv: int, k: int, seed: int):
     return rng.choice(nv, size=k, replace=False).astype(np.int32)
 
 
+def disjoint_union(parts, shift=3.0):
+    """Several meshes side by side as one mesh with several connected
+    components (each part moved by shift * index along x).  Returns
+    (verts, tris, first vertex id of each part)."""
+    vs, fs, starts = [], [], []
+    n = 0
+    for i, (v, f) in enumerate(parts):
+        vs.append(np.asarray(v, dtype=np.float64) + [shift * i, 0.0, 0.0])
+        fs.append(np.asarray(f, dtype=np.int32) + n)
+        starts.append(n)
+        n += v.shape[0]
+    return np.vstack(vs), np.vstack(fs).astype(np.int32), starts
+
+
 # --------------------------------------------------------------------------
 # the named workloads
 # --------------------------------------------------------------------------

@@ -37,7 +37,8 @@ class Opts(C.Structure):
         ("formulation", C.c_int32), ("m", C.c_double), ("tol_u", C.c_double),
         ("tol_admm", C.c_double), ("max_sweeps", C.c_int32), ("max_admm", C.c_int32),
         ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
-        ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("reserved", C.c_int32 * 6),
+        ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("source_paths", C.c_int32),
+        ("reserved", C.c_int32 * 5),
     ]
 
 
@@ -52,7 +53,7 @@ class Info(C.Structure):
         ("converged_u", C.c_int32), ("converged_admm", C.c_int32),
         ("ms_pass_kernel", C.c_float), ("ms_admm_kernel", C.c_float),
         ("bytes_pass_kernel", C.c_uint64), ("bytes_admm_kernel", C.c_uint64),
-        ("reserved", C.c_int32 * 8),
+        ("n_paths", C.c_int32), ("path_edges", C.c_int32), ("reserved", C.c_int32 * 6),
     ]
 
     def as_dict(self):
@@ -78,8 +79,8 @@ _API = {
     "hg_bfs": [_P, _P, C.c_int32, _P, _P, _P, C.POINTER(C.c_int32)],
     "hg_diffuse": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
     "hg_normalize": [_P, _P, _P, _P],
-    "hg_admm_edge": [_P, _P, C.c_int32, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
-    "hg_admm_face": [_P, _P, C.c_int32, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_admm_edge": [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_admm_face": [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
     "hg_integrate_edge": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_integrate_face": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_mesh_edges": [_P, _P, _P],
@@ -256,21 +257,27 @@ class Mesh:
                                  _dptr(h, torch.float32, 3 * self.nf), _stream(stream)))
         return h
 
-    def admm_edge(self, h, iters: int = 0, opts: Opts | None = None, stream=None):
+    def admm_edge(self, h, iters: int = 0, opts: Opts | None = None, stream=None, sources=None):
+        """Edge-form ADMM; `sources` (two or more) adds the path constraints
+        of Eq. 25."""
         torch = _torch()
         x = torch.empty(self.ne, dtype=torch.float32, device="cuda")
         info = Info()
-        st = _lib.hg_admm_edge(self._h, _dptr(h, torch.float32, 3 * self.nf), int(iters),
+        a, p, n = _src_array(sources) if sources is not None else (None, None, 0)
+        st = _lib.hg_admm_edge(self._h, _dptr(h, torch.float32, 3 * self.nf), p, n, int(iters),
                                C.byref(opts) if opts else None, _dptr(x, torch.float32, self.ne),
                                _stream(stream), C.byref(info))
         _check(st)
         return x, SolveInfo(info.as_dict())
 
-    def admm_face(self, h, iters: int = 0, opts: Opts | None = None, stream=None):
+    def admm_face(self, h, iters: int = 0, opts: Opts | None = None, stream=None, sources=None):
+        """Face-form ADMM; `sources` (two or more) adds the path constraints
+        of Eq. 24."""
         torch = _torch()
         g = torch.empty((self.nf, 3), dtype=torch.float32, device="cuda")
         info = Info()
-        st = _lib.hg_admm_face(self._h, _dptr(h, torch.float32, 3 * self.nf), int(iters),
+        a, p, n = _src_array(sources) if sources is not None else (None, None, 0)
+        st = _lib.hg_admm_face(self._h, _dptr(h, torch.float32, 3 * self.nf), p, n, int(iters),
                                C.byref(opts) if opts else None, _dptr(g, torch.float32, 3 * self.nf),
                                _stream(stream), C.byref(info))
         _check(st)

@@ -22,6 +22,7 @@ SOURCES = [
     "kernels_admm.hip",
     "kernels_integrate.hip",
     "kernels_patch.hip",
+    "kernels_paths.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

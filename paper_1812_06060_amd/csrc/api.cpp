@@ -18,7 +18,12 @@ size_t Mesh::Work::bytes() const {
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
            h.bytes() + sumz.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
-           src.bytes();
+           src.bytes() + dprev.bytes() + paths.bytes();
+}
+
+size_t Mesh::Work::Paths::bytes() const {
+    return ptr.bytes() + edge.bytes() + face.bytes() + sign.bytes() + vec.bytes() + eg_ptr.bytes() + eg_id.bytes() +
+           eg_slot.bytes() + fg_ptr.bytes() + fg_id.bytes() + fg_slot.bytes() + z.bytes() + seff.bytes();
 }
 
 uint64_t Mesh::mesh_bytes() const {
@@ -73,6 +78,7 @@ static hg_opts resolve_opts(const hg_opts* o) {
         throw Error{HG_E_INVALID_ARG, "formulation must be HG_FORM_FACE or HG_FORM_EDGE"};
     if (!(r.mu >= 0.0) || !std::isfinite(r.mu)) throw Error{HG_E_INVALID_ARG, "mu must be >= 0 (0 = auto)"};
     if (!(r.relax > 0.0 && r.relax < 2.0)) throw Error{HG_E_INVALID_ARG, "relax must lie in (0, 2)"};
+    if (r.source_paths != 0 && r.source_paths != 1) throw Error{HG_E_INVALID_ARG, "source_paths must be 0 or 1"};
     if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
         throw Error{HG_E_INVALID_ARG, "iteration caps must be positive"};
     return r;
@@ -127,6 +133,7 @@ hg_status hg_opts_default(hg_opts* o) {
     o->check_every = 32;
     o->diffusion_schedule = 0;
     o->inner_sweeps = 0;
+    o->source_paths = 1;
     return HG_OK;
 }
 
@@ -270,17 +277,20 @@ hg_status hg_normalize(hg_mesh_t mesh, const double* logu_dev, float* h_dev, voi
     });
 }
 
-static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts, float* out,
-                            void* stream, hg_info* info, int form) {
+static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, const int32_t* src, int32_t nsrc, int32_t iters,
+                            const hg_opts* opts, float* out, void* stream, hg_info* info, int form) {
     return guarded([&]() -> hg_status {
         if (!mesh || !h_dev || !out) return fail(HG_E_INVALID_ARG, "null argument");
         auto* m = reinterpret_cast<Mesh*>(mesh);
         hipStream_t s = (hipStream_t)stream;
         hg_opts o = resolve_opts(opts);
         if (o.mu == 0.0) o.mu = 100.0;   // no breadth-first depth here: the paper's value
+        const bool paths = src && nsrc > 1 && o.source_paths;
+        if (paths) build_source_paths(*m, map_sources(*m, src, nsrc), s);
         m->w.h.alloc((size_t)3 * m->nf);
         gather_faces_to_internal(*m, h_dev, m->w.h.p, s);
-        AdmmResult r = form == HG_FORM_EDGE ? run_admm_edge(*m, iters, o, s) : run_admm_face(*m, iters, o, s);
+        AdmmResult r = form == HG_FORM_EDGE ? run_admm_edge(*m, iters, o, s, -1, paths)
+                                            : run_admm_face(*m, iters, o, s, -1, paths);
         if (form == HG_FORM_EDGE)
             scatter_edges_to_user(*m, m->w.xe.p, out, s);
         else
@@ -292,19 +302,21 @@ static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, int32_t iters, c
             info->res_primal = r.rp;
             info->res_dual = r.rd;
             info->converged_admm = r.converged;
+            info->n_paths = paths ? m->w.paths.np : 0;
+            info->path_edges = paths ? m->w.paths.ns : 0;
         }
         return r.converged ? HG_OK : fail(HG_E_NOT_CONVERGED, "ADMM iteration cap reached");
     });
 }
 
-hg_status hg_admm_edge(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts, float* x_dev,
-                       void* stream, hg_info* info) {
-    return admm_stage(mesh, h_dev, iters, opts, x_dev, stream, info, HG_FORM_EDGE);
+hg_status hg_admm_edge(hg_mesh_t mesh, const float* h_dev, const int32_t* src, int32_t nsrc, int32_t iters,
+                       const hg_opts* opts, float* x_dev, void* stream, hg_info* info) {
+    return admm_stage(mesh, h_dev, src, nsrc, iters, opts, x_dev, stream, info, HG_FORM_EDGE);
 }
 
-hg_status hg_admm_face(hg_mesh_t mesh, const float* h_dev, int32_t iters, const hg_opts* opts, float* g_dev,
-                       void* stream, hg_info* info) {
-    return admm_stage(mesh, h_dev, iters, opts, g_dev, stream, info, HG_FORM_FACE);
+hg_status hg_admm_face(hg_mesh_t mesh, const float* h_dev, const int32_t* src, int32_t nsrc, int32_t iters,
+                       const hg_opts* opts, float* g_dev, void* stream, hg_info* info) {
+    return admm_stage(mesh, h_dev, src, nsrc, iters, opts, g_dev, stream, info, HG_FORM_FACE);
 }
 
 static hg_status integrate_stage(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, const float* in, float* d_dev,
@@ -349,6 +361,8 @@ hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, do
         double tt = resolve_t(*m, t, o);
         StageTimer tm(s);
         tm.mark();
+        const bool paths = nsrc > 1 && o.source_paths;
+        if (paths) build_source_paths(*m, si, s);
         int depth = run_bfs(*m, si, s);
         tm.mark();
         DiffusionResult dr = run_diffusion(*m, si, tt, o, s);
@@ -356,12 +370,17 @@ hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, do
         run_normalize(*m, s);
         tm.mark();
         // ADMM penalty: the low-frequency error of these iterations decays
-        // fastest for mu of the order of the breadth-first depth (measured:
-        // best mu ~ 100 at depth 167, ~ 300 at depth 663); mu = 0 picks
-        // max(30, depth / 2)
-        if (o.mu == 0.0) o.mu = std::max(30.0, 0.5 * depth);
-        AdmmResult ar = o.formulation == HG_FORM_EDGE ? run_admm_edge(*m, 0, o, s, depth)
-                                                      : run_admm_face(*m, 0, o, s, depth);
+        // fastest for mu of the order of the longest chain the field is
+        // integrated along (measured, one source: best mu ~ 100 at depth 167,
+        // ~ 300 at depth 663; several sources with path constraints: best mu
+        // ~ 1 - 1.8 times the longest path's edge count); mu = 0 picks
+        // max(30, depth / 2, 1.5 * longest path)
+        if (o.mu == 0.0) {
+            o.mu = std::max(30.0, 0.5 * depth);
+            if (paths && m->w.paths.np > 0) o.mu = std::max(o.mu, 1.5 * m->w.paths.max_len);
+        }
+        AdmmResult ar = o.formulation == HG_FORM_EDGE ? run_admm_edge(*m, 0, o, s, depth, paths)
+                                                      : run_admm_face(*m, 0, o, s, depth, paths);
         tm.mark();
         integrate(*m, o.formulation, depth, d_dev, s);
         tm.mark();
@@ -390,6 +409,8 @@ hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, do
             info->bytes_pass_kernel = dr.bytes_per_pass;
             info->bytes_admm_kernel = ar.bytes_per_iter;
             info->bytes_alg = dr.bytes_per_pass * (uint64_t)dr.passes + ar.bytes_per_iter * (uint64_t)ar.iters;
+            info->n_paths = paths ? m->w.paths.np : 0;
+            info->path_edges = paths ? m->w.paths.ns : 0;
         }
         if (!dr.converged) return fail(HG_E_NOT_CONVERGED, "diffusion sweep cap reached");
         if (!ar.converged) return fail(HG_E_NOT_CONVERGED, "ADMM iteration cap reached");

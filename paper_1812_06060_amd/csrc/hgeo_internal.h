@@ -144,6 +144,19 @@ struct Mesh {
         DBuf<double> red_host_dummy;
         double* pinned = nullptr;           // host pinned reduction results
         DBuf<int32_t> src;
+        // source paths of the multi-source constraints (Eqs. 24-25), built by
+        // build_source_paths: np paths over ns slots, slots grouped by edge
+        // and by face (CSR over the distinct ids, slots in increasing order)
+        struct Paths {
+            int np = 0, ns = 0, ng_edge = 0, ng_face = 0;
+            int max_len = 0;                        // edges on the longest path
+            DBuf<int32_t> ptr, edge, face;
+            DBuf<float> sign, vec;                  // [ns], [3*ns]
+            DBuf<int32_t> eg_ptr, eg_id, eg_slot, fg_ptr, fg_id, fg_slot;
+            DBuf<float> z;                          // folded copies: [ns] edge form, [3*ns] face form
+            DBuf<float> seff;                       // edge form: [ne] effective target sums
+            size_t bytes() const;
+        } paths;
         size_t bytes() const;
     } w;
 
@@ -210,8 +223,15 @@ struct RunTimer {
 // iters > 0: exactly that many iterations.  Otherwise run to convergence:
 // with depth >= 0 (the breadth-first depth of the query) by the change of the
 // integrated distance field (DistStop), else by the paper's residuals.
-AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1);
-AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1);
+// With use_paths, the constraints of Eqs. 24-25 over m.w.paths are added.
+AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1,
+                         bool use_paths = false);
+AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1,
+                         bool use_paths = false);
+// Builds m.w.paths from the (internal) source list; runs breadth-first
+// searches from single sources, so it overwrites level/parent/pslot: run the
+// query's own breadth-first search after it.
+void build_source_paths(Mesh& m, const std::vector<int32_t>& src_internal, hipStream_t s);
 void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s);
 // integrates the given state (edge differences xe or face gradients g) and
 // returns max |d - d_prev| (inf on the first call) and max |d|; d_prev <- d
@@ -222,7 +242,9 @@ void dist_change(Mesh& m, int form, int depth, const float* xe, const float* g, 
 // between two checks and r = delta_k / delta_{k-1} < 1, the remaining change
 // of a geometrically converging iteration is at most delta_k r / (1 - r);
 // stop once that is <= tol * max|d|, or once delta_k itself is at the FP32
-// rounding floor (<= tol * max|d| / 20).
+// rounding floor (<= tol * max|d| / 100; the rounding noise of d is orders of
+// magnitude lower, and a slowly converging iteration -- time constant tau
+// iterations -- is only stopped early by this rule if tau >~ 64 * 100).
 struct DistStop {
     bool first = true;
     double prev = 0.0;
@@ -233,7 +255,7 @@ struct DistStop {
                 double r = delta / prev;
                 done = delta * r / (1.0 - r) <= tol * dmax;
             }
-            if (delta <= 0.05 * tol * dmax) done = true;
+            if (delta <= 0.01 * tol * dmax) done = true;
         }
         first = false;
         prev = delta;

@@ -251,6 +251,156 @@ __global__ void k_edge_x(int ne, const uint32_t* dummy, const int32_t* ef, const
     x[e] = edge_x(sumz[e], z[2 * e], z[2 * e + 1], bnd, inv1mu);
 }
 
+// ------------------------------------------------- source paths (Eqs. 24-25)
+// Each path S of m.w.paths adds a group of copies with the constraint of
+// Eq. 25 (edge form) or Eq. 24 (face form); their duals are folded like the
+// face copies.  One iteration = the form's face kernel, then
+// k_path_*_proj (one block per path: the group's projection, from the same
+// state the face kernel read), then k_path_*_fix (one thread per edge or
+// face that carries path copies: completes the update the face kernel did
+// without them).
+//
+// Edge form.  Per path slot keep zeta_S = kappa + mu v_hat; with n_e path
+// slots on edge e the X-update becomes
+//   x_e = (S_e + sum_faces zeta + sum_slots zeta_S) / (|H_e| (1 + mu) + mu n_e).
+// The face kernel keeps its formula x_e = (S'_e + sum_faces zeta) / (|H_e| (1 + mu))
+// on an effective target sum S'_e = x_e |H_e| (1 + mu) - sum_faces zeta, which
+// the fix kernel writes for path edges (in FP64: both terms are ~mu^2 times
+// larger than their difference).  The projection of a path's copies is
+//   t = 2 x - zeta_S / mu,  v = t - (s.t / |S|) s,  zeta_S' = zeta_S + mu alpha (v - x).
+//
+// Face form.  Per path slot keep z_S = y_S + kappa / (mu alpha_f) for the face
+// f chosen on the slot's edge; q = 2 g_f - z_S, the weighted projection onto
+// sum_j e_j . y_j = 0 is y_j = q_j - (c / A_j) e_j with
+// c = sum_j e_j . q_j / sum_j |e_j|^2 / A_j, z_S' = z_S + alpha (y - g_f), and the
+// fix kernel redoes the G-update of a face with its path copies included.
+constexpr int kBlockPath = 1024;
+
+__device__ inline double block_sum_all(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    return r;
+}
+
+__global__ void k_path_edge_zinit(int ns, const int32_t* edge, const int32_t* ef, const float* sumz, float mu,
+                                  float* zp) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns) return;
+    int e = edge[k];
+    float nh = ef[2 * e + 1] >= 0 ? 2.f : 1.f;
+    zp[k] = mu * (sumz[e] / nh);   // kappa = 0, v = x = mean target
+}
+
+__global__ void __launch_bounds__(kBlockPath) k_path_edge_proj(const int32_t* __restrict__ ptr,
+                                                               const int32_t* __restrict__ edge,
+                                                               const float* __restrict__ sign,
+                                                               const int32_t* __restrict__ ef,
+                                                               const float* __restrict__ seff,
+                                                               const float* __restrict__ zin, float* zp, float mu,
+                                                               float inv1mu, float mu_relax) {
+    __shared__ double sh[kBlockPath / 64];
+    const int b = ptr[blockIdx.x], n = ptr[blockIdx.x + 1] - b;
+    double acc = 0.0;
+    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
+        int e = edge[k];
+        float x = edge_x(seff[e], zin[2 * e], zin[2 * e + 1], ef[2 * e + 1] < 0, inv1mu);
+        acc += (double)sign[k] * (double)(2.f * x - zp[k] / mu);
+    }
+    const float c = (float)(block_sum_all(acc, sh) / n);
+    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
+        int e = edge[k];
+        float x = edge_x(seff[e], zin[2 * e], zin[2 * e + 1], ef[2 * e + 1] < 0, inv1mu);
+        float t = 2.f * x - zp[k] / mu;
+        float v = t - c * sign[k];
+        zp[k] = zp[k] + mu_relax * (v - x);
+    }
+}
+
+__global__ void k_path_edge_fix(int ng, const int32_t* gptr, const int32_t* gid, const int32_t* gslot,
+                                const float* zp, const float* sumz, const float* zout, const int32_t* ef, double mu,
+                                float* seff) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int e = gid[g];
+    double P = 0.0;
+    for (int j = gptr[g]; j < gptr[g + 1]; ++j) P += zp[gslot[j]];
+    const int n = gptr[g + 1] - gptr[g];
+    const bool bnd = ef[2 * e + 1] < 0;
+    const double Z = (double)zout[2 * e] + (bnd ? 0.0 : (double)zout[2 * e + 1]);
+    const double D0 = (bnd ? 1.0 : 2.0) * (1.0 + mu);
+    const double x = ((double)sumz[e] + P + Z) / (D0 + mu * n);
+    seff[e] = (float)(x * D0 - Z);
+}
+
+__global__ void k_path_face_zinit(int ns, const int32_t* face, const float* h, float* zp) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns) return;
+    int f = face[k];
+    for (int c = 0; c < 3; ++c) zp[3 * k + c] = h[3 * f + c];   // y = g = h, kappa = 0
+}
+
+__global__ void __launch_bounds__(kBlockPath) k_path_face_proj(const int32_t* __restrict__ ptr,
+                                                               const int32_t* __restrict__ face,
+                                                               const float* __restrict__ vec,
+                                                               const double* __restrict__ farea,
+                                                               const float* __restrict__ gin, float* zp, float relax) {
+    __shared__ double sh[kBlockPath / 64];
+    const int b = ptr[blockIdx.x], n = ptr[blockIdx.x + 1] - b;
+    double dot = 0.0, den = 0.0;
+    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
+        int f = face[k];
+        double ee = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double ec = vec[3 * k + c];
+            dot += ec * (double)(2.f * gin[3 * f + c] - zp[3 * k + c]);
+            ee += ec * ec;
+        }
+        den += ee / farea[f];
+    }
+    dot = block_sum_all(dot, sh);
+    den = block_sum_all(den, sh);
+    const double cc = dot / den;
+    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
+        int f = face[k];
+        const float ca = (float)(cc / farea[f]);
+        for (int c = 0; c < 3; ++c) {
+            float g = gin[3 * f + c];
+            float q = 2.f * g - zp[3 * k + c];
+            float y = q - ca * vec[3 * k + c];
+            zp[3 * k + c] = zp[3 * k + c] + relax * (y - g);
+        }
+    }
+}
+
+__global__ void k_path_face_fix(int ng, const int32_t* gptr, const int32_t* gid, const int32_t* gslot,
+                                const float* zp, const uint32_t* fslot, const float* zout, const float* h, float mu,
+                                float* gout) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int f = gid[g];
+    float acc[3] = {0.f, 0.f, 0.f};
+    int cnt = 0;
+    for (int k = 0; k < 3; ++k) {
+        uint32_t sl = fslot[3 * f + k];
+        if (slot_bnd(sl)) continue;
+        const float* z = zout + 3 * (2 * slot_edge(sl) + slot_side(sl));
+        for (int c = 0; c < 3; ++c) acc[c] += z[c];
+        ++cnt;
+    }
+    for (int j = gptr[g]; j < gptr[g + 1]; ++j) {
+        const float* z = zp + 3 * gslot[j];
+        for (int c = 0; c < 3; ++c) acc[c] += z[c];
+        ++cnt;
+    }
+    const float den = 1.f / (2.f + mu * (float)cnt);
+    for (int c = 0; c < 3; ++c) gout[3 * f + c] = (2.f * h[3 * f + c] + mu * acc[c]) * den;
+}
+
 static void reduce_pair(Mesh& m, int nblocks, hipStream_t s, double& a, double& b) {
     hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlockA), 0, s, m.w.partial.p, nblocks);
     HG_CHECK_HIP(hipGetLastError());
@@ -261,7 +411,7 @@ static void reduce_pair(Mesh& m, int nblocks, hipStream_t s, double& a, double& 
     b = m.w.pinned[1];
 }
 
-AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth) {
+AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
     const int nf = (int)m.nf, ne = (int)m.ne;
     auto& w = m.w;
     w.sumz.alloc(ne);
@@ -275,6 +425,18 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
                        w.h.p, w.sumz.p);
     hipLaunchKernelGGL(k_zeta_init, dim3(ge), dim3(kBlockA), 0, s, ne, m.ef.p, w.sumz.p, mu, w.z0.p);
     HG_CHECK_HIP(hipGetLastError());
+    auto& P = w.paths;
+    use_paths = use_paths && P.np > 0;
+    const float* S = w.sumz.p;   // target sums as the face kernel sees them
+    if (use_paths) {
+        P.z.alloc(P.ns);
+        P.seff.alloc(ne);
+        HG_CHECK_HIP(hipMemcpyAsync(P.seff.p, w.sumz.p, (size_t)ne * sizeof(float), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_path_edge_zinit, dim3(grid_for(P.ns, kBlockA)), dim3(kBlockA), 0, s, P.ns, P.edge.p,
+                           m.ef.p, w.sumz.p, mu, P.z.p);
+        HG_CHECK_HIP(hipGetLastError());
+        S = P.seff.p;
+    }
     AdmmResult r;
     const bool fixed = iters > 0;
     const bool monitor = !fixed && depth >= 0;
@@ -285,12 +447,15 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
     // algorithmic bytes of one iteration: fslot + sign per face, the zeta pair
     // and target sum per edge read once, one zeta written per face slot
     r.bytes_per_iter = (uint64_t)13 * nf + (uint64_t)12 * ne + (uint64_t)12 * nf;
+    // path kernels: per slot its edge, sign, copy (read + write), the edge's
+    // zeta pair, S' and ef; per group its slot list, copies, S, zeta pair, S'
+    if (use_paths) r.bytes_per_iter += (uint64_t)32 * P.ns + (uint64_t)8 * P.ns + (uint64_t)28 * P.ng_edge;
     RunTimer rt;
     int run_len = 0;
     DistStop stop;
     // residuals as rms over the 3|F| copies, r_p / hbar and r_d / (mu hbar)
     auto residuals = [&](const float* prev, const float* cur) {
-        hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, w.sumz.p, prev, cur, mu,
+        hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, S, prev, cur, mu,
                            inv1mu, mu_relax, w.partial.p);
         double a, b;
         reduce_pair(m, gf, s, a, b);
@@ -302,8 +467,14 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
             rt.start(s);
             run_len = 0;
         }
-        hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.fsign.p, w.sumz.p, za, zb,
-                           mu, inv1mu, mu_relax);
+        hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.fsign.p, S, za, zb, mu,
+                           inv1mu, mu_relax);
+        if (use_paths) {
+            hipLaunchKernelGGL(k_path_edge_proj, dim3(P.np), dim3(kBlockPath), 0, s, P.ptr.p, P.edge.p, P.sign.p,
+                               m.ef.p, S, za, P.z.p, mu, inv1mu, mu_relax);
+            hipLaunchKernelGGL(k_path_edge_fix, dim3(grid_for(P.ng_edge, kBlockA)), dim3(kBlockA), 0, s, P.ng_edge,
+                               P.eg_ptr.p, P.eg_id.p, P.eg_slot.p, P.z.p, w.sumz.p, zb, m.ef.p, (double)mu, P.seff.p);
+        }
         HG_CHECK_HIP(hipGetLastError());
         ++run_len;
         r.iters = it;
@@ -314,8 +485,8 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
             r.timed_launches += run_len;
             bool done;
             if (monitor) {
-                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, w.sumz.p, za,
-                                   inv1mu, w.xe.p);
+                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, S, za, inv1mu,
+                                   w.xe.p);
                 double delta, dmax;
                 dist_change(m, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax);
                 done = stop.update(delta, dmax, o.tol_admm);
@@ -335,7 +506,7 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
     }
     if (fixed) r.converged = true;
     if (r.iters > 0) residuals(zb, za);
-    hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, w.sumz.p, za, inv1mu, w.xe.p);
+    hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, S, za, inv1mu, w.xe.p);
     HG_CHECK_HIP(hipGetLastError());
     if (za != w.z0.p)
         HG_CHECK_HIP(hipMemcpyAsync(w.z0.p, za, (size_t)2 * ne * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -469,7 +640,7 @@ static void face_residuals(Mesh& m, int gf, const float* gprev, const float* gcu
     r.rd = sqrt(b) / normM;
 }
 
-AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth) {
+AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
     const int nf = (int)m.nf, ne = (int)m.ne;
     auto& w = m.w;
     w.g0.alloc((size_t)3 * nf);
@@ -482,6 +653,13 @@ AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
     const int gi = grid_for(std::max(nf, ne), kBlockA);
     if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
     hipLaunchKernelGGL(k_face_init, dim3(gi), dim3(kBlockA), 0, s, nf, ne, m.ef.p, w.h.p, w.g0.p, w.z0.p);
+    auto& P = w.paths;
+    use_paths = use_paths && P.np > 0;
+    if (use_paths) {
+        P.z.alloc((size_t)3 * P.ns);
+        hipLaunchKernelGGL(k_path_face_zinit, dim3(grid_for(P.ns, kBlockA)), dim3(kBlockA), 0, s, P.ns, P.face.p,
+                           w.h.p, P.z.p);
+    }
     hipLaunchKernelGGL(k_normM, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.farea.p, w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
     double nm2, dummy;
@@ -496,6 +674,9 @@ AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
     // algorithmic bytes of one iteration: per face g, h, fslot, area read and
     // g written; per edge ef, unit vector and both z copies read, z written
     r.bytes_per_iter = (uint64_t)56 * nf + (uint64_t)68 * ne;
+    // path kernels: per slot face, vector, area, g, copy (read + write); per
+    // group its slot list, the face's slots, z copies, path copies, h, g
+    if (use_paths) r.bytes_per_iter += (uint64_t)60 * P.ns + (uint64_t)16 * P.ns + (uint64_t)72 * P.ng_face;
     RunTimer rt;
     int run_len = 0;
     DistStop stop;
@@ -506,6 +687,12 @@ AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
         }
         hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.ef.p, m.ebar.p, m.farea.p,
                            w.h.p, ga, za, gb, zb, mu, (float)o.relax);
+        if (use_paths) {
+            hipLaunchKernelGGL(k_path_face_proj, dim3(P.np), dim3(kBlockPath), 0, s, P.ptr.p, P.face.p, P.vec.p,
+                               m.farea.p, ga, P.z.p, (float)o.relax);
+            hipLaunchKernelGGL(k_path_face_fix, dim3(grid_for(P.ng_face, kBlockA)), dim3(kBlockA), 0, s, P.ng_face,
+                               P.fg_ptr.p, P.fg_id.p, P.fg_slot.p, P.z.p, m.fslot.p, zb, w.h.p, mu, gb);
+        }
         HG_CHECK_HIP(hipGetLastError());
         ++run_len;
         r.iters = it;

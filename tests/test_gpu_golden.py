@@ -42,16 +42,7 @@ def hg():
     _meshes.clear()
 
 
-def _param(p):
-    name = os.path.basename(p)[:-4]
-    marks = []
-    if "multi" in name:
-        marks.append(pytest.mark.xfail(reason="several sources need the path constraints of Eqs. 24-25",
-                                       strict=False))
-    return pytest.param(p, id=name, marks=marks)
-
-
-@pytest.mark.parametrize("path", [_param(p) for p in GOLDEN])
+@pytest.mark.parametrize("path", GOLDEN, ids=[os.path.basename(p)[:-4] for p in GOLDEN])
 def test_full_size_parity(hg, path):
     g = np.load(path)
     name = os.path.basename(path)[:-4]
@@ -66,6 +57,6 @@ def test_full_size_parity(hg, path):
     ds = d.cpu().numpy()[g["idx"]].astype(np.float64)
     err = np.abs(ds - g["d"]) / float(g["diam"])
     print(f"[gpu-case] {name}: {dt * 1e3:.0f} ms sweeps={info.sweeps} passes={info.passes} "
-          f"admm={info.admm_iters} mean={err.mean():.2e} max={err.max():.2e}", flush=True)
+          f"admm={info.admm_iters} paths={info.n_paths} mean={err.mean():.2e} max={err.max():.2e}", flush=True)
     assert info.converged_u and info.converged_admm
     assert err.mean() <= 1e-4 and err.max() <= 1e-3
