@@ -20,9 +20,14 @@ value.  Principal submatrices of an M-matrix are M-matrices: their LU with
 diagonal pivots and the right-hand side above involve no cancellation, so
 each band is accurate componentwise and relatively.  Cutting the system B
 rings further out changes the band's values by a factor decaying like the
-Green's function over those rings (far below FP64 rounding for the B above;
-the pins check it against an independent 80-bit iteration).  One band (the
-whole mesh, no scaling) is the plain FP64 solve.  The result is log u.
+Green's function over those rings, provided nothing beyond the cut holds a
+larger u than the band -- which hop rings do not guarantee far from the
+sources (the hop count overestimates distance by up to 2/sqrt(3) depending
+on direction).  A refinement therefore re-solves with bands in the order of
+the values themselves, taken from the previous pass, until the result
+confirms its own windows (:func:`solve_log`); the pins check it against an
+independent 80-bit iteration and a deliberately poor first pass.  One band
+(the whole mesh, no scaling) is the plain FP64 solve.  The result is log u.
 
 Reference iteration (:func:`gauss_seidel_bfs`): the paper's breadth-first
 Gauss-Seidel of Eqs. 6-7 -- the vertex sets D_i are swept in order, all
@@ -62,19 +67,99 @@ def hop_levels(M: sp.spmatrix, sources) -> np.ndarray:
     return lev
 
 
-def solve_log(M: sp.csr_matrix, sources, band_rings: int | None = None,
-              margin_rings: int | None = None) -> np.ndarray:
-    """log u for M u = u_0 (u_0 = 1 at each source), marching outward over
-    bands of breadth-first rings.  Unreachable vertices get log u = -inf.
-    band_rings=None picks B = floor(300 / beta) (see the module text); the
-    margin defaults to B rings.  At t = m hbar^2 the truncation error falls by
-    about e^(-2 / sqrt(m)) per margin ring, so the default margin is ample for
-    m up to ~30."""
+def _solve_window(M, U, core, solved, out, u0):
+    """Solve the principal subsystem on the vertex set U (indices) with the
+    solved vertices as data and zero beyond U; write log u on U[core]."""
+    MU = M[U]
+    rows = MU.tocoo()
+    known = solved[rows.col]
+    scale = out[rows.col[known]].max() if known.any() else 0.0
+    rhs = np.zeros(U.size)
+    src_in = u0[U] > 0
+    if src_in.any():
+        rhs[src_in] = np.exp(-scale)
+    if known.any():
+        contrib = -rows.data[known] * np.exp(out[rows.col[known]] - scale)
+        rhs += np.bincount(rows.row[known], weights=contrib, minlength=U.size)
+    S = MU[:, U].tocsc()
+    lu = spla.splu(S, permc_spec="COLAMD", diag_pivot_thresh=0.0,
+                   options=dict(SymmetricMode=True))
+    w = lu.solve(rhs)
+    with np.errstate(divide="ignore"):
+        out[U[core]] = np.log(w[core]) + scale
+    solved[U[core]] = True
+
+
+def _ring_pass(M, sources, lev, B, G):
     nv = M.shape[0]
+    out = np.full(nv, -np.inf)
+    u0 = np.zeros(nv)
+    u0[sources] = 1.0
+    solved = np.zeros(nv, dtype=bool)
+    for lo in range(0, int(lev.max()) + 1, B):
+        U = np.flatnonzero((lev >= lo) & (lev < lo + B + G))
+        _solve_window(M, U, lev[U] < lo + B, solved, out, u0)
+    return out
+
+
+def _value_pass(M, sources, psi, delta, gamma, check):
+    """Bands by the estimate psi of log u: band = the unsolved vertices with
+    psi in [top - delta, top], window = those with psi >= top - delta - gamma.
+    Returns (log u, ok) with ok = every vertex left out of a band's window
+    ends at least `check` nats below that band's smallest value."""
+    nv = M.shape[0]
+    out = np.full(nv, -np.inf)
+    u0 = np.zeros(nv)
+    u0[sources] = 1.0
+    solved = np.zeros(nv, dtype=bool)
+    reach = np.isfinite(psi)
+    order = np.flatnonzero(reach)[np.argsort(-psi[reach], kind="stable")]
+    ps = psi[order]
+    bands = []
+    i = 0
+    while i < order.size:
+        top = ps[i]
+        j = i + int(np.searchsorted(-ps[i:], -(top - delta), side="right"))
+        k = i + int(np.searchsorted(-ps[i:], -(top - delta - gamma), side="right"))
+        U = order[i:k]
+        _solve_window(M, U, np.arange(U.size) < j - i, solved, out, u0)
+        bands.append((i, j, k))
+        i = j
+    # a-posteriori: vertices beyond window k of band (i, j) are order[k:]
+    tail_max = np.maximum.accumulate(out[order][::-1])[::-1] if order.size else np.zeros(0)
+    ok = True
+    for i, j, k in bands:
+        if k < order.size and tail_max[k] > out[order[i:j]].min() - check:
+            ok = False
+    return out, ok
+
+
+def solve_log(M: sp.csr_matrix, sources, band_rings: int | None = None,
+              margin_rings: int | None = None, refine: bool = True,
+              value_band: float = 100.0, value_margin: float = 60.0,
+              check_nats: float = 40.0, max_refine: int = 6) -> np.ndarray:
+    """log u for M u = u_0 (u_0 = 1 at each source).  Unreachable vertices
+    get log u = -inf.
+
+    First pass: bands of breadth-first rings.  band_rings=None picks
+    B = floor(300 / beta) (see the module text); the margin defaults to B
+    rings.  Hop rings are only a proxy for the decay of u: on a near
+    equilateral lattice the hop count overestimates the distance by up to
+    2/sqrt(3) depending on direction, so far from the sources a vertex
+    several dozen rings out can hold a larger u than some vertices of the
+    band, and cutting it off is then not negligible.
+
+    Refinement (refine=True): bands in value order instead -- sorted by the
+    previous pass's log u, each band spans value_band nats and its window
+    extends value_margin nats further down, so every cut-off vertex holds a
+    u e^-value_margin below the band's smallest by the previous estimate.
+    Passes repeat until the result confirms its own windows: every vertex
+    outside a band's window ends at least check_nats below the band's
+    smallest value (the cut then changes the band relatively by less than
+    e^-check_nats times the Green's function decay across the window)."""
     sources = np.unique(np.asarray(sources, dtype=np.int64))
     M = M.tocsr()
     lev = hop_levels(M, sources)
-    out = np.full(nv, -np.inf)
     if band_rings is None:
         C = M.tocoo()
         off = C.row != C.col
@@ -83,33 +168,14 @@ def solve_log(M: sp.csr_matrix, sources, band_rings: int | None = None,
         band_rings = max(1, int(300.0 // beta))
     B = int(band_rings)
     G = int(margin_rings) if margin_rings is not None else B
-    depth = int(lev.max())
-    u0 = np.zeros(nv)
-    u0[sources] = 1.0
-    solved = np.zeros(nv, dtype=bool)
-    for lo in range(0, depth + 1, B):
-        U = np.flatnonzero((lev >= lo) & (lev < lo + B + G))
-        core = (lev >= lo) & (lev < lo + B)
-        MU = M[U]
-        rows = MU.tocoo()
-        known = solved[rows.col]
-        scale = out[rows.col[known]].max() if known.any() else 0.0
-        rhs = np.zeros(U.size)
-        src_in = u0[U] > 0
-        if src_in.any():
-            rhs[src_in] = np.exp(-scale)
-        if known.any():
-            contrib = -rows.data[known] * np.exp(out[rows.col[known]] - scale)
-            rhs += np.bincount(rows.row[known], weights=contrib, minlength=U.size)
-        S = MU[:, U].tocsc()
-        lu = spla.splu(S, permc_spec="COLAMD", diag_pivot_thresh=0.0,
-                       options=dict(SymmetricMode=True))
-        w = lu.solve(rhs)
-        keep = core[U]
-        with np.errstate(divide="ignore"):
-            out[U[keep]] = np.log(w[keep]) + scale
-        solved[U[keep]] = True
-    return out
+    out = _ring_pass(M, sources, lev, B, G)
+    if not refine:
+        return out
+    for _ in range(max_refine):
+        out, ok = _value_pass(M, sources, out, value_band, value_margin, check_nats)
+        if ok:
+            return out
+    raise RuntimeError("value-band refinement did not confirm its windows")
 
 
 def gauss_seidel_bfs(K: sp.csr_matrix, A: np.ndarray, t: float, sources,

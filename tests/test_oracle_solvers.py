@@ -6,6 +6,7 @@ import scipy.sparse as sp
 from scipy.sparse.csgraph import dijkstra, shortest_path
 
 import meshgen
+from tests.oracle_fixtures import equilateral_patch
 from oracle import admm, assembly, bfs, diffusion, gradient, integrate, mesh, metrics, pipeline, poisson
 
 
@@ -36,6 +37,24 @@ def test_diffusion_dense_solve_and_bands(bumpy3):
     l_auto = diffusion.solve_log(M, src)
     for l in (l_one, l_band, l_auto):
         assert np.abs(l - np.log(dense)).max() < 1e-11
+
+
+@pytest.mark.parametrize("value_band", [100.0, 8.0])
+def test_value_bands_repair_rings_that_misorder_u(value_band):
+    """On an equilateral lattice the hop count overestimates distance by up
+    to 2/sqrt(3) depending on direction, so hop rings misorder u far from
+    the source: a ring-banded solve with thin margins is visibly wrong, and
+    the value-ordered refinement recovers the dense solve from that same
+    poor first pass (narrow value bands exercise many windows)."""
+    v, f = equilateral_patch(40)
+    topo, K, A, t = _setup(v, f)
+    M = diffusion.heat_matrix(K, A, t)
+    src = [0]
+    exact = np.log(np.linalg.solve(M.toarray(), np.eye(v.shape[0])[0]))
+    rough = diffusion.solve_log(M, src, band_rings=2, margin_rings=2, refine=False)
+    fixed = diffusion.solve_log(M, src, band_rings=2, margin_rings=2, value_band=value_band)
+    assert np.abs(rough - exact).max() > 1e-2
+    assert np.abs(fixed - exact).max() < 1e-12
 
 
 def test_diffusion_mass_conservation_and_symmetry(bumpy3):
@@ -326,9 +345,8 @@ def test_converged_admm_integrates_to_poisson(bumpy3, mu, alpha):
 
 
 def _two_component_mesh():
-    v1, f1 = meshgen.grid(6, 0.1, seed=4)
-    v2, f2 = meshgen.grid(5, 0.1, seed=5)
-    return np.vstack([v1, v2 + [3.0, 0.0, 0.0]]), np.vstack([f1, f2 + v1.shape[0]]), v1.shape[0]
+    v, f, starts = meshgen.disjoint_union([meshgen.grid(6, 0.1, seed=4), meshgen.grid(5, 0.1, seed=5)])
+    return v, f, starts[1]
 
 
 def test_source_paths_are_tree_paths_between_sources():
