@@ -215,6 +215,54 @@ hg_status hg_integrate_face(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
 /* Canonical edge list: DEVICE int32[ne*2] (smaller id, larger id). */
 hg_status hg_mesh_edges(hg_mesh_t mesh, int32_t* edges_dev, void* stream);
 
+/* ---- serving: concurrent queries over resident meshes ----
+ *
+ * A server runs queries on n_slots worker threads, each with its own HIP
+ * stream on the device current at creation.  hg_server_submit queues a
+ * query and returns at once; a free slot takes the oldest query that can be
+ * admitted and runs it exactly as hg_geodesic_solve would (same kernels,
+ * private workspace), so results do not depend on what else runs; queries
+ * that arrive while others run start as soon as a slot and memory allow and
+ * overlap with them on the device.  Admission by device memory: query
+ * workspaces are pooled per mesh and reused; a new one is created only while
+ * the workspaces held stay within workspace_budget bytes (0 = half of the
+ * free device memory at creation), releasing idle workspaces of other meshes
+ * for the oldest waiting query; with nothing running the oldest query is
+ * always admitted.  Meshes, source arrays' contents (copied at submit) and
+ * the output buffers must stay valid until the query's result is taken. */
+typedef struct hg_server_s* hg_server_t;
+
+typedef struct {
+    int64_t ticket;         /* as returned by hg_server_submit; -1 = none */
+    int32_t status;         /* hg_status of the query */
+    int32_t reserved0;
+    double t_submit, t_start, t_end;   /* hg_server_clock() seconds */
+    hg_info info;
+} hg_result;
+
+typedef struct {
+    int32_t n_slots, pending, running, completed_unread, workspaces_idle;
+    int32_t reserved0;
+    uint64_t workspace_bytes_held, workspace_bytes_idle, workspace_budget;
+    int32_t reserved[8];
+} hg_server_stats_t;
+
+/* n_slots in [1, 64].  *out receives the server. */
+hg_status hg_server_create(int32_t n_slots, uint64_t workspace_budget, hg_server_t* out);
+/* Queue one query: arguments as hg_geodesic_solve (src is copied, opts may be
+ * NULL); d_dev is written when the query completes.  *ticket (optional)
+ * identifies the result. */
+hg_status hg_server_submit(hg_server_t server, hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
+                           const hg_opts* opts, float* d_dev, int64_t* ticket);
+/* Take the oldest completed result, waiting up to timeout_ms (< 0: without
+ * limit); out->ticket = -1 if none completed in time. */
+hg_status hg_server_wait(hg_server_t server, hg_result* out, int32_t timeout_ms);
+hg_status hg_server_stats(hg_server_t server, hg_server_stats_t* stats);
+/* Seconds on the clock of the result timestamps (monotonic). */
+double hg_server_clock(void);
+/* Runs the queued queries to completion, then frees the server. */
+void hg_server_destroy(hg_server_t server);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* hg_last_error(void);
 

@@ -12,6 +12,7 @@ from ._hgeo import (  # noqa: F401
     Mesh,
     NotConverged,
     Opts,
+    Server,
     default_opts,
     load_library,
 )

@@ -68,6 +68,22 @@ class MeshStats(C.Structure):
     ]
 
 
+class Result(C.Structure):
+    _fields_ = [
+        ("ticket", C.c_int64), ("status", C.c_int32), ("reserved0", C.c_int32),
+        ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double), ("info", Info),
+    ]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [
+        ("n_slots", C.c_int32), ("pending", C.c_int32), ("running", C.c_int32),
+        ("completed_unread", C.c_int32), ("workspaces_idle", C.c_int32), ("reserved0", C.c_int32),
+        ("workspace_bytes_held", C.c_uint64), ("workspace_bytes_idle", C.c_uint64),
+        ("workspace_budget", C.c_uint64), ("reserved", C.c_int32 * 8),
+    ]
+
+
 # (name, argtypes)
 _P = C.c_void_p
 _API = {
@@ -84,6 +100,12 @@ _API = {
     "hg_integrate_edge": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_integrate_face": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_mesh_edges": [_P, _P, _P],
+    "hg_server_create": [C.c_int32, C.c_uint64, C.POINTER(_P)],
+    "hg_server_submit": [_P, _P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, C.POINTER(C.c_int64)],
+    "hg_server_wait": [_P, C.POINTER(Result), C.c_int32],
+    "hg_server_stats": [_P, C.POINTER(ServerStats)],
+    "hg_server_clock": [],
+    "hg_server_destroy": [_P],
     "hg_last_error": [],
 }
 EXPORTED = tuple(_API)
@@ -104,8 +126,10 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
         if name == "hg_last_error":
             fn.restype = C.c_char_p
-        elif name == "hg_mesh_destroy":
+        elif name in ("hg_mesh_destroy", "hg_server_destroy"):
             fn.restype = None
+        elif name == "hg_server_clock":
+            fn.restype = C.c_double
         else:
             fn.restype = C.c_int
     if path == LIB_PATH:
@@ -298,3 +322,58 @@ class Mesh:
         _check(_lib.hg_integrate_face(self._h, p, n, _dptr(g, torch.float32, 3 * self.nf),
                                       _dptr(d, torch.float32, self.nv), _stream(stream)))
         return d
+
+
+class Server:
+    """Concurrent query runtime (hg_server_*): n_slots worker slots, each on
+    its own stream; queries are admitted as slots and memory free up."""
+
+    def __init__(self, n_slots: int = 4, workspace_budget: int = 0):
+        load_library()
+        _torch()
+        h = C.c_void_p()
+        _check(_lib.hg_server_create(int(n_slots), int(workspace_budget), C.byref(h)))
+        self._h = h
+        self._keep = {}   # ticket -> (mesh, out tensor) kept alive until taken
+
+    def submit(self, mesh: "Mesh", sources, out=None, t: float = 0.0, opts: Opts | None = None) -> tuple:
+        torch = _torch()
+        if out is None:
+            out = torch.empty(mesh.nv, dtype=torch.float32, device="cuda")
+        a, p, n = _src_array(sources)
+        tk = C.c_int64()
+        _check(_lib.hg_server_submit(self._h, mesh._h, p, n, float(t), C.byref(opts) if opts else None,
+                                     _dptr(out, torch.float32, mesh.nv), C.byref(tk)))
+        self._keep[tk.value] = (mesh, out)
+        return tk.value, out
+
+    def wait(self, timeout_ms: int = -1):
+        """The next completed query as a dict (None on timeout)."""
+        r = Result()
+        _check(_lib.hg_server_wait(self._h, C.byref(r), int(timeout_ms)))
+        if r.ticket < 0:
+            return None
+        mesh, out = self._keep.pop(r.ticket)
+        return {"ticket": r.ticket, "status": r.status, "t_submit": r.t_submit, "t_start": r.t_start,
+                "t_end": r.t_end, "info": SolveInfo(r.info.as_dict()), "out": out}
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.hg_server_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_ if not k.startswith("reserved")}
+
+    @staticmethod
+    def clock() -> float:
+        load_library()
+        return _lib.hg_server_clock()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

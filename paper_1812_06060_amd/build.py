@@ -23,6 +23,7 @@ SOURCES = [
     "kernels_integrate.hip",
     "kernels_patch.hip",
     "kernels_paths.hip",
+    "server.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

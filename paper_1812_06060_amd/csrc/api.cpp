@@ -13,7 +13,7 @@ namespace hg {
 
 static thread_local std::string g_last_error;
 
-size_t Mesh::Work::bytes() const {
+size_t Work::bytes() const {
     return level.bytes() + parent.bytes() + pslot.bytes() + frontier_a.bytes() + frontier_b.bytes() +
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
            h.bytes() + sumz.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
@@ -21,7 +21,7 @@ size_t Mesh::Work::bytes() const {
            src.bytes() + dprev.bytes() + paths.bytes();
 }
 
-size_t Mesh::Work::Paths::bytes() const {
+size_t Work::Paths::bytes() const {
     return ptr.bytes() + edge.bytes() + face.bytes() + sign.bytes() + vec.bytes() + eg_ptr.bytes() + eg_id.bytes() +
            eg_slot.bytes() + fg_ptr.bytes() + fg_id.bytes() + fg_slot.bytes() + z.bytes() + seff.bytes();
 }
@@ -34,9 +34,7 @@ uint64_t Mesh::mesh_bytes() const {
            theta_ell.bytes();
 }
 
-Mesh::~Mesh() {
-    if (w.pinned) (void)hipHostFree(w.pinned);
-}
+Mesh::~Mesh() = default;
 
 static hg_status fail(hg_status code, const std::string& msg) {
     g_last_error = msg;
@@ -90,9 +88,6 @@ static double resolve_t(const Mesh& m, double t, const hg_opts& o) {
     return mm * m.hbar * m.hbar;
 }
 
-static void ensure_pinned(Mesh& m) {
-    if (!m.w.pinned) HG_CHECK_HIP(hipHostMalloc(&m.w.pinned, 8 * sizeof(double), hipHostMallocDefault));
-}
 
 struct StageTimer {
     hipStream_t s;
@@ -116,6 +111,73 @@ struct StageTimer {
 }  // namespace hg
 
 using namespace hg;
+
+// One whole query (Algorithm 1) on workspace w and stream s.  Throws Error
+// for invalid arguments and device failures; non-convergence is returned.
+QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
+                         float* d_dev, hipStream_t s, hg_info* info) {
+    Mesh* m = &mesh_ref;
+    w.ensure_pinned();
+    hg_opts o = resolve_opts(opts);
+    auto si = map_sources(*m, src, nsrc);
+    double tt = resolve_t(*m, t, o);
+    StageTimer tm(s);
+    tm.mark();
+    const bool paths = nsrc > 1 && o.source_paths;
+    if (paths) build_source_paths(*m, w, si, s);
+    int depth = run_bfs(*m, w, si, s);
+    tm.mark();
+    DiffusionResult dr = run_diffusion(*m, w, si, tt, o, s);
+    tm.mark();
+    run_normalize(*m, w, s);
+    tm.mark();
+    // ADMM penalty: the low-frequency error of these iterations decays
+    // fastest for mu of the order of the longest chain the field is
+    // integrated along (measured, one source: best mu ~ 100 at depth 167,
+    // ~ 300 at depth 663; several sources with path constraints: best mu
+    // ~ 1 - 1.8 times the longest path's edge count); mu = 0 picks
+    // max(30, depth / 2, 1.5 * longest path)
+    if (o.mu == 0.0) {
+        o.mu = std::max(30.0, 0.5 * depth);
+        if (paths && w.paths.np > 0) o.mu = std::max(o.mu, 1.5 * w.paths.max_len);
+    }
+    AdmmResult ar = o.formulation == HG_FORM_EDGE ? run_admm_edge(*m, w, 0, o, s, depth, paths)
+                                                  : run_admm_face(*m, w, 0, o, s, depth, paths);
+    tm.mark();
+    integrate(*m, w, o.formulation, depth, d_dev, s);
+    tm.mark();
+    HG_CHECK_HIP(hipStreamSynchronize(s));
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->bfs_depth = depth;
+        info->sweeps = dr.sweeps;
+        info->passes = dr.passes;
+        info->admm_iters = ar.iters;
+        info->res_u = dr.res;
+        info->res_primal = ar.rp;
+        info->res_dual = ar.rd;
+        info->t = tt;
+        info->ms_bfs = tm.ms(0, 1);
+        info->ms_diffusion = tm.ms(1, 2);
+        info->ms_normalize = tm.ms(2, 3);
+        info->ms_admm = tm.ms(3, 4);
+        info->ms_integrate = tm.ms(4, 5);
+        info->ms_total = tm.ms(0, 5);
+        info->workspace_bytes = w.bytes();
+        info->converged_u = dr.converged;
+        info->converged_admm = ar.converged;
+        info->ms_pass_kernel = dr.timed_launches ? (float)(dr.kernel_ms / dr.timed_launches) : 0.f;
+        info->ms_admm_kernel = ar.timed_launches ? (float)(ar.kernel_ms / ar.timed_launches) : 0.f;
+        info->bytes_pass_kernel = dr.bytes_per_pass;
+        info->bytes_admm_kernel = ar.bytes_per_iter;
+        info->bytes_alg = dr.bytes_per_pass * (uint64_t)dr.passes + ar.bytes_per_iter * (uint64_t)ar.iters;
+        info->n_paths = paths ? w.paths.np : 0;
+        info->path_edges = paths ? w.paths.ns : 0;
+    }
+    if (!dr.converged) return {HG_E_NOT_CONVERGED, "diffusion sweep cap reached"};
+    if (!ar.converged) return {HG_E_NOT_CONVERGED, "ADMM iteration cap reached"};
+    return {HG_OK, ""};
+}
 
 extern "C" {
 
@@ -180,7 +242,7 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
             m->ell_ptr.upload(T.ell_ptr, s);
             m->lnb.upload(T.lnb, s);
             m->ell_width.upload(T.ell_width, s);
-            ensure_pinned(*m);
+            m->w.ensure_pinned();
             geometry_init(*m, s);
         } catch (...) {
             delete m;
@@ -229,7 +291,7 @@ hg_status hg_bfs(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, int32_t* leve
         auto* m = reinterpret_cast<Mesh*>(mesh);
         hipStream_t s = (hipStream_t)stream;
         auto si = map_sources(*m, src, nsrc);
-        int depth = run_bfs(*m, si, s);
+        int depth = run_bfs(*m, m->w, si, s);
         if (level_dev) scatter_vertices_to_user_i(*m, m->w.level.p, level_dev, false, s);
         if (parent_dev) scatter_vertices_to_user_i(*m, m->w.parent.p, parent_dev, true, s);
         HG_CHECK_HIP(hipStreamSynchronize(s));
@@ -247,9 +309,9 @@ hg_status hg_diffuse(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
         hg_opts o = resolve_opts(opts);
         auto si = map_sources(*m, src, nsrc);
         double tt = resolve_t(*m, t, o);
-        int depth = run_bfs(*m, si, s);
-        DiffusionResult r = run_diffusion(*m, si, tt, o, s);
-        diffusion_logu(*m, s);
+        int depth = run_bfs(*m, m->w, si, s);
+        DiffusionResult r = run_diffusion(*m, m->w, si, tt, o, s);
+        diffusion_logu(*m, m->w, s);
         scatter_vertices_to_user_d(*m, m->w.logu.p, logu_dev, s);
         HG_CHECK_HIP(hipStreamSynchronize(s));
         if (info) {
@@ -270,7 +332,7 @@ hg_status hg_normalize(hg_mesh_t mesh, const double* logu_dev, float* h_dev, voi
         if (!mesh || !logu_dev || !h_dev) return fail(HG_E_INVALID_ARG, "null argument");
         auto* m = reinterpret_cast<Mesh*>(mesh);
         hipStream_t s = (hipStream_t)stream;
-        normalize_from_logu(*m, logu_dev, s);
+        normalize_from_logu(*m, m->w, logu_dev, s);
         scatter_faces_to_user(*m, m->w.h.p, h_dev, s);
         HG_CHECK_HIP(hipStreamSynchronize(s));
         return HG_OK;
@@ -286,11 +348,11 @@ static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, const int32_t* s
         hg_opts o = resolve_opts(opts);
         if (o.mu == 0.0) o.mu = 100.0;   // no breadth-first depth here: the paper's value
         const bool paths = src && nsrc > 1 && o.source_paths;
-        if (paths) build_source_paths(*m, map_sources(*m, src, nsrc), s);
+        if (paths) build_source_paths(*m, m->w, map_sources(*m, src, nsrc), s);
         m->w.h.alloc((size_t)3 * m->nf);
         gather_faces_to_internal(*m, h_dev, m->w.h.p, s);
-        AdmmResult r = form == HG_FORM_EDGE ? run_admm_edge(*m, iters, o, s, -1, paths)
-                                            : run_admm_face(*m, iters, o, s, -1, paths);
+        AdmmResult r = form == HG_FORM_EDGE ? run_admm_edge(*m, m->w, iters, o, s, -1, paths)
+                                            : run_admm_face(*m, m->w, iters, o, s, -1, paths);
         if (form == HG_FORM_EDGE)
             scatter_edges_to_user(*m, m->w.xe.p, out, s);
         else
@@ -326,7 +388,7 @@ static hg_status integrate_stage(hg_mesh_t mesh, const int32_t* src, int32_t nsr
         auto* m = reinterpret_cast<Mesh*>(mesh);
         hipStream_t s = (hipStream_t)stream;
         auto si = map_sources(*m, src, nsrc);
-        int depth = run_bfs(*m, si, s);
+        int depth = run_bfs(*m, m->w, si, s);
         if (form == HG_FORM_EDGE) {
             m->w.xe.alloc(m->ne);
             gather_edges_to_internal(*m, in, m->w.xe.p, s);
@@ -334,7 +396,7 @@ static hg_status integrate_stage(hg_mesh_t mesh, const int32_t* src, int32_t nsr
             m->w.gf.alloc((size_t)3 * m->nf);
             gather_faces_to_internal(*m, in, m->w.gf.p, s);
         }
-        integrate(*m, form, depth, d_dev, s);
+        integrate(*m, m->w, form, depth, d_dev, s);
         HG_CHECK_HIP(hipStreamSynchronize(s));
         return HG_OK;
     });
@@ -355,66 +417,8 @@ hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, do
     return guarded([&]() -> hg_status {
         if (!mesh || !d_dev) return fail(HG_E_INVALID_ARG, "null argument");
         auto* m = reinterpret_cast<Mesh*>(mesh);
-        hipStream_t s = (hipStream_t)stream;
-        hg_opts o = resolve_opts(opts);
-        auto si = map_sources(*m, src, nsrc);
-        double tt = resolve_t(*m, t, o);
-        StageTimer tm(s);
-        tm.mark();
-        const bool paths = nsrc > 1 && o.source_paths;
-        if (paths) build_source_paths(*m, si, s);
-        int depth = run_bfs(*m, si, s);
-        tm.mark();
-        DiffusionResult dr = run_diffusion(*m, si, tt, o, s);
-        tm.mark();
-        run_normalize(*m, s);
-        tm.mark();
-        // ADMM penalty: the low-frequency error of these iterations decays
-        // fastest for mu of the order of the longest chain the field is
-        // integrated along (measured, one source: best mu ~ 100 at depth 167,
-        // ~ 300 at depth 663; several sources with path constraints: best mu
-        // ~ 1 - 1.8 times the longest path's edge count); mu = 0 picks
-        // max(30, depth / 2, 1.5 * longest path)
-        if (o.mu == 0.0) {
-            o.mu = std::max(30.0, 0.5 * depth);
-            if (paths && m->w.paths.np > 0) o.mu = std::max(o.mu, 1.5 * m->w.paths.max_len);
-        }
-        AdmmResult ar = o.formulation == HG_FORM_EDGE ? run_admm_edge(*m, 0, o, s, depth, paths)
-                                                      : run_admm_face(*m, 0, o, s, depth, paths);
-        tm.mark();
-        integrate(*m, o.formulation, depth, d_dev, s);
-        tm.mark();
-        HG_CHECK_HIP(hipStreamSynchronize(s));
-        if (info) {
-            std::memset(info, 0, sizeof(*info));
-            info->bfs_depth = depth;
-            info->sweeps = dr.sweeps;
-            info->passes = dr.passes;
-            info->admm_iters = ar.iters;
-            info->res_u = dr.res;
-            info->res_primal = ar.rp;
-            info->res_dual = ar.rd;
-            info->t = tt;
-            info->ms_bfs = tm.ms(0, 1);
-            info->ms_diffusion = tm.ms(1, 2);
-            info->ms_normalize = tm.ms(2, 3);
-            info->ms_admm = tm.ms(3, 4);
-            info->ms_integrate = tm.ms(4, 5);
-            info->ms_total = tm.ms(0, 5);
-            info->workspace_bytes = m->w.bytes();
-            info->converged_u = dr.converged;
-            info->converged_admm = ar.converged;
-            info->ms_pass_kernel = dr.timed_launches ? (float)(dr.kernel_ms / dr.timed_launches) : 0.f;
-            info->ms_admm_kernel = ar.timed_launches ? (float)(ar.kernel_ms / ar.timed_launches) : 0.f;
-            info->bytes_pass_kernel = dr.bytes_per_pass;
-            info->bytes_admm_kernel = ar.bytes_per_iter;
-            info->bytes_alg = dr.bytes_per_pass * (uint64_t)dr.passes + ar.bytes_per_iter * (uint64_t)ar.iters;
-            info->n_paths = paths ? m->w.paths.np : 0;
-            info->path_edges = paths ? m->w.paths.ns : 0;
-        }
-        if (!dr.converged) return fail(HG_E_NOT_CONVERGED, "diffusion sweep cap reached");
-        if (!ar.converged) return fail(HG_E_NOT_CONVERGED, "ADMM iteration cap reached");
-        return HG_OK;
+        QueryOutcome q = solve_query(*m, m->w, src, nsrc, t, opts, d_dev, (hipStream_t)stream, info);
+        return q.status == HG_OK ? HG_OK : fail(q.status, q.msg);
     });
 }
 

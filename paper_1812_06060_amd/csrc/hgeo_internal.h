@@ -99,6 +99,53 @@ struct HostTopo {
 void build_topology(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, int patch_size,
                     HostTopo& out);
 
+// Per-query device workspace.  A query runs on one Work and one stream; the
+// mesh data it reads is never written after mesh_create, so queries on the
+// same mesh with different Works may run concurrently on different streams.
+// Buffers grow on demand and are kept for the next query.
+struct Work {
+    Work() = default;
+    Work(const Work&) = delete;
+    Work& operator=(const Work&) = delete;
+    ~Work() {
+        if (pinned) (void)hipHostFree(pinned);
+    }
+    void ensure_pinned() {
+        if (!pinned) HG_CHECK_HIP(hipHostMalloc(&pinned, 8 * sizeof(double), hipHostMallocDefault));
+    }
+    DBuf<int32_t> level, parent, pslot, frontier_a, frontier_b, counters;
+    DBuf<double> v0, v1, invD;          // diffusion mantissas, 1/(A + t sum theta)
+    DBuf<int32_t> e0, e1;               // diffusion exponents
+    DBuf<double> logu;
+    DBuf<float> h;                      // [nf*3] internal order
+    DBuf<float> sumz;                   // [ne] edge-form target sums
+    DBuf<float> z0, z1;                 // edge form: zeta [2*ne]; face form: z [2*ne*3]
+    DBuf<float> g0, g1;                 // face form gradients [nf*3]
+    DBuf<float> xe;                     // [ne] final edge differences (internal)
+    DBuf<float> gf;                     // [nf*3] final face gradients (internal)
+    DBuf<float> shi0, slo0, shi1, slo1; // integration double-float sums
+    DBuf<int32_t> jp0, jp1;             // pointer-jumping parents
+    DBuf<float> dprev;                  // distance at the previous ADMM check
+    DBuf<double> partial;               // reduction partials
+    DBuf<double> red_host_dummy;
+    double* pinned = nullptr;           // host pinned reduction results
+    DBuf<int32_t> src;
+    // source paths of the multi-source constraints (Eqs. 24-25), built by
+    // build_source_paths: np paths over ns slots, slots grouped by edge
+    // and by face (CSR over the distinct ids, slots in increasing order)
+    struct Paths {
+        int np = 0, ns = 0, ng_edge = 0, ng_face = 0;
+        int max_len = 0;                        // edges on the longest path
+        DBuf<int32_t> ptr, edge, face;
+        DBuf<float> sign, vec;                  // [ns], [3*ns]
+        DBuf<int32_t> eg_ptr, eg_id, eg_slot, fg_ptr, fg_id, fg_slot;
+        DBuf<float> z;                          // folded copies: [ns] edge form, [3*ns] face form
+        DBuf<float> seff;                       // edge form: [ne] effective target sums
+        size_t bytes() const;
+    } paths;
+    size_t bytes() const;
+};
+
 struct Mesh {
     int device = 0;
     int64_t nv = 0, nf = 0, ne = 0, nbnd = 0;
@@ -125,40 +172,9 @@ struct Mesh {
     DBuf<uint8_t> ell_width;
     DBuf<double> theta_ell;                 // theta in the tiles' ELL layout
 
-    // per-query workspace (kept between queries)
-    struct Work {
-        DBuf<int32_t> level, parent, pslot, frontier_a, frontier_b, counters;
-        DBuf<double> v0, v1, invD;          // diffusion mantissas, 1/(A + t sum theta)
-        DBuf<int32_t> e0, e1;               // diffusion exponents
-        DBuf<double> logu;
-        DBuf<float> h;                      // [nf*3] internal order
-        DBuf<float> sumz;                   // [ne] edge-form target sums
-        DBuf<float> z0, z1;                 // edge form: zeta [2*ne]; face form: z [2*ne*3]
-        DBuf<float> g0, g1;                 // face form gradients [nf*3]
-        DBuf<float> xe;                     // [ne] final edge differences (internal)
-        DBuf<float> gf;                     // [nf*3] final face gradients (internal)
-        DBuf<float> shi0, slo0, shi1, slo1; // integration double-float sums
-        DBuf<int32_t> jp0, jp1;             // pointer-jumping parents
-        DBuf<float> dprev;                  // distance at the previous ADMM check
-        DBuf<double> partial;               // reduction partials
-        DBuf<double> red_host_dummy;
-        double* pinned = nullptr;           // host pinned reduction results
-        DBuf<int32_t> src;
-        // source paths of the multi-source constraints (Eqs. 24-25), built by
-        // build_source_paths: np paths over ns slots, slots grouped by edge
-        // and by face (CSR over the distinct ids, slots in increasing order)
-        struct Paths {
-            int np = 0, ns = 0, ng_edge = 0, ng_face = 0;
-            int max_len = 0;                        // edges on the longest path
-            DBuf<int32_t> ptr, edge, face;
-            DBuf<float> sign, vec;                  // [ns], [3*ns]
-            DBuf<int32_t> eg_ptr, eg_id, eg_slot, fg_ptr, fg_id, fg_slot;
-            DBuf<float> z;                          // folded copies: [ns] edge form, [3*ns] face form
-            DBuf<float> seff;                       // edge form: [ne] effective target sums
-            size_t bytes() const;
-        } paths;
-        size_t bytes() const;
-    } w;
+    // default per-query workspace of the synchronous entry points (also
+    // used for the mesh's own reductions)
+    Work w;
 
     uint64_t mesh_bytes() const;
     ~Mesh();
@@ -166,7 +182,7 @@ struct Mesh {
 
 // ---- kernels / stage drivers (implemented in the .hip files) ----
 void geometry_init(Mesh& m, hipStream_t s);
-int run_bfs(Mesh& m, const std::vector<int32_t>& src_internal, hipStream_t s);
+int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s);
 struct DiffusionResult {
     int sweeps = 0, passes = 0;
     double res = 0.0;
@@ -175,14 +191,14 @@ struct DiffusionResult {
     int timed_launches = 0;      // launches covered by kernel_ms
     uint64_t bytes_per_pass = 0; // algorithmic HBM bytes of one pass kernel
 };
-DiffusionResult run_diffusion(Mesh& m, const std::vector<int32_t>& src_internal, double t,
+DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, double t,
                               const hg_opts& o, hipStream_t s);
-void diffusion_logu(Mesh& m, hipStream_t s);                   // w.logu from (v, e)
+void diffusion_logu(Mesh& m, Work& w, hipStream_t s);                   // w.logu from (v, e)
 void build_theta_ell(Mesh& m, hipStream_t s);
 bool patch_supported(const Mesh& m);
-DiffusionResult run_diffusion_patch(Mesh& m, double t, const hg_opts& o, int inner, hipStream_t s);
-void run_normalize(Mesh& m, hipStream_t s);                    // w.h from (v, e)
-void normalize_from_logu(Mesh& m, const double* logu_user, hipStream_t s);
+DiffusionResult run_diffusion_patch(Mesh& m, Work& w, double t, const hg_opts& o, int inner, hipStream_t s);
+void run_normalize(Mesh& m, Work& w, hipStream_t s);                    // w.h from (v, e)
+void normalize_from_logu(Mesh& m, Work& w, const double* logu_user, hipStream_t s);
 struct AdmmResult {
     int iters = 0;
     double rp = 0.0, rd = 0.0;
@@ -224,18 +240,18 @@ struct RunTimer {
 // with depth >= 0 (the breadth-first depth of the query) by the change of the
 // integrated distance field (DistStop), else by the paper's residuals.
 // With use_paths, the constraints of Eqs. 24-25 over m.w.paths are added.
-AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1,
+AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStream_t s, int depth = -1,
                          bool use_paths = false);
-AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth = -1,
+AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStream_t s, int depth = -1,
                          bool use_paths = false);
 // Builds m.w.paths from the (internal) source list; runs breadth-first
 // searches from single sources, so it overwrites level/parent/pslot: run the
 // query's own breadth-first search after it.
-void build_source_paths(Mesh& m, const std::vector<int32_t>& src_internal, hipStream_t s);
-void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s);
+void build_source_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s);
+void integrate(Mesh& m, Work& w, int form, int depth, float* d_user, hipStream_t s);
 // integrates the given state (edge differences xe or face gradients g) and
 // returns max |d - d_prev| (inf on the first call) and max |d|; d_prev <- d
-void dist_change(Mesh& m, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
+void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
                  double& delta, double& dmax);
 
 // Stopping rule on the distance field: with delta_k the largest change of d
@@ -263,6 +279,15 @@ struct DistStop {
     }
 };
 
+// One whole query (the body of hg_geodesic_solve) on a given workspace and
+// stream; throws Error for invalid arguments and device failures.
+struct QueryOutcome {
+    hg_status status;
+    std::string msg;
+};
+QueryOutcome solve_query(Mesh& m, Work& w, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
+                         float* d_dev, hipStream_t s, hg_info* info);
+
 // permutation helpers
 void gather_faces_to_internal(Mesh& m, const float* user3, float* internal3, hipStream_t s);
 void scatter_faces_to_user(Mesh& m, const float* internal3, float* user3, hipStream_t s);
@@ -275,7 +300,7 @@ void scatter_vertices_to_user_i(Mesh& m, const int32_t* internal, int32_t* user,
 void edges_to_user(Mesh& m, int32_t* edges_user, hipStream_t s);
 
 // reductions: sum or max of n doubles produced per block into w.partial
-double reduce_partials(Mesh& m, int nblocks, bool is_max, hipStream_t s);
+double reduce_partials(Mesh& m, Work& w, int nblocks, bool is_max, hipStream_t s);
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
 

@@ -123,10 +123,10 @@ __global__ void k_edge_targets(int ne, const int32_t* ev, const int32_t* ef, con
     sumz[e] = (float)s;
 }
 
-void run_normalize(Mesh& m, hipStream_t s) {
-    m.w.h.alloc((size_t)3 * m.nf);
+void run_normalize(Mesh& m, Work& w, hipStream_t s) {
+    w.h.alloc((size_t)3 * m.nf);
     hipLaunchKernelGGL(k_normalize, dim3(grid_for(m.nf, kBlockA)), dim3(kBlockA), 0, s, (int)m.nf, m.tri.p, m.px.p,
-                       m.py.p, m.pz.p, m.w.v0.p, m.w.e0.p, m.w.h.p);
+                       m.py.p, m.pz.p, w.v0.p, w.e0.p, w.h.p);
     HG_CHECK_HIP(hipGetLastError());
 }
 
@@ -145,13 +145,13 @@ __global__ void k_logu_to_ve(int nv, const int32_t* perm_v, const double* logu_u
     v[j] = exp(l - ex * 0.69314718055994530942);
 }
 
-void normalize_from_logu(Mesh& m, const double* logu_user, hipStream_t s) {
-    m.w.v0.alloc(m.nv);
-    m.w.e0.alloc(m.nv);
+void normalize_from_logu(Mesh& m, Work& w, const double* logu_user, hipStream_t s) {
+    w.v0.alloc(m.nv);
+    w.e0.alloc(m.nv);
     hipLaunchKernelGGL(k_logu_to_ve, dim3(grid_for(m.nv, kBlockA)), dim3(kBlockA), 0, s, (int)m.nv, m.perm_v.p,
-                       logu_user, m.w.v0.p, m.w.e0.p);
+                       logu_user, w.v0.p, w.e0.p);
     HG_CHECK_HIP(hipGetLastError());
-    run_normalize(m, s);
+    run_normalize(m, w, s);
 }
 
 // ---------------------------------------------------------------- edge form
@@ -252,7 +252,7 @@ __global__ void k_edge_x(int ne, const uint32_t* dummy, const int32_t* ef, const
 }
 
 // ------------------------------------------------- source paths (Eqs. 24-25)
-// Each path S of m.w.paths adds a group of copies with the constraint of
+// Each path S of w.paths adds a group of copies with the constraint of
 // Eq. 25 (edge form) or Eq. 24 (face form); their duals are folded like the
 // face copies.  One iteration = the form's face kernel, then
 // k_path_*_proj (one block per path: the group's projection, from the same
@@ -401,19 +401,18 @@ __global__ void k_path_face_fix(int ng, const int32_t* gptr, const int32_t* gid,
     for (int c = 0; c < 3; ++c) gout[3 * f + c] = (2.f * h[3 * f + c] + mu * acc[c]) * den;
 }
 
-static void reduce_pair(Mesh& m, int nblocks, hipStream_t s, double& a, double& b) {
-    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlockA), 0, s, m.w.partial.p, nblocks);
+static void reduce_pair(Mesh& m, Work& w, int nblocks, hipStream_t s, double& a, double& b) {
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlockA), 0, s, w.partial.p, nblocks);
     HG_CHECK_HIP(hipGetLastError());
     HG_CHECK_HIP(
-        hipMemcpyAsync(m.w.pinned, m.w.partial.p + 2 * nblocks, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        hipMemcpyAsync(w.pinned, w.partial.p + 2 * nblocks, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HG_CHECK_HIP(hipStreamSynchronize(s));
-    a = m.w.pinned[0];
-    b = m.w.pinned[1];
+    a = w.pinned[0];
+    b = w.pinned[1];
 }
 
-AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
+AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
     const int nf = (int)m.nf, ne = (int)m.ne;
-    auto& w = m.w;
     w.sumz.alloc(ne);
     w.z0.alloc((size_t)2 * ne);
     w.z1.alloc((size_t)2 * ne);
@@ -458,7 +457,7 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
         hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, S, prev, cur, mu,
                            inv1mu, mu_relax, w.partial.p);
         double a, b;
-        reduce_pair(m, gf, s, a, b);
+        reduce_pair(m, w, gf, s, a, b);
         r.rp = sqrt(a) / (sqrt(3.0 * (double)nf) * m.hbar);
         r.rd = sqrt(b) / (sqrt(3.0 * (double)nf) * m.hbar * o.mu);
     };
@@ -488,7 +487,7 @@ AdmmResult run_admm_edge(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
                 hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, S, za, inv1mu,
                                    w.xe.p);
                 double delta, dmax;
-                dist_change(m, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax);
+                dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax);
                 done = stop.update(delta, dmax, o.tol_admm);
             } else {
                 residuals(zb, za);
@@ -629,20 +628,19 @@ __global__ void k_normM(int nf, const uint32_t* fslot, const double* farea, doub
     }
 }
 
-static void face_residuals(Mesh& m, int gf, const float* gprev, const float* gcur, const float* zprev,
+static void face_residuals(Mesh& m, Work& w, int gf, const float* gprev, const float* gcur, const float* zprev,
                            const float* zcur, float mu, double relax, double normM, hipStream_t s, AdmmResult& r) {
     hipLaunchKernelGGL(k_resid_face, dim3(gf), dim3(kBlockA), 0, s, (int)m.nf, m.fslot.p, m.farea.p, gprev, gcur, zprev,
-                       zcur, mu, (float)relax, m.w.partial.p);
+                       zcur, mu, (float)relax, w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
     double a, b;
-    reduce_pair(m, gf, s, a, b);
+    reduce_pair(m, w, gf, s, a, b);
     r.rp = sqrt(a) / normM;
     r.rd = sqrt(b) / normM;
 }
 
-AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
+AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
     const int nf = (int)m.nf, ne = (int)m.ne;
-    auto& w = m.w;
     w.g0.alloc((size_t)3 * nf);
     w.g1.alloc((size_t)3 * nf);
     w.z0.alloc((size_t)6 * ne);
@@ -663,7 +661,7 @@ AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
     hipLaunchKernelGGL(k_normM, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.farea.p, w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
     double nm2, dummy;
-    reduce_pair(m, gf, s, nm2, dummy);
+    reduce_pair(m, w, gf, s, nm2, dummy);
     const double normM = sqrt(nm2);
     AdmmResult r;
     const bool fixed = iters > 0;
@@ -705,10 +703,10 @@ AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
             bool done;
             if (monitor) {
                 double delta, dmax;
-                dist_change(m, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax);
+                dist_change(m, w, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax);
                 done = stop.update(delta, dmax, o.tol_admm);
             } else {
-                face_residuals(m, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
+                face_residuals(m, w, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
                 done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;
             }
             if (done) {
@@ -722,7 +720,7 @@ AdmmResult run_admm_face(Mesh& m, int iters, const hg_opts& o, hipStream_t s, in
         r.timed_launches += run_len;
     }
     if (fixed) r.converged = true;
-    if (r.iters > 0) face_residuals(m, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
+    if (r.iters > 0) face_residuals(m, w, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
     HG_CHECK_HIP(hipMemcpyAsync(w.gf.p, ga, (size_t)3 * nf * sizeof(float), hipMemcpyDeviceToDevice, s));
     return r;
 }

@@ -104,9 +104,8 @@ __global__ void k_bfs_parent(int nv, const int32_t* row_ptr, const int32_t* col,
     pslot[j] = bslot;
 }
 
-int run_bfs(Mesh& m, const std::vector<int32_t>& src, hipStream_t s) {
+int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src, hipStream_t s) {
     const int nv = (int)m.nv;
-    auto& w = m.w;
     w.level.alloc(nv);
     w.parent.alloc(nv);
     w.pslot.alloc(nv);

@@ -124,16 +124,15 @@ __global__ void k_diff_logu(int nv, const double* v, const int32_t* e, double* l
     logu[j] = x > 0.0 ? log(x) + (double)e[j] * 0.69314718055994530942 : -INFINITY;
 }
 
-static DiffusionResult run_diffusion_jacobi(Mesh& m, double t, const hg_opts& o, hipStream_t s);
+static DiffusionResult run_diffusion_jacobi(Mesh& m, Work& w, double t, const hg_opts& o, hipStream_t s);
 
 // Schedule choice: LDS-tiled passes (default when every tile's valence fits)
 // or plain global Jacobi sweeps.  Both start from u = 1 at the sources and 0
 // elsewhere and stop on the largest relative change of u.
-DiffusionResult run_diffusion(Mesh& m, const std::vector<int32_t>& src, double t, const hg_opts& o,
+DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src, double t, const hg_opts& o,
                               hipStream_t s) {
     (void)src;   // sources are the level-0 vertices of the preceding BFS
     const int nv = (int)m.nv;
-    auto& w = m.w;
     w.v0.alloc(nv);
     w.v1.alloc(nv);
     w.e0.alloc(nv);
@@ -147,14 +146,13 @@ DiffusionResult run_diffusion(Mesh& m, const std::vector<int32_t>& src, double t
     if (patch) {
         if (!patch_supported(m)) throw Error{HG_E_INVALID_ARG, "tiled schedule needs valence <= 16"};
         const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : 32;
-        return run_diffusion_patch(m, t, o, inner, s);
+        return run_diffusion_patch(m, w, t, o, inner, s);
     }
-    return run_diffusion_jacobi(m, t, o, s);
+    return run_diffusion_jacobi(m, w, t, o, s);
 }
 
-static DiffusionResult run_diffusion_jacobi(Mesh& m, double t, const hg_opts& o, hipStream_t s) {
+static DiffusionResult run_diffusion_jacobi(Mesh& m, Work& w, double t, const hg_opts& o, hipStream_t s) {
     const int nv = (int)m.nv;
-    auto& w = m.w;
     const int grid = grid_for(nv, kBlockD);
     if ((int)w.partial.n < grid + 8) w.partial.alloc((size_t)grid + 8);
     DiffusionResult r;
@@ -184,7 +182,7 @@ static DiffusionResult run_diffusion_jacobi(Mesh& m, double t, const hg_opts& o,
         if (want) {
             r.kernel_ms += rt.stop(s);
             r.timed_launches += run_len;
-            r.res = reduce_partials(m, grid, true, s);
+            r.res = reduce_partials(m, w, grid, true, s);
             if (r.res <= o.tol_u) {
                 r.converged = true;
                 break;
@@ -200,10 +198,10 @@ static DiffusionResult run_diffusion_jacobi(Mesh& m, double t, const hg_opts& o,
     return r;
 }
 
-void diffusion_logu(Mesh& m, hipStream_t s) {
-    m.w.logu.alloc(m.nv);
-    hipLaunchKernelGGL(k_diff_logu, dim3(grid_for(m.nv, kBlockD)), dim3(kBlockD), 0, s, (int)m.nv, m.w.v0.p,
-                       m.w.e0.p, m.w.logu.p);
+void diffusion_logu(Mesh& m, Work& w, hipStream_t s) {
+    w.logu.alloc(m.nv);
+    hipLaunchKernelGGL(k_diff_logu, dim3(grid_for(m.nv, kBlockD)), dim3(kBlockD), 0, s, (int)m.nv, w.v0.p,
+                       w.e0.p, w.logu.p);
     HG_CHECK_HIP(hipGetLastError());
 }
 

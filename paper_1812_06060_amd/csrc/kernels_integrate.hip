@@ -112,9 +112,8 @@ struct IntSums {
     int32_t* jp;
 };
 
-static IntSums integrate_sums(Mesh& m, int form, int depth, const float* xe, const float* g, hipStream_t s) {
+static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, hipStream_t s) {
     const int nv = (int)m.nv;
-    auto& w = m.w;
     w.shi0.alloc(nv);
     w.slo0.alloc(nv);
     w.shi1.alloc(nv);
@@ -140,8 +139,8 @@ static IntSums integrate_sums(Mesh& m, int form, int depth, const float* xe, con
     return IntSums{ha, la, pa};
 }
 
-void integrate(Mesh& m, int form, int depth, float* d_user, hipStream_t s) {
-    IntSums r = integrate_sums(m, form, depth, m.w.xe.p, m.w.gf.p, s);
+void integrate(Mesh& m, Work& w, int form, int depth, float* d_user, hipStream_t s) {
+    IntSums r = integrate_sums(m, w, form, depth, w.xe.p, w.gf.p, s);
     hipLaunchKernelGGL(k_int_out, dim3(grid_for(m.nv, kBlockI)), dim3(kBlockI), 0, s, (int)m.nv, m.perm_v.p, r.jp,
                        r.hi, r.lo, d_user);
     HG_CHECK_HIP(hipGetLastError());
@@ -195,14 +194,13 @@ __global__ void k_reduce_pairs_max(double* partial, int n) {
     }
 }
 
-void dist_change(Mesh& m, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
+void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
                  double& delta, double& dmax) {
     const int nv = (int)m.nv;
-    auto& w = m.w;
     w.dprev.alloc(nv);
     const int grid = grid_for(nv, kBlockI);
     if ((int)w.partial.n < 2 * grid + 8) w.partial.alloc((size_t)2 * grid + 8);
-    IntSums r = integrate_sums(m, form, depth, xe, g, s);
+    IntSums r = integrate_sums(m, w, form, depth, xe, g, s);
     hipLaunchKernelGGL(k_dist_delta, dim3(grid), dim3(kBlockI), 0, s, nv, r.jp, r.hi, r.lo, w.dprev.p,
                        first ? 1 : 0, w.partial.p);
     hipLaunchKernelGGL(k_reduce_pairs_max, dim3(1), dim3(kBlockI), 0, s, w.partial.p, grid);

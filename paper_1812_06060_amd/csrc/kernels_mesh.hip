@@ -38,12 +38,13 @@ __global__ void k_reduce_final(double* partial, int n, int is_max) {
     if (threadIdx.x == 0) partial[n] = acc;
 }
 
-double reduce_partials(Mesh& m, int nblocks, bool is_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, m.w.partial.p, nblocks, is_max ? 1 : 0);
+double reduce_partials(Mesh& m, Work& w, int nblocks, bool is_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, w.partial.p, nblocks, is_max ? 1 : 0);
     HG_CHECK_HIP(hipGetLastError());
-    HG_CHECK_HIP(hipMemcpyAsync(m.w.pinned, m.w.partial.p + nblocks, sizeof(double), hipMemcpyDeviceToHost, s));
+    HG_CHECK_HIP(hipMemcpyAsync(w.pinned, w.partial.p + nblocks, sizeof(double), hipMemcpyDeviceToHost, s));
     HG_CHECK_HIP(hipStreamSynchronize(s));
-    return *m.w.pinned;
+    (void)m;
+    return *w.pinned;
 }
 
 // ------------------------------------------------------------------ geometry
@@ -160,14 +161,14 @@ void geometry_init(Mesh& m, hipStream_t s) {
     hipLaunchKernelGGL(k_face_geom, dim3(gf), dim3(kBlock), 0, s, nf, m.tri.p, m.px.p, m.py.p, m.pz.p, m.farea.p,
                        fcot.p, bad.p, m.w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
-    m.total_area = reduce_partials(m, gf, false, s);
+    m.total_area = reduce_partials(m, m.w, gf, false, s);
     int hbad = 0;
     HG_CHECK_HIP(hipMemcpy(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost));
     if (hbad) throw Error{HG_E_BAD_MESH, "zero-area face"};
     hipLaunchKernelGGL(k_edge_theta, dim3(ge), dim3(kBlock), 0, s, ne, m.ev.p, m.ef.p, m.fslot.p, fcot.p, m.px.p,
                        m.py.p, m.pz.p, theta_e.p, m.ebar.p, m.w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
-    m.hbar = reduce_partials(m, ge, false, s) / (double)ne;
+    m.hbar = reduce_partials(m, m.w, ge, false, s) / (double)ne;
     hipLaunchKernelGGL(k_vertex_fill, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, nv, m.row_ptr.p,
                        m.csr_edge.p, m.ef.p, theta_e.p, m.farea.p, m.theta.p, m.sum_theta.p, m.Av.p);
     HG_CHECK_HIP(hipGetLastError());

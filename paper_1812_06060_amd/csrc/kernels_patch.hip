@@ -244,9 +244,8 @@ bool patch_supported(const Mesh& m) {
 }
 
 // Runs patch passes until the largest relative change over a pass is <= tol.
-DiffusionResult run_diffusion_patch(Mesh& m, double t, const hg_opts& o, int inner, hipStream_t s) {
+DiffusionResult run_diffusion_patch(Mesh& m, Work& w, double t, const hg_opts& o, int inner, hipStream_t s) {
     const int nv = (int)m.nv;
-    auto& w = m.w;
     const int nt = m.n_patches;
     if ((int)w.partial.n < nt + 8) w.partial.alloc((size_t)nt + 8);
     const size_t lds = patch_lds_bytes(m);
@@ -287,7 +286,7 @@ DiffusionResult run_diffusion_patch(Mesh& m, double t, const hg_opts& o, int inn
         if ((it % check) == 0 || it == max_passes) {
             r.kernel_ms += rt.stop(s);
             r.timed_launches += run_len;
-            r.res = reduce_partials(m, nt, true, s);
+            r.res = reduce_partials(m, w, nt, true, s);
             if (r.res <= o.tol_u) {
                 r.converged = true;
                 break;

@@ -91,8 +91,8 @@ static void group_slots(const std::vector<int32_t>& id, std::vector<int32_t>& gp
     if (ns > 0) gptr.push_back(ns);
 }
 
-void build_source_paths(Mesh& m, const std::vector<int32_t>& src_internal, hipStream_t s) {
-    auto& P = m.w.paths;
+void build_source_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s) {
+    auto& P = w.paths;
     P.np = P.ns = P.max_len = 0;
     std::vector<int32_t> todo;
     for (int32_t v : src_internal)
@@ -102,13 +102,13 @@ void build_source_paths(Mesh& m, const std::vector<int32_t>& src_internal, hipSt
     DBuf<int32_t> d_src, d_lvl, d_base, d_len, d_vert, d_edge, d_face;
     DBuf<float> d_sign, d_vec;
     while (todo.size() > 1) {
-        run_bfs(m, {todo[0]}, s);
+        run_bfs(m, w, {todo[0]}, s);
         std::vector<int32_t> rest(todo.begin() + 1, todo.end());
         const int n = (int)rest.size();
         d_src.upload(rest, s);
         d_lvl.alloc(n);
         hipLaunchKernelGGL(k_gather_level, dim3(grid_for(n, kBlockP)), dim3(kBlockP), 0, s, n, d_src.p,
-                           m.w.level.p, d_lvl.p);
+                           w.level.p, d_lvl.p);
         HG_CHECK_HIP(hipGetLastError());
         std::vector<int32_t> lvl(n);
         HG_CHECK_HIP(hipMemcpyAsync(lvl.data(), d_lvl.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -136,9 +136,9 @@ void build_source_paths(Mesh& m, const std::vector<int32_t>& src_internal, hipSt
             d_sign.alloc(ns);
             d_vec.alloc((size_t)3 * ns);
             hipLaunchKernelGGL(k_path_walk, dim3(grid_for(np, 64)), dim3(64), 0, s, np, d_src.p, d_base.p, d_len.p,
-                               m.w.parent.p, d_vert.p);
+                               w.parent.p, d_vert.p);
             hipLaunchKernelGGL(k_path_slots, dim3(grid_for(ns, kBlockP)), dim3(kBlockP), 0, s, ns, d_vert.p,
-                               m.w.parent.p, m.w.pslot.p, m.csr_edge.p, m.ev.p, m.ef.p, m.fslot.p, m.fsign.p,
+                               w.parent.p, w.pslot.p, m.csr_edge.p, m.ev.p, m.ef.p, m.fslot.p, m.fsign.p,
                                m.px.p, m.py.p, m.pz.p, d_edge.p, d_sign.p, d_face.p, d_vec.p);
             HG_CHECK_HIP(hipGetLastError());
             const size_t o = h_edge.size();

@@ -43,13 +43,15 @@ def test_exports_every_declared_symbol(lib):
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include "hgeo.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(hg_opts), sizeof(hg_info),'
-                   ' sizeof(hg_mesh_stats), offsetof(hg_info, bytes_alg), offsetof(hg_opts, mu));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hg_opts), sizeof(hg_info),'
+                   ' sizeof(hg_mesh_stats), offsetof(hg_info, bytes_alg), offsetof(hg_opts, mu),'
+                   ' sizeof(hg_result), offsetof(hg_result, info), sizeof(hg_server_stats_t));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(_hgeo.Opts), C.sizeof(_hgeo.Info), C.sizeof(_hgeo.MeshStats),
-                   _hgeo.Info.bytes_alg.offset, _hgeo.Opts.mu.offset]
+                   _hgeo.Info.bytes_alg.offset, _hgeo.Opts.mu.offset, C.sizeof(_hgeo.Result),
+                   _hgeo.Result.info.offset, C.sizeof(_hgeo.ServerStats)]
 
 
 def test_defaults(lib):
@@ -90,3 +92,13 @@ def test_null_and_empty_arguments(lib):
     assert st == _hgeo.HG_E_INVALID_ARG and "empty" in msg
     st, msg = _create(lib, np.full((3, 3), np.nan), [[0, 1, 2]])
     assert st == _hgeo.HG_E_INVALID_ARG
+
+
+def test_server_rejects_null_arguments(lib):
+    assert lib.hg_server_create(0, 0, C.byref(C.c_void_p())) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_server_create(4, 0, None) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_server_submit(None, None, None, 1, 0.0, None, None, None) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_server_wait(None, None, 0) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_server_stats(None, None) == _hgeo.HG_E_INVALID_ARG
+    lib.hg_server_destroy(None)
+    assert lib.hg_server_clock() > 0.0
