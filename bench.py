@@ -94,6 +94,12 @@ def main():
     ap.add_argument("--cache", default=os.environ.get("HGEO_MESH_CACHE", "/tmp/hgeo_mesh_cache"))
     ap.add_argument("--cpu-sample-level", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving measurement (Poisson stream over a pool of resident meshes)")
+    ap.add_argument("--serve-levels", default="4-8")
+    ap.add_argument("--serve-queries", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=1.5,
+                    help="offered load as a multiple of the plain path's saturation rate")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (scale for PMC byte counters)")
     args = ap.parse_args()
@@ -182,7 +188,9 @@ def main():
                    "stage_ms": {"bfs": last.ms_bfs, "diffusion": last.ms_diffusion,
                                 "normalize": last.ms_normalize, "admm": last.ms_admm,
                                 "integrate": last.ms_integrate},
-                   "mesh_create_s": t_create},
+                   "mesh_create_s": t_create,
+                   "hbm_bytes_per_vertex": (mesh.stats["mesh_bytes"] + last.workspace_bytes) / mesh.nv,
+                   "mesh_bytes": mesh.stats["mesh_bytes"], "query_workspace_bytes": last.workspace_bytes},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_kernel_ms": kms, "alg_bytes_per_launch": int(kbytes)},
@@ -190,6 +198,12 @@ def main():
     }
     mesh.close()
     del out
+    if not args.no_serving:
+        from paper_1812_06060_amd import serving_bench
+        lo, hi = (int(x) for x in args.serve_levels.split("-"))
+        print("[bench] serving ...", file=sys.stderr, flush=True)
+        result["serving"] = serving_bench.run((lo, hi), 32, args.serve_queries, 16, args.serve_rate, 4,
+                                              log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample_level, v.shape[0])
