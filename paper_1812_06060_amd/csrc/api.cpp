@@ -31,7 +31,7 @@ uint64_t Mesh::mesh_bytes() const {
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() + ebar.bytes() +
            tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
-           theta_ell.bytes();
+           theta_ell.bytes() + tile_order.bytes();
 }
 
 Mesh::~Mesh() = default;
@@ -242,6 +242,8 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
             m->ell_ptr.upload(T.ell_ptr, s);
             m->lnb.upload(T.lnb, s);
             m->ell_width.upload(T.ell_width, s);
+            m->color_ptr_host = T.color_ptr;
+            m->tile_order.upload(T.tile_order, s);
             m->w.ensure_pinned();
             geometry_init(*m, s);
         } catch (...) {

@@ -91,6 +91,9 @@ struct HostTopo {
     std::vector<uint16_t> lnb;              // ELL local neighbour slots
     std::vector<int32_t> ell_ptr;           // per patch: offset of its ELL block
     std::vector<uint8_t> ell_width;         // per patch: ELL width
+    // colouring of the tile adjacency graph (tiles sharing a mesh edge get
+    // different colours): tiles of colour c are tile_order[color_ptr[c] ..]
+    std::vector<int32_t> color_ptr, tile_order;
     int max_halo = 0;
     int max_ell_width = 0;
 };
@@ -171,6 +174,8 @@ struct Mesh {
     DBuf<uint16_t> lnb;
     DBuf<uint8_t> ell_width;
     DBuf<double> theta_ell;                 // theta in the tiles' ELL layout
+    std::vector<int32_t> color_ptr_host;    // tile colours (see HostTopo)
+    DBuf<int32_t> tile_order;
 
     // default per-query workspace of the synchronous entry points (also
     // used for the mesh's own reductions)

@@ -232,6 +232,32 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
     hb.clear();
     hb.shrink_to_fit();
 
+    // ---- internal edge order: by owning face (the side-0 face, which has the
+    //      smaller internal id), then slot, so consecutive faces touch mostly
+    //      consecutive edges
+    {
+        std::vector<int32_t> nid(ne, -1);
+        int32_t next = 0;
+        for (int64_t h = 0; h < nh; ++h) {
+            uint32_t sl = T.fslot[h];
+            if ((sl & 1u) == 0u) nid[sl >> 2] = next++;
+        }
+        std::vector<int32_t> ev2(2 * ne), ef2(2 * ne);
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t n = nid[e];
+            ev2[2 * n] = T.ev[2 * e];
+            ev2[2 * n + 1] = T.ev[2 * e + 1];
+            ef2[2 * n] = T.ef[2 * e];
+            ef2[2 * n + 1] = T.ef[2 * e + 1];
+        }
+        T.ev.swap(ev2);
+        T.ef.swap(ef2);
+        for (int64_t h = 0; h < nh; ++h) {
+            uint32_t sl = T.fslot[h];
+            T.fslot[h] = ((uint32_t)nid[sl >> 2] << 2) | (sl & 3u);
+        }
+    }
+
     // ---- canonical edge numbering: sort by (min caller id, max caller id)
     {
         std::vector<int32_t> c2(nv + 1, 0);
@@ -336,6 +362,34 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
         if ((int64_t)T.lnb.size() >= (1ll << 31)) throw Error{HG_E_INVALID_ARG, "tile table too large"};
     }
     T.ell_ptr[np] = (int32_t)T.lnb.size();
+
+    // ---- greedy colouring of the tiles: a tile's halo lies in its
+    //      neighbour tiles, so tiles of one colour never read each other
+    {
+        std::vector<int32_t> tile_of(nv);
+        for (int64_t p = 0; p < np; ++p)
+            for (int32_t v = T.tile_ptr[p]; v < T.tile_ptr[p + 1]; ++v) tile_of[v] = (int32_t)p;
+        std::vector<int32_t> color(np, -1);
+        std::vector<int32_t> mark;
+        int ncol = 0;
+        for (int64_t p = 0; p < np; ++p) {
+            mark.assign(ncol + 1, 0);
+            for (int32_t h = T.halo_ptr[p]; h < T.halo_ptr[p + 1]; ++h) {
+                int32_t c = color[tile_of[T.halo_idx[h]]];
+                if (c >= 0) mark[c] = 1;
+            }
+            int c = 0;
+            while (mark[c]) ++c;
+            color[p] = c;
+            ncol = std::max(ncol, c + 1);
+        }
+        T.color_ptr.assign(ncol + 1, 0);
+        for (int64_t p = 0; p < np; ++p) T.color_ptr[color[p] + 1]++;
+        for (int c = 0; c < ncol; ++c) T.color_ptr[c + 1] += T.color_ptr[c];
+        T.tile_order.assign(np, 0);
+        std::vector<int32_t> pos(T.color_ptr.begin(), T.color_ptr.end() - 1);
+        for (int64_t p = 0; p < np; ++p) T.tile_order[pos[color[p]]++] = (int32_t)p;
+    }
 }
 
 }  // namespace hg
