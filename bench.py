@@ -50,10 +50,11 @@ def _mesh(level: int, cache_dir: str | None):
     return v, f, s
 
 
-def _measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
-    record (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a
-    1 GiB copy), or None when the kernel's source changed since then."""
+def _measured_traffic(kernel: str, per: str = "launch"):
+    """HBM bytes per launch (or per diffusion pass, one launch per tile
+    colour) of `kernel` from the committed rocprofv3 PMC record
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB
+    copy), or None when the kernel's source changed since then."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -64,7 +65,7 @@ def _measured_traffic(kernel: str):
     src = os.path.join(ROOT, rec["src"])
     if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["src_sha256"]:
         return None
-    return rec["bytes_per_launch"]
+    return rec.get("bytes_per_" + per)
 
 
 def cpu_baseline(sample_level: int, full_nv: int):
@@ -166,7 +167,7 @@ def main():
         kbytes = infos[-1].bytes_admm_kernel
     achieved = kbytes / (kms * 1e-3) / 1e9
     kname = "k_patch_pass" if name == "diffusion pass" else ("k_admm_edge" if args.form == "edge" else "k_admm_face")
-    traffic = _measured_traffic(kname)
+    traffic = _measured_traffic(kname, "pass" if kname == "k_patch_pass" else "launch")
     last = infos[-1]
     result = {
         "metric": METRIC,
