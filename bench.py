@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--cache", default=os.environ.get("HGEO_MESH_CACHE", "/tmp/hgeo_mesh_cache"))
     ap.add_argument("--cpu-sample-level", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch measurement (256 small meshes in one solve)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement (Poisson stream over a pool of resident meshes)")
     ap.add_argument("--serve-levels", default="4-8")
@@ -199,6 +201,10 @@ def main():
     }
     mesh.close()
     del out
+    if not args.no_batch:
+        from paper_1812_06060_amd import batch_bench
+        print("[bench] batch of 256 small meshes ...", file=sys.stderr, flush=True)
+        result["batch"] = batch_bench.run(256, args.form, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_serving:
         from paper_1812_06060_amd import serving_bench
         lo, hi = (int(x) for x in args.serve_levels.split("-"))

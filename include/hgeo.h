@@ -90,7 +90,13 @@ typedef struct {
                                each connected component to each other source
                                in it, so that the optimised field gives every
                                source the same distance; 0 = without them */
-    int32_t reserved[5];
+    int32_t t_per_component; /* 1: when t <= 0, each connected component
+                               uses t = m hbar_c^2 with hbar_c its own mean
+                               edge length, so a mesh made of several
+                               meshes side by side (a batch in one solve)
+                               gives each the result it has alone;
+                               0 (default): hbar of the whole mesh */
+    int32_t reserved[4];
 } hg_opts;
 
 /* Per-solve report. */
@@ -102,7 +108,8 @@ typedef struct {
     double res_u;           /* final largest relative sweep change of u */
     double res_primal;      /* final ADMM primal residual (form's scale) */
     double res_dual;        /* final ADMM dual residual (form's scale) */
-    double t;               /* diffusion time used */
+    double t;               /* diffusion time used (of component 0 when
+                               t_per_component is set) */
     float ms_bfs, ms_diffusion, ms_normalize, ms_admm, ms_integrate, ms_total;
     uint64_t bytes_alg;     /* algorithmic HBM bytes of the solve's kernels */
     uint64_t workspace_bytes; /* device bytes held for this mesh's queries */
@@ -125,7 +132,9 @@ typedef struct {
     int32_t max_valence;
     int32_t n_patches;      /* LDS tiles of the patch diffusion schedule */
     uint64_t mesh_bytes;    /* device bytes held by the mesh */
-    int32_t reserved[8];
+    int32_t n_components;   /* connected components (vertex adjacency) */
+    int32_t n_colors;       /* colours of the diffusion tiles */
+    int32_t reserved[6];
 } hg_mesh_stats;
 
 /* Fill *opts with the defaults above. */

@@ -38,7 +38,7 @@ class Opts(C.Structure):
         ("tol_admm", C.c_double), ("max_sweeps", C.c_int32), ("max_admm", C.c_int32),
         ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
         ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("source_paths", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("t_per_component", C.c_int32), ("reserved", C.c_int32 * 4),
     ]
 
 
@@ -64,7 +64,8 @@ class MeshStats(C.Structure):
     _fields_ = [
         ("nv", C.c_int64), ("nf", C.c_int64), ("ne", C.c_int64), ("n_boundary_edges", C.c_int64),
         ("hbar", C.c_double), ("total_area", C.c_double), ("max_valence", C.c_int32),
-        ("n_patches", C.c_int32), ("mesh_bytes", C.c_uint64), ("reserved", C.c_int32 * 8),
+        ("n_patches", C.c_int32), ("mesh_bytes", C.c_uint64), ("n_components", C.c_int32),
+        ("n_colors", C.c_int32), ("reserved", C.c_int32 * 6),
     ]
 
 

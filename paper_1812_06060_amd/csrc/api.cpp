@@ -18,7 +18,7 @@ size_t Work::bytes() const {
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
            h.bytes() + sumz.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
-           src.bytes() + dprev.bytes() + paths.bytes();
+           src.bytes() + dprev.bytes() + paths.bytes() + tcomp.bytes() + tile_t.bytes();
 }
 
 size_t Work::Paths::bytes() const {
@@ -31,7 +31,7 @@ uint64_t Mesh::mesh_bytes() const {
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() + ebar.bytes() +
            tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
-           theta_ell.bytes() + tile_order.bytes();
+           theta_ell.bytes() + tile_order.bytes() + comp_v.bytes() + tile_comp.bytes();
 }
 
 Mesh::~Mesh() = default;
@@ -77,15 +77,25 @@ static hg_opts resolve_opts(const hg_opts* o) {
     if (!(r.mu >= 0.0) || !std::isfinite(r.mu)) throw Error{HG_E_INVALID_ARG, "mu must be >= 0 (0 = auto)"};
     if (!(r.relax > 0.0 && r.relax < 2.0)) throw Error{HG_E_INVALID_ARG, "relax must lie in (0, 2)"};
     if (r.source_paths != 0 && r.source_paths != 1) throw Error{HG_E_INVALID_ARG, "source_paths must be 0 or 1"};
+    if (r.t_per_component != 0 && r.t_per_component != 1)
+        throw Error{HG_E_INVALID_ARG, "t_per_component must be 0 or 1"};
     if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
         throw Error{HG_E_INVALID_ARG, "iteration caps must be positive"};
     return r;
 }
 
-static double resolve_t(const Mesh& m, double t, const hg_opts& o) {
-    if (t > 0.0 && std::isfinite(t)) return t;
-    double mm = (o.m > 0.0 && std::isfinite(o.m)) ? o.m : 1.0;
-    return mm * m.hbar * m.hbar;
+// Diffusion time of each connected component: the given t > 0, else
+// m hbar^2 (Eq. 27) with hbar the mean edge length of the whole mesh or,
+// with opts.t_per_component, of the component itself.
+static std::vector<double> resolve_t(const Mesh& m, double t, const hg_opts& o) {
+    std::vector<double> tc(std::max(1, m.n_comp));
+    const double mm = (o.m > 0.0 && std::isfinite(o.m)) ? o.m : 1.0;
+    for (size_t c = 0; c < tc.size(); ++c) {
+        double h = m.hbar;
+        if (o.t_per_component && c < m.comp_hbar_host.size() && m.comp_hbar_host[c] > 0.0) h = m.comp_hbar_host[c];
+        tc[c] = (t > 0.0 && std::isfinite(t)) ? t : mm * h * h;
+    }
+    return tc;
 }
 
 
@@ -120,7 +130,7 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
     w.ensure_pinned();
     hg_opts o = resolve_opts(opts);
     auto si = map_sources(*m, src, nsrc);
-    double tt = resolve_t(*m, t, o);
+    std::vector<double> tt = resolve_t(*m, t, o);
     StageTimer tm(s);
     tm.mark();
     const bool paths = nsrc > 1 && o.source_paths;
@@ -156,7 +166,7 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
         info->res_u = dr.res;
         info->res_primal = ar.rp;
         info->res_dual = ar.rd;
-        info->t = tt;
+        info->t = tt[0];
         info->ms_bfs = tm.ms(0, 1);
         info->ms_diffusion = tm.ms(1, 2);
         info->ms_normalize = tm.ms(2, 3);
@@ -243,6 +253,10 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
             m->lnb.upload(T.lnb, s);
             m->ell_width.upload(T.ell_width, s);
             m->color_ptr_host = T.color_ptr;
+            m->n_comp = T.n_comp;
+            m->comp_hbar_host = T.comp_hbar;
+            m->comp_v.upload(T.comp, s);
+            m->tile_comp.upload(T.tile_comp, s);
             m->tile_order.upload(T.tile_order, s);
             m->w.ensure_pinned();
             geometry_init(*m, s);
@@ -271,6 +285,8 @@ hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* st) {
         st->max_valence = m->max_valence;
         st->n_patches = m->n_patches;
         st->mesh_bytes = m->mesh_bytes();
+        st->n_components = m->n_comp;
+        st->n_colors = (int32_t)m->color_ptr_host.size() - 1;
         return HG_OK;
     });
 }
@@ -310,7 +326,7 @@ hg_status hg_diffuse(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
         hipStream_t s = (hipStream_t)stream;
         hg_opts o = resolve_opts(opts);
         auto si = map_sources(*m, src, nsrc);
-        double tt = resolve_t(*m, t, o);
+        std::vector<double> tt = resolve_t(*m, t, o);
         int depth = run_bfs(*m, m->w, si, s);
         DiffusionResult r = run_diffusion(*m, m->w, si, tt, o, s);
         diffusion_logu(*m, m->w, s);
@@ -322,7 +338,7 @@ hg_status hg_diffuse(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
             info->sweeps = r.sweeps;
             info->passes = r.passes;
             info->res_u = r.res;
-            info->t = tt;
+            info->t = tt[0];
             info->converged_u = r.converged;
         }
         return r.converged ? HG_OK : fail(HG_E_NOT_CONVERGED, "diffusion sweep cap reached");

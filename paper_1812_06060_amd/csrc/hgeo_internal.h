@@ -94,6 +94,12 @@ struct HostTopo {
     // colouring of the tile adjacency graph (tiles sharing a mesh edge get
     // different colours): tiles of colour c are tile_order[color_ptr[c] ..]
     std::vector<int32_t> color_ptr, tile_order;
+    // connected components: comp[v] per internal vertex, numbered in the
+    // order of their smallest caller vertex id; mean edge length of each;
+    // the component of each tile (tiles are connected)
+    int n_comp = 0;
+    std::vector<int32_t> comp, tile_comp;
+    std::vector<double> comp_hbar;
     int max_halo = 0;
     int max_ell_width = 0;
 };
@@ -118,6 +124,7 @@ struct Work {
     }
     DBuf<int32_t> level, parent, pslot, frontier_a, frontier_b, counters;
     DBuf<double> v0, v1, invD;          // diffusion mantissas, 1/(A + t sum theta)
+    DBuf<double> tcomp, tile_t;         // diffusion time per component and per tile
     DBuf<int32_t> e0, e1;               // diffusion exponents
     DBuf<double> logu;
     DBuf<float> h;                      // [nf*3] internal order
@@ -176,6 +183,10 @@ struct Mesh {
     DBuf<double> theta_ell;                 // theta in the tiles' ELL layout
     std::vector<int32_t> color_ptr_host;    // tile colours (see HostTopo)
     DBuf<int32_t> tile_order;
+    // connected components (see HostTopo)
+    int n_comp = 0;
+    std::vector<double> comp_hbar_host;
+    DBuf<int32_t> comp_v, tile_comp;
 
     // default per-query workspace of the synchronous entry points (also
     // used for the mesh's own reductions)
@@ -196,12 +207,14 @@ struct DiffusionResult {
     int timed_launches = 0;      // launches covered by kernel_ms
     uint64_t bytes_per_pass = 0; // algorithmic HBM bytes of one pass kernel
 };
-DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, double t,
+// t[c]: diffusion time of component c (one entry per connected component)
+DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src_internal,
+                              const std::vector<double>& t,
                               const hg_opts& o, hipStream_t s);
 void diffusion_logu(Mesh& m, Work& w, hipStream_t s);                   // w.logu from (v, e)
 void build_theta_ell(Mesh& m, hipStream_t s);
 bool patch_supported(const Mesh& m);
-DiffusionResult run_diffusion_patch(Mesh& m, Work& w, double t, const hg_opts& o, int inner, hipStream_t s);
+DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inner, hipStream_t s);
 void run_normalize(Mesh& m, Work& w, hipStream_t s);                    // w.h from (v, e)
 void normalize_from_logu(Mesh& m, Work& w, const double* logu_user, hipStream_t s);
 struct AdmmResult {

@@ -39,18 +39,20 @@ __device__ inline double block_max(double v) {
 }
 
 // 1 / (A_j + t sum_k theta_jk), and the initial state (1 at sources, else 0).
-__global__ void k_diff_init(int nv, double t, const double* Av, const double* sum_theta, const int32_t* level,
-                            double* invD, double* v, int32_t* e) {
+__global__ void k_diff_init(int nv, const double* tcomp, const int32_t* comp, const double* Av,
+                            const double* sum_theta, const int32_t* level, double* invD, double* v, int32_t* e) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nv) return;
-    invD[j] = 1.0 / (Av[j] + t * sum_theta[j]);
+    invD[j] = 1.0 / (Av[j] + tcomp[comp[j]] * sum_theta[j]);
     v[j] = level[j] == 0 ? 1.0 : 0.0;
     e[j] = 0;
 }
 
 // One Jacobi sweep.  res: largest relative change |u_new - u_old| / u_new
 // over reachable vertices (1 for a vertex that is still 0 or just reached).
-__global__ void __launch_bounds__(kBlockD) k_diff_sweep(int nv, double t, const int32_t* __restrict__ row_ptr,
+__global__ void __launch_bounds__(kBlockD) k_diff_sweep(int nv, const double* __restrict__ tcomp,
+                                                        const int32_t* __restrict__ comp,
+                                                        const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ theta,
                                                         const double* __restrict__ invD,
@@ -84,7 +86,7 @@ __global__ void __launch_bounds__(kBlockD) k_diff_sweep(int nv, double t, const 
                     const int c = col[k];
                     acc += theta[k] * ldexp(vin[c], ein[c] - m);
                 }
-                double y = t * acc;
+                double y = tcomp[comp[j]] * acc;
                 if (lj == 0) y += ldexp(1.0, -m);
                 y *= invD[j];
                 if (y == 0.0) {
@@ -124,13 +126,18 @@ __global__ void k_diff_logu(int nv, const double* v, const int32_t* e, double* l
     logu[j] = x > 0.0 ? log(x) + (double)e[j] * 0.69314718055994530942 : -INFINITY;
 }
 
-static DiffusionResult run_diffusion_jacobi(Mesh& m, Work& w, double t, const hg_opts& o, hipStream_t s);
+static DiffusionResult run_diffusion_jacobi(Mesh& m, Work& w, const hg_opts& o, hipStream_t s);
+
+__global__ void k_tile_t(int nt, const int32_t* tile_comp, const double* tcomp, double* tile_t) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nt) tile_t[p] = tcomp[tile_comp[p]];
+}
 
 // Schedule choice: LDS-tiled passes (default when every tile's valence fits)
 // or plain global Jacobi sweeps.  Both start from u = 1 at the sources and 0
 // elsewhere and stop on the largest relative change of u.
-DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src, double t, const hg_opts& o,
-                              hipStream_t s) {
+DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src, const std::vector<double>& t,
+                              const hg_opts& o, hipStream_t s) {
     (void)src;   // sources are the level-0 vertices of the preceding BFS
     const int nv = (int)m.nv;
     w.v0.alloc(nv);
@@ -139,19 +146,24 @@ DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src,
     w.e1.alloc(nv);
     w.invD.alloc(nv);
     const int grid = grid_for(nv, kBlockD);
-    hipLaunchKernelGGL(k_diff_init, dim3(grid), dim3(kBlockD), 0, s, nv, t, m.Av.p, m.sum_theta.p, w.level.p,
-                       w.invD.p, w.v0.p, w.e0.p);
+    if ((int)t.size() != m.n_comp) throw Error{HG_E_INVALID_ARG, "one diffusion time per component expected"};
+    w.tcomp.upload(t, s);
+    w.tile_t.alloc(std::max(1, m.n_patches));
+    hipLaunchKernelGGL(k_tile_t, dim3(grid_for(m.n_patches, kBlockD)), dim3(kBlockD), 0, s, m.n_patches,
+                       m.tile_comp.p, w.tcomp.p, w.tile_t.p);
+    hipLaunchKernelGGL(k_diff_init, dim3(grid), dim3(kBlockD), 0, s, nv, w.tcomp.p, m.comp_v.p, m.Av.p,
+                       m.sum_theta.p, w.level.p, w.invD.p, w.v0.p, w.e0.p);
     HG_CHECK_HIP(hipGetLastError());
     const bool patch = o.diffusion_schedule == 2 || (o.diffusion_schedule == 0 && patch_supported(m));
     if (patch) {
         if (!patch_supported(m)) throw Error{HG_E_INVALID_ARG, "tiled schedule needs valence <= 16"};
         const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : 32;
-        return run_diffusion_patch(m, w, t, o, inner, s);
+        return run_diffusion_patch(m, w, o, inner, s);
     }
-    return run_diffusion_jacobi(m, w, t, o, s);
+    return run_diffusion_jacobi(m, w, o, s);
 }
 
-static DiffusionResult run_diffusion_jacobi(Mesh& m, Work& w, double t, const hg_opts& o, hipStream_t s) {
+static DiffusionResult run_diffusion_jacobi(Mesh& m, Work& w, const hg_opts& o, hipStream_t s) {
     const int nv = (int)m.nv;
     const int grid = grid_for(nv, kBlockD);
     if ((int)w.partial.n < grid + 8) w.partial.alloc((size_t)grid + 8);
@@ -172,7 +184,8 @@ static DiffusionResult run_diffusion_jacobi(Mesh& m, Work& w, double t, const hg
             rt.start(s);
             run_len = 0;
         }
-        hipLaunchKernelGGL(k_diff_sweep, dim3(grid), dim3(kBlockD), 0, s, nv, t, m.row_ptr.p, m.col.p, m.theta.p,
+        hipLaunchKernelGGL(k_diff_sweep, dim3(grid), dim3(kBlockD), 0, s, nv, w.tcomp.p, m.comp_v.p, m.row_ptr.p,
+                           m.col.p, m.theta.p,
                            w.invD.p, w.level.p, va, ea, vb, eb, want ? 1 : 0, w.partial.p);
         HG_CHECK_HIP(hipGetLastError());
         ++run_len;

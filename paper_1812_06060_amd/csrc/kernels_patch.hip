@@ -54,7 +54,7 @@ constexpr int kNone = -(1 << 30);   // "no reference exponent yet"
 
 template <int MAXW>
 __global__ void __launch_bounds__(kThreads) k_patch_pass(
-    const int32_t* __restrict__ tile_list, double t, const int32_t* __restrict__ tile_ptr,
+    const int32_t* __restrict__ tile_list, const double* __restrict__ tile_t, const int32_t* __restrict__ tile_ptr,
     const int32_t* __restrict__ halo_ptr,
     const int32_t* __restrict__ halo_idx, const int32_t* __restrict__ ell_ptr,
     const uint8_t* __restrict__ ell_width, const uint16_t* __restrict__ lnb, const double* __restrict__ theta_ell,
@@ -64,6 +64,7 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
     extern __shared__ double lds[];
     __shared__ double shd[kThreads / 64];
     const int p = tile_list[xcd_block(blockIdx.x, gridDim.x)];
+    const double t = tile_t[p];   // the diffusion time of the tile's component
     const int v0 = tile_ptr[p];
     const int np = tile_ptr[p + 1] - v0;
     const int h0 = halo_ptr[p], nh = halo_ptr[p + 1] - h0;
@@ -250,7 +251,7 @@ bool patch_supported(const Mesh& m) {
 }
 
 // Runs patch passes until the largest relative change over a pass is <= tol.
-DiffusionResult run_diffusion_patch(Mesh& m, Work& w, double t, const hg_opts& o, int inner, hipStream_t s) {
+DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inner, hipStream_t s) {
     const int nv = (int)m.nv;
     const int nt = m.n_patches;
     if ((int)w.partial.n < nt + 8) w.partial.alloc((size_t)nt + 8);
@@ -279,7 +280,8 @@ DiffusionResult run_diffusion_patch(Mesh& m, Work& w, double t, const hg_opts& o
         for (size_t c = 0; c + 1 < m.color_ptr_host.size(); ++c) {
             const int c0 = m.color_ptr_host[c], nc = m.color_ptr_host[c + 1] - c0;
 #define HG_PATCH_ARGS                                                                                             \
-    dim3(nc), dim3(kThreads), lds, s, m.tile_order.p + c0, t, m.tile_ptr.p, m.halo_ptr.p, m.halo_idx.p,      \
+    dim3(nc), dim3(kThreads), lds, s, m.tile_order.p + c0, w.tile_t.p, m.tile_ptr.p, m.halo_ptr.p,         \
+        m.halo_idx.p,                                                                                       \
         m.ell_ptr.p, m.ell_width.p, m.lnb.p, m.theta_ell.p, w.invD.p, w.level.p, va, ea, va, ea, inner,       \
         w.partial.p
             if (m.max_ell_width <= 6)

@@ -363,6 +363,52 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
     }
     T.ell_ptr[np] = (int32_t)T.lnb.size();
 
+    // ---- connected components (several meshes may be packed into one)
+    {
+        T.comp.assign(nv, -1);
+        std::vector<int32_t> stack;
+        std::vector<int32_t> first_caller;   // smallest caller id per provisional component
+        int nc = 0;
+        for (int64_t v = 0; v < nv; ++v) {
+            if (T.comp[v] >= 0) continue;
+            int32_t lo = T.perm_v[v];
+            T.comp[v] = nc;
+            stack.assign(1, (int32_t)v);
+            while (!stack.empty()) {
+                int32_t u = stack.back();
+                stack.pop_back();
+                lo = std::min(lo, T.perm_v[u]);
+                for (int32_t k = T.row_ptr[u]; k < T.row_ptr[u + 1]; ++k) {
+                    int32_t x = T.col[k];
+                    if (T.comp[x] < 0) {
+                        T.comp[x] = nc;
+                        stack.push_back(x);
+                    }
+                }
+            }
+            first_caller.push_back(lo);
+            ++nc;
+        }
+        std::vector<int32_t> ord(nc), rank(nc);
+        for (int c = 0; c < nc; ++c) ord[c] = c;
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) { return first_caller[a] < first_caller[b]; });
+        for (int c = 0; c < nc; ++c) rank[ord[c]] = c;
+        for (int64_t v = 0; v < nv; ++v) T.comp[v] = rank[T.comp[v]];
+        T.n_comp = nc;
+        std::vector<double> len(nc, 0.0);
+        std::vector<int64_t> cnt(nc, 0);
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t a = T.ev[2 * e], b = T.ev[2 * e + 1];
+            double dx = T.px[a] - T.px[b], dy = T.py[a] - T.py[b], dz = T.pz[a] - T.pz[b];
+            len[T.comp[a]] += std::sqrt(dx * dx + dy * dy + dz * dz);
+            cnt[T.comp[a]]++;
+        }
+        T.comp_hbar.assign(nc, 0.0);
+        for (int c = 0; c < nc; ++c) T.comp_hbar[c] = cnt[c] ? len[c] / (double)cnt[c] : 0.0;
+        T.tile_comp.assign(np, 0);
+        for (int64_t p = 0; p < np; ++p) T.tile_comp[p] = T.comp[T.tile_ptr[p]];
+    }
+
     // ---- greedy colouring of the tiles: a tile's halo lies in its
     //      neighbour tiles, so tiles of one colour never read each other
     {
