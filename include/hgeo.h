@@ -96,7 +96,13 @@ typedef struct {
                                meshes side by side (a batch in one solve)
                                gives each the result it has alone;
                                0 (default): hbar of the whole mesh */
-    int32_t reserved[4];
+    int32_t use_graphs;     /* 1 (default): the launches between two
+                               convergence checks are captured once into a
+                               HIP graph and replayed; on the null stream the
+                               solve runs on a stream of its own, ordered
+                               after the caller's work on the null stream;
+                               0: plain launches */
+    int32_t reserved[3];
 } hg_opts;
 
 /* Per-solve report. */

@@ -38,7 +38,7 @@ class Opts(C.Structure):
         ("tol_admm", C.c_double), ("max_sweeps", C.c_int32), ("max_admm", C.c_int32),
         ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
         ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("source_paths", C.c_int32),
-        ("t_per_component", C.c_int32), ("reserved", C.c_int32 * 4),
+        ("t_per_component", C.c_int32), ("use_graphs", C.c_int32), ("reserved", C.c_int32 * 3),
     ]
 
 

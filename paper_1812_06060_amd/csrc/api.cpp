@@ -16,14 +16,15 @@ static thread_local std::string g_last_error;
 size_t Work::bytes() const {
     return level.bytes() + parent.bytes() + pslot.bytes() + frontier_a.bytes() + frontier_b.bytes() +
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
-           h.bytes() + sumz.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
+           h.bytes() + sumz.bytes() + sumd.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
            src.bytes() + dprev.bytes() + paths.bytes() + tcomp.bytes() + tile_t.bytes();
 }
 
 size_t Work::Paths::bytes() const {
     return ptr.bytes() + edge.bytes() + face.bytes() + sign.bytes() + vec.bytes() + eg_ptr.bytes() + eg_id.bytes() +
-           eg_slot.bytes() + fg_ptr.bytes() + fg_id.bytes() + fg_slot.bytes() + z.bytes() + seff.bytes();
+           eg_slot.bytes() + fg_ptr.bytes() + fg_id.bytes() + fg_slot.bytes() + z.bytes() + seff.bytes() +
+           zslot.bytes() + gzslot.bytes();
 }
 
 uint64_t Mesh::mesh_bytes() const {
@@ -31,7 +32,7 @@ uint64_t Mesh::mesh_bytes() const {
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() + ebar.bytes() +
            tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
-           theta_ell.bytes() + tile_order.bytes() + comp_v.bytes() + tile_comp.bytes();
+           theta_ell.bytes() + tile_order.bytes() + twin.bytes() + h01.bytes() + comp_v.bytes() + tile_comp.bytes();
 }
 
 Mesh::~Mesh() = default;
@@ -77,6 +78,7 @@ static hg_opts resolve_opts(const hg_opts* o) {
     if (!(r.mu >= 0.0) || !std::isfinite(r.mu)) throw Error{HG_E_INVALID_ARG, "mu must be >= 0 (0 = auto)"};
     if (!(r.relax > 0.0 && r.relax < 2.0)) throw Error{HG_E_INVALID_ARG, "relax must lie in (0, 2)"};
     if (r.source_paths != 0 && r.source_paths != 1) throw Error{HG_E_INVALID_ARG, "source_paths must be 0 or 1"};
+    if (r.use_graphs != 0 && r.use_graphs != 1) throw Error{HG_E_INVALID_ARG, "use_graphs must be 0 or 1"};
     if (r.t_per_component != 0 && r.t_per_component != 1)
         throw Error{HG_E_INVALID_ARG, "t_per_component must be 0 or 1"};
     if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
@@ -129,6 +131,14 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
     Mesh* m = &mesh_ref;
     w.ensure_pinned();
     hg_opts o = resolve_opts(opts);
+    if (!s && o.use_graphs) {
+        // the null stream cannot be captured: run on the workspace's own
+        // stream, after what the caller queued on the null stream
+        w.ensure_stream();
+        HG_CHECK_HIP(hipEventRecord(w.ev, nullptr));
+        HG_CHECK_HIP(hipStreamWaitEvent(w.own_stream, w.ev, 0));
+        s = w.own_stream;
+    }
     auto si = map_sources(*m, src, nsrc);
     std::vector<double> tt = resolve_t(*m, t, o);
     StageTimer tm(s);
@@ -206,6 +216,7 @@ hg_status hg_opts_default(hg_opts* o) {
     o->diffusion_schedule = 0;
     o->inner_sweeps = 0;
     o->source_paths = 1;
+    o->use_graphs = 1;
     return HG_OK;
 }
 
@@ -242,6 +253,8 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
             m->fsign.upload(T.fsign, s);
             m->ev.upload(T.ev, s);
             m->ef.upload(T.ef, s);
+            m->twin.upload(T.twin, s);
+            m->h01.upload(T.h01, s);
             m->patch_size = T.patch_size;
             m->n_patches = (int)(T.halo_ptr.size() - 1);
             m->max_halo = T.max_halo;

@@ -84,6 +84,7 @@ struct HostTopo {
     std::vector<int32_t> ev;                // [ne*2] tail, head (internal ids)
     std::vector<int32_t> ef;                // [ne*2] incident faces, -1 if none
     std::vector<int32_t> perm_e;            // internal edge -> canonical edge
+    std::vector<int32_t> twin, h01;         // per slot: the other face's slot (-1); per edge: its two slots
     // tiles (contiguous internal vertex ranges) and their halos
     int patch_size = 0;
     std::vector<int32_t> tile_ptr;          // [n_tiles+1] first internal vertex
@@ -118,9 +119,19 @@ struct Work {
     Work& operator=(const Work&) = delete;
     ~Work() {
         if (pinned) (void)hipHostFree(pinned);
+        if (ev) (void)hipEventDestroy(ev);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
     }
     void ensure_pinned() {
         if (!pinned) HG_CHECK_HIP(hipHostMalloc(&pinned, 8 * sizeof(double), hipHostMallocDefault));
+    }
+    // a stream of the workspace's own (default priority, non-blocking), used
+    // in place of the null stream, which cannot be captured into a graph
+    hipStream_t own_stream = nullptr;
+    hipEvent_t ev = nullptr;
+    void ensure_stream() {
+        if (!own_stream) HG_CHECK_HIP(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+        if (!ev) HG_CHECK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     }
     DBuf<int32_t> level, parent, pslot, frontier_a, frontier_b, counters;
     DBuf<double> v0, v1, invD;          // diffusion mantissas, 1/(A + t sum theta)
@@ -129,6 +140,7 @@ struct Work {
     DBuf<double> logu;
     DBuf<float> h;                      // [nf*3] internal order
     DBuf<float> sumz;                   // [ne] edge-form target sums
+    DBuf<float> sumd;                   // [3nf] target sum of each slot's edge
     DBuf<float> z0, z1;                 // edge form: zeta [2*ne]; face form: z [2*ne*3]
     DBuf<float> g0, g1;                 // face form gradients [nf*3]
     DBuf<float> xe;                     // [ne] final edge differences (internal)
@@ -149,6 +161,8 @@ struct Work {
         DBuf<int32_t> ptr, edge, face;
         DBuf<float> sign, vec;                  // [ns], [3*ns]
         DBuf<int32_t> eg_ptr, eg_id, eg_slot, fg_ptr, fg_id, fg_slot;
+        DBuf<int2> zslot;                       // per path slot: the edge's two face slots (edge form)
+        DBuf<int2> gzslot;                      // per edge group: the same
         DBuf<float> z;                          // folded copies: [ns] edge form, [3*ns] face form
         DBuf<float> seff;                       // edge form: [ne] effective target sums
         size_t bytes() const;
@@ -174,6 +188,7 @@ struct Mesh {
     DBuf<double> farea;                     // per face (FP64)
     DBuf<int32_t> ev, ef;
     DBuf<float> ebar;                       // [ne*3] unit edge vectors (face form)
+    DBuf<int32_t> twin, h01;
 
     // patch tiles
     int patch_size = 0, n_patches = 0, max_halo = 0, max_ell_width = 0;
@@ -254,6 +269,45 @@ struct RunTimer {
         return ms;
     }
 };
+// A fixed sequence of launches captured once into a HIP graph and replayed
+// (one graph launch instead of many kernel launches).  Only kernel launches
+// are captured.  capture() returns false (and the caller runs the launches
+// directly) where the stream cannot be captured.
+struct GraphChunk {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    bool tried = false;
+    GraphChunk() = default;
+    GraphChunk(const GraphChunk&) = delete;
+    GraphChunk& operator=(const GraphChunk&) = delete;
+    ~GraphChunk() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    template <class F>
+    bool capture(hipStream_t s, F&& enqueue) {
+        tried = true;
+        if (!s) return false;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+        enqueue();
+        hipGraph_t gg = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &gg);
+        if (e != hipSuccess || !gg) {
+            (void)hipGetLastError();
+            return false;
+        }
+        g = gg;
+        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            x = nullptr;
+            return false;
+        }
+        return true;
+    }
+    bool ready() const { return x != nullptr; }
+    void launch(hipStream_t s) { HG_CHECK_HIP(hipGraphLaunch(x, s)); }
+};
+
 // iters > 0: exactly that many iterations.  Otherwise run to convergence:
 // with depth >= 0 (the breadth-first depth of the query) by the change of the
 // integrated distance field (DistStop), else by the paper's residuals.

@@ -16,6 +16,10 @@
 // (zeta = lambda + mu w_hat with w_hat = alpha w + (1 - alpha) x.)
 // Starting from zeta = mu * (mean target) reproduces the paper's
 // initialisation (lambda = 0, x = mean of targets).
+// Layout: zeta is kept per face slot (3f + k), with a copy of S_e per slot
+// and the slot of the edge's other face ("twin", -1 on the boundary), so a
+// face reads and writes its three slots contiguously and gathers only the
+// twins' zeta: the iteration streams 49 bytes per face.
 //
 // Face form.  Per auxiliary copy k of face i keep z = y + lambda/(mu alpha_i);
 // then q_k = g_i - lambda_k/(mu alpha_i) = 2 g_i - z_k, the Y-update gives
@@ -155,13 +159,18 @@ void normalize_from_logu(Mesh& m, Work& w, const double* logu_user, hipStream_t 
 }
 
 // ---------------------------------------------------------------- edge form
-__global__ void k_zeta_init(int ne, const int32_t* ef, const float* sumz, float mu, float* zeta) {
+__global__ void k_zeta_init(int ne, const int32_t* h01, const float* sumz, float mu, float* zeta, float* sumd) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    float nh = ef[2 * e + 1] >= 0 ? 2.f : 1.f;
+    const int h0 = h01[2 * e], h1 = h01[2 * e + 1];
+    float nh = h1 >= 0 ? 2.f : 1.f;
     float z = mu * (sumz[e] / nh);
-    zeta[2 * e] = z;
-    zeta[2 * e + 1] = ef[2 * e + 1] >= 0 ? z : 0.f;
+    zeta[h0] = z;
+    sumd[h0] = sumz[e];
+    if (h1 >= 0) {
+        zeta[h1] = z;
+        sumd[h1] = sumz[e];
+    }
 }
 
 __device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1mu) {
@@ -169,21 +178,18 @@ __device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1m
     return bnd ? (S + z0) * inv1mu : 0.5f * (S + z0 + z1) * inv1mu;
 }
 
-__global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const uint32_t* __restrict__ fslot,
-                                                       const uint8_t* __restrict__ fsign,
-                                                       const float* __restrict__ sumz,
-                                                       const float* __restrict__ zin, float* __restrict__ zout,
-                                                       float mu, float inv1mu, float mu_relax) {
-    int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    uint32_t sl[3];
+__device__ inline void admm_edge_face(int f, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
+                                      const float* __restrict__ sumd, const float* __restrict__ zin,
+                                      float* __restrict__ zout, float mu, float inv1mu, float mu_relax) {
     float x[3], zo[3];
+    int tw[3];
     for (int k = 0; k < 3; ++k) {
-        sl[k] = fslot[3 * f + k];
-        int e = slot_edge(sl[k]);
-        float2 zz = *reinterpret_cast<const float2*>(zin + 2 * e);
-        x[k] = edge_x(sumz[e], zz.x, zz.y, slot_bnd(sl[k]), inv1mu);
-        zo[k] = slot_side(sl[k]) ? zz.y : zz.x;
+        tw[k] = twin[3 * f + k];
+        zo[k] = zin[3 * f + k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        const float tz = tw[k] >= 0 ? zin[tw[k]] : 0.f;
+        x[k] = edge_x(sumd[3 * f + k], zo[k], tz, tw[k] < 0, inv1mu);
     }
     uint8_t sg = fsign[f];
     float q[3], v[3];
@@ -196,24 +202,33 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const uint32_t* _
     qv *= (1.f / 3.f);
     for (int k = 0; k < 3; ++k) {
         float w = v[k] - qv * q[k];
-        zout[2 * slot_edge(sl[k]) + slot_side(sl[k])] = zo[k] + mu_relax * (w - x[k]);
+        zout[3 * f + k] = zo[k] + mu_relax * (w - x[k]);
     }
+}
+
+__global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const int32_t* __restrict__ twin,
+                                                       const uint8_t* __restrict__ fsign,
+                                                       const float* __restrict__ sumd,
+                                                       const float* __restrict__ zin, float* __restrict__ zout,
+                                                       float mu, float inv1mu, float mu_relax) {
+    int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    admm_edge_face(f, twin, fsign, sumd, zin, zout, mu, inv1mu, mu_relax);
 }
 
 // r_p = w' - x' with w' = x + (zeta' - zeta)/(mu alpha) (from the zeta
 // update), r_d = mu (x' - x).  partial = (sum r_p^2, sum r_d^2) per block.
-__global__ void k_resid_edge(int nf, const uint32_t* fslot, const float* sumz, const float* za, const float* zb,
+__global__ void k_resid_edge(int nf, const int32_t* twin, const float* sumz, const float* za, const float* zb,
                              float mu, float inv1mu, float mu_relax, double* partial) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     double rp = 0.0, rd = 0.0;
     if (f < nf) {
         for (int k = 0; k < 3; ++k) {
-            uint32_t sl = fslot[3 * f + k];
-            int e = slot_edge(sl), side = slot_side(sl), bnd = slot_bnd(sl);
-            float S = sumz[e];
-            float xa = edge_x(S, za[2 * e], za[2 * e + 1], bnd, inv1mu);
-            float xb = edge_x(S, zb[2 * e], zb[2 * e + 1], bnd, inv1mu);
-            double wn = (double)xa + ((double)zb[2 * e + side] - (double)za[2 * e + side]) / mu_relax;
+            const int h = 3 * f + k, t = twin[h];
+            const int bnd = t < 0;
+            float xa = edge_x(sumz[h], za[h], bnd ? 0.f : za[t], bnd, inv1mu);
+            float xb = edge_x(sumz[h], zb[h], bnd ? 0.f : zb[t], bnd, inv1mu);
+            double wn = (double)xa + ((double)zb[h] - (double)za[h]) / mu_relax;
             double p = wn - (double)xb;
             double d = (double)mu * ((double)xb - (double)xa);
             rp += p * p;
@@ -242,13 +257,13 @@ __global__ void k_reduce_pairs(double* partial, int n) {
     }
 }
 
-__global__ void k_edge_x(int ne, const uint32_t* dummy, const int32_t* ef, const float* sumz, const float* z,
+__global__ void k_edge_x(int ne, const int32_t* h01, const int32_t* ef, const float* sumz, const float* z,
                          float inv1mu, float* x) {
-    (void)dummy;
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     int bnd = ef[2 * e + 1] < 0;
-    x[e] = edge_x(sumz[e], z[2 * e], z[2 * e + 1], bnd, inv1mu);
+    const int h0 = h01[2 * e], h1 = h01[2 * e + 1];
+    x[e] = edge_x(sumz[e], z[h0], h1 >= 0 ? z[h1] : 0.f, bnd, inv1mu);
 }
 
 // ------------------------------------------------- source paths (Eqs. 24-25)
@@ -296,45 +311,67 @@ __global__ void k_path_edge_zinit(int ns, const int32_t* edge, const int32_t* ef
     zp[k] = mu * (sumz[e] / nh);   // kappa = 0, v = x = mean target
 }
 
-__global__ void __launch_bounds__(kBlockPath) k_path_edge_proj(const int32_t* __restrict__ ptr,
-                                                               const int32_t* __restrict__ edge,
-                                                               const float* __restrict__ sign,
-                                                               const int32_t* __restrict__ ef,
-                                                               const float* __restrict__ seff,
-                                                               const float* __restrict__ zin, float* zp, float mu,
-                                                               float inv1mu, float mu_relax) {
-    __shared__ double sh[kBlockPath / 64];
-    const int b = ptr[blockIdx.x], n = ptr[blockIdx.x + 1] - b;
+__device__ inline void path_edge_proj_block(int p, const int32_t* __restrict__ ptr, const int32_t* __restrict__ edge,
+                                            const float* __restrict__ sign, const int2* __restrict__ zslot,
+                                            const float* __restrict__ seff, const float* __restrict__ zin,
+                                            float* zp, float mu, float inv1mu, float mu_relax, double* sh) {
+    const int b = ptr[p], n = ptr[p + 1] - b;
     double acc = 0.0;
     for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
-        int e = edge[k];
-        float x = edge_x(seff[e], zin[2 * e], zin[2 * e + 1], ef[2 * e + 1] < 0, inv1mu);
+        const int e = edge[k];
+        const int2 hh = zslot[k];
+        float x = edge_x(seff[e], zin[hh.x], hh.y >= 0 ? zin[hh.y] : 0.f, hh.y < 0, inv1mu);
         acc += (double)sign[k] * (double)(2.f * x - zp[k] / mu);
     }
     const float c = (float)(block_sum_all(acc, sh) / n);
     for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
-        int e = edge[k];
-        float x = edge_x(seff[e], zin[2 * e], zin[2 * e + 1], ef[2 * e + 1] < 0, inv1mu);
+        const int e = edge[k];
+        const int2 hh = zslot[k];
+        float x = edge_x(seff[e], zin[hh.x], hh.y >= 0 ? zin[hh.y] : 0.f, hh.y < 0, inv1mu);
         float t = 2.f * x - zp[k] / mu;
         float v = t - c * sign[k];
         zp[k] = zp[k] + mu_relax * (v - x);
     }
 }
 
+// The face update and the path projections of one iteration in one launch:
+// blocks [0, np) project one path each -- long, latency-bound blocks, so
+// they are dispatched first and overlap the many short face blocks
+// [np, np + nfb) (both read the previous state only and write disjoint
+// outputs).
+__global__ void __launch_bounds__(kBlockA) k_admm_edge_paths(
+    int nf, int nfb, int np, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
+    const float* __restrict__ sumd, const float* __restrict__ zin, float* __restrict__ zout,
+    const int32_t* __restrict__ ptr, const int32_t* __restrict__ edge, const float* __restrict__ sign,
+    const int2* __restrict__ zslot, const float* __restrict__ seff, float* zp, float mu, float inv1mu,
+    float mu_relax) {
+    __shared__ double sh[kBlockA / 64];
+    if ((int)blockIdx.x < np) {
+        path_edge_proj_block((int)blockIdx.x, ptr, edge, sign, zslot, seff, zin, zp, mu, inv1mu, mu_relax, sh);
+        return;
+    }
+    const int f = xcd_block((int)blockIdx.x - np, nfb) * blockDim.x + threadIdx.x;
+    if (f < nf) admm_edge_face(f, twin, fsign, sumd, zin, zout, mu, inv1mu, mu_relax);
+}
+
 __global__ void k_path_edge_fix(int ng, const int32_t* gptr, const int32_t* gid, const int32_t* gslot,
-                                const float* zp, const float* sumz, const float* zout, const int32_t* ef, double mu,
-                                float* seff) {
+                                const float* zp, const float* sumz, const float* zout, const int2* gzslot,
+                                double mu, float* seff, float* sumd) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const int e = gid[g];
     double P = 0.0;
     for (int j = gptr[g]; j < gptr[g + 1]; ++j) P += zp[gslot[j]];
     const int n = gptr[g + 1] - gptr[g];
-    const bool bnd = ef[2 * e + 1] < 0;
-    const double Z = (double)zout[2 * e] + (bnd ? 0.0 : (double)zout[2 * e + 1]);
+    const int h0 = gzslot[g].x, h1 = gzslot[g].y;
+    const bool bnd = h1 < 0;
+    const double Z = (double)zout[h0] + (bnd ? 0.0 : (double)zout[h1]);
     const double D0 = (bnd ? 1.0 : 2.0) * (1.0 + mu);
     const double x = ((double)sumz[e] + P + Z) / (D0 + mu * n);
-    seff[e] = (float)(x * D0 - Z);
+    const float sp = (float)(x * D0 - Z);
+    seff[e] = sp;
+    sumd[h0] = sp;   // the face kernel reads S' per slot
+    if (!bnd) sumd[h1] = sp;
 }
 
 __global__ void k_path_face_zinit(int ns, const int32_t* face, const float* h, float* zp) {
@@ -414,15 +451,16 @@ static void reduce_pair(Mesh& m, Work& w, int nblocks, hipStream_t s, double& a,
 AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
     const int nf = (int)m.nf, ne = (int)m.ne;
     w.sumz.alloc(ne);
-    w.z0.alloc((size_t)2 * ne);
-    w.z1.alloc((size_t)2 * ne);
+    w.z0.alloc((size_t)3 * nf);
+    w.z1.alloc((size_t)3 * nf);
+    w.sumd.alloc((size_t)3 * nf);
     w.xe.alloc(ne);
     const float mu = (float)o.mu, inv1mu = 1.0f / (1.0f + mu), mu_relax = (float)(o.mu * o.relax);
     const int gf = grid_for(nf, kBlockA), ge = grid_for(ne, kBlockA);
     if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
     hipLaunchKernelGGL(k_edge_targets, dim3(ge), dim3(kBlockA), 0, s, ne, m.ev.p, m.ef.p, m.px.p, m.py.p, m.pz.p,
                        w.h.p, w.sumz.p);
-    hipLaunchKernelGGL(k_zeta_init, dim3(ge), dim3(kBlockA), 0, s, ne, m.ef.p, w.sumz.p, mu, w.z0.p);
+    hipLaunchKernelGGL(k_zeta_init, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, w.sumz.p, mu, w.z0.p, w.sumd.p);
     HG_CHECK_HIP(hipGetLastError());
     auto& P = w.paths;
     use_paths = use_paths && P.np > 0;
@@ -443,9 +481,10 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
     float* za = w.z0.p;
     float* zb = w.z1.p;
-    // algorithmic bytes of one iteration: fslot + sign per face, the zeta pair
-    // and target sum per edge read once, one zeta written per face slot
-    r.bytes_per_iter = (uint64_t)13 * nf + (uint64_t)12 * ne + (uint64_t)12 * nf;
+    // algorithmic bytes of one iteration: per face its three zeta, S copies
+    // and twin slots and its sign byte read, its three zeta written (the
+    // twins' zeta are the same array, read by their own faces)
+    r.bytes_per_iter = (uint64_t)49 * nf;
     // path kernels: per slot its edge, sign, copy (read + write), the edge's
     // zeta pair, S' and ef; per group its slot list, copies, S, zeta pair, S'
     if (use_paths) r.bytes_per_iter += (uint64_t)32 * P.ns + (uint64_t)8 * P.ns + (uint64_t)28 * P.ng_edge;
@@ -454,37 +493,64 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     DistStop stop;
     // residuals as rms over the 3|F| copies, r_p / hbar and r_d / (mu hbar)
     auto residuals = [&](const float* prev, const float* cur) {
-        hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, S, prev, cur, mu,
+        hipLaunchKernelGGL(k_resid_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.twin.p, w.sumd.p, prev, cur, mu,
                            inv1mu, mu_relax, w.partial.p);
         double a, b;
         reduce_pair(m, w, gf, s, a, b);
         r.rp = sqrt(a) / (sqrt(3.0 * (double)nf) * m.hbar);
         r.rd = sqrt(b) / (sqrt(3.0 * (double)nf) * m.hbar * o.mu);
     };
-    for (int it = 1; it <= cap; ++it) {
-        if (!rt.open) {
-            rt.start(s);
-            run_len = 0;
-        }
-        hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.fsign.p, S, za, zb, mu,
-                           inv1mu, mu_relax);
-        if (use_paths) {
-            hipLaunchKernelGGL(k_path_edge_proj, dim3(P.np), dim3(kBlockPath), 0, s, P.ptr.p, P.edge.p, P.sign.p,
-                               m.ef.p, S, za, P.z.p, mu, inv1mu, mu_relax);
+    // one iteration from state zi into zo (the face kernel, then the path
+    // constraint groups)
+    auto iterate = [&](float* zi, float* zo) {
+        if (!use_paths) {
+            hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.twin.p, m.fsign.p, w.sumd.p, zi, zo,
+                               mu, inv1mu, mu_relax);
+        } else {
+            hipLaunchKernelGGL(k_admm_edge_paths, dim3(gf + P.np), dim3(kBlockA), 0, s, nf, gf, P.np, m.twin.p, m.fsign.p,
+                               w.sumd.p, zi, zo, P.ptr.p, P.edge.p, P.sign.p, P.zslot.p, S, P.z.p, mu, inv1mu,
+                               mu_relax);
             hipLaunchKernelGGL(k_path_edge_fix, dim3(grid_for(P.ng_edge, kBlockA)), dim3(kBlockA), 0, s, P.ng_edge,
-                               P.eg_ptr.p, P.eg_id.p, P.eg_slot.p, P.z.p, w.sumz.p, zb, m.ef.p, (double)mu, P.seff.p);
+                               P.eg_ptr.p, P.eg_id.p, P.eg_slot.p, P.z.p, w.sumz.p, zo, P.gzslot.p, (double)mu, P.seff.p,
+                               w.sumd.p);
+        }
+    };
+    // runs of `check` iterations between two checks; with an even count the
+    // two buffers are back in their roles after a run, so one captured graph
+    // serves every full run
+    GraphChunk graph;
+    const bool graphs = !fixed && o.use_graphs && (check % 2) == 0;
+    int it = 0;
+    while (it < cap) {
+        const int n = std::min(check - it % check, cap - it);
+        rt.start(s);
+        if (graphs && n == check && !graph.tried)
+            graph.capture(s, [&] {
+                float *a = za, *b = zb;
+                for (int k = 0; k < n; ++k) {
+                    iterate(a, b);
+                    std::swap(a, b);
+                }
+            });
+        if (graphs && n == check && graph.ready()) {
+            graph.launch(s);
+        } else {
+            for (int k = 0; k < n; ++k) {
+                iterate(za, zb);
+                std::swap(za, zb);   // za is now the current state, zb the previous
+            }
         }
         HG_CHECK_HIP(hipGetLastError());
-        ++run_len;
+        it += n;
         r.iters = it;
-        std::swap(za, zb);   // za is now the current state, zb the previous
+        run_len = n;
+        r.kernel_ms += rt.stop(s);
+        r.timed_launches += run_len;
         const bool want = (it % check) == 0 || it == cap;
         if (!fixed && want) {
-            r.kernel_ms += rt.stop(s);
-            r.timed_launches += run_len;
             bool done;
             if (monitor) {
-                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, S, za, inv1mu,
+                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
                                    w.xe.p);
                 double delta, dmax;
                 dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax);
@@ -505,10 +571,10 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     }
     if (fixed) r.converged = true;
     if (r.iters > 0) residuals(zb, za);
-    hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, nullptr, m.ef.p, S, za, inv1mu, w.xe.p);
+    hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu, w.xe.p);
     HG_CHECK_HIP(hipGetLastError());
     if (za != w.z0.p)
-        HG_CHECK_HIP(hipMemcpyAsync(w.z0.p, za, (size_t)2 * ne * sizeof(float), hipMemcpyDeviceToDevice, s));
+        HG_CHECK_HIP(hipMemcpyAsync(w.z0.p, za, (size_t)3 * nf * sizeof(float), hipMemcpyDeviceToDevice, s));
     return r;
 }
 
@@ -678,28 +744,50 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     RunTimer rt;
     int run_len = 0;
     DistStop stop;
-    for (int it = 1; it <= cap; ++it) {
-        if (!rt.open) {
-            rt.start(s);
-            run_len = 0;
-        }
+    auto iterate = [&](float* gi, float* zi, float* go, float* zo) {
         hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.ef.p, m.ebar.p, m.farea.p,
-                           w.h.p, ga, za, gb, zb, mu, (float)o.relax);
+                           w.h.p, gi, zi, go, zo, mu, (float)o.relax);
         if (use_paths) {
             hipLaunchKernelGGL(k_path_face_proj, dim3(P.np), dim3(kBlockPath), 0, s, P.ptr.p, P.face.p, P.vec.p,
-                               m.farea.p, ga, P.z.p, (float)o.relax);
+                               m.farea.p, gi, P.z.p, (float)o.relax);
             hipLaunchKernelGGL(k_path_face_fix, dim3(grid_for(P.ng_face, kBlockA)), dim3(kBlockA), 0, s, P.ng_face,
-                               P.fg_ptr.p, P.fg_id.p, P.fg_slot.p, P.z.p, m.fslot.p, zb, w.h.p, mu, gb);
+                               P.fg_ptr.p, P.fg_id.p, P.fg_slot.p, P.z.p, m.fslot.p, zo, w.h.p, mu, go);
+        }
+    };
+    // runs of `check` iterations between checks, one captured graph for every
+    // full run (an even count leaves the double buffers in their roles)
+    GraphChunk graph;
+    const bool graphs = !fixed && o.use_graphs && (check % 2) == 0;
+    int it = 0;
+    while (it < cap) {
+        const int n = std::min(check - it % check, cap - it);
+        rt.start(s);
+        if (graphs && n == check && !graph.tried)
+            graph.capture(s, [&] {
+                float *g1 = ga, *g2 = gb, *z1 = za, *z2 = zb;
+                for (int k = 0; k < n; ++k) {
+                    iterate(g1, z1, g2, z2);
+                    std::swap(g1, g2);
+                    std::swap(z1, z2);
+                }
+            });
+        if (graphs && n == check && graph.ready()) {
+            graph.launch(s);
+        } else {
+            for (int k = 0; k < n; ++k) {
+                iterate(ga, za, gb, zb);
+                std::swap(ga, gb);   // (ga, za) is now the current state, (gb, zb) the previous
+                std::swap(za, zb);
+            }
         }
         HG_CHECK_HIP(hipGetLastError());
-        ++run_len;
+        it += n;
         r.iters = it;
-        std::swap(ga, gb);   // (ga, za) is now the current state, (gb, zb) the previous
-        std::swap(za, zb);
+        run_len = n;
+        r.kernel_ms += rt.stop(s);
+        r.timed_launches += run_len;
         const bool want = (it % check) == 0 || it == cap;
         if (!fixed && want) {
-            r.kernel_ms += rt.stop(s);
-            r.timed_launches += run_len;
             bool done;
             if (monitor) {
                 double delta, dmax;

@@ -261,29 +261,20 @@ DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inne
     // list, 1/D and level, (v, e) read for tile and halo, (v, e) written
     r.bytes_per_pass = (uint64_t)m.lnb.n * (2 + 8) + (uint64_t)m.halo_idx.n * (4 + 16) +
                        (uint64_t)nv * (8 + 4 + 12 + 12) + (uint64_t)nt * 17;
-    double* va = w.v0.p;
-    double* vb = w.v1.p;
+    double* va = w.v0.p;   // updated in place
     int32_t* ea = w.e0.p;
-    int32_t* eb = w.e1.p;
     const int check = std::max(1, o.check_every / std::max(1, inner / 4));
-    RunTimer rt;
-    int run_len = 0;
     const int max_passes = std::max(1, o.max_sweeps / std::max(1, inner));
-    for (int it = 1; it <= max_passes; ++it) {
-        if (!rt.open) {
-            rt.start(s);
-            run_len = 0;
-        }
-        // one pass = the colours in order, each updating its tiles in place
-        // from the latest values of the others (block Gauss-Seidel between
-        // tiles, Jacobi within a colour: tiles of one colour are independent)
+    // one pass = the colours in order, each updating its tiles in place from
+    // the latest values of the others (block Gauss-Seidel between tiles,
+    // Jacobi within a colour: tiles of one colour are independent)
+    auto pass = [&] {
         for (size_t c = 0; c + 1 < m.color_ptr_host.size(); ++c) {
             const int c0 = m.color_ptr_host[c], nc = m.color_ptr_host[c + 1] - c0;
 #define HG_PATCH_ARGS                                                                                             \
     dim3(nc), dim3(kThreads), lds, s, m.tile_order.p + c0, w.tile_t.p, m.tile_ptr.p, m.halo_ptr.p,         \
-        m.halo_idx.p,                                                                                       \
-        m.ell_ptr.p, m.ell_width.p, m.lnb.p, m.theta_ell.p, w.invD.p, w.level.p, va, ea, va, ea, inner,       \
-        w.partial.p
+        m.halo_idx.p, m.ell_ptr.p, m.ell_width.p, m.lnb.p, m.theta_ell.p, w.invD.p, w.level.p, va, ea, va, ea, \
+        inner, w.partial.p
             if (m.max_ell_width <= 6)
                 hipLaunchKernelGGL(k_patch_pass<6>, HG_PATCH_ARGS);
             else if (m.max_ell_width <= 8)
@@ -291,24 +282,35 @@ DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inne
             else
                 hipLaunchKernelGGL(k_patch_pass<16>, HG_PATCH_ARGS);
 #undef HG_PATCH_ARGS
-            HG_CHECK_HIP(hipGetLastError());
         }
-        ++run_len;
+    };
+    // runs of `check` passes between checks, captured once into a graph
+    GraphChunk graph;
+    RunTimer rt;
+    int it = 0;
+    while (it < max_passes) {
+        const int n = std::min(check, max_passes - it);
+        rt.start(s);
+        if (o.use_graphs && n == check && !graph.tried)
+            graph.capture(s, [&] {
+                for (int k = 0; k < n; ++k) pass();
+            });
+        if (o.use_graphs && n == check && graph.ready()) {
+            graph.launch(s);
+        } else {
+            for (int k = 0; k < n; ++k) pass();
+        }
+        HG_CHECK_HIP(hipGetLastError());
+        it += n;
         r.passes = it;
         r.sweeps = it * inner;
-        if ((it % check) == 0 || it == max_passes) {
-            r.kernel_ms += rt.stop(s);
-            r.timed_launches += run_len;
-            r.res = reduce_partials(m, w, nt, true, s);
-            if (r.res <= o.tol_u) {
-                r.converged = true;
-                break;
-            }
+        r.kernel_ms += rt.stop(s);
+        r.timed_launches += n;
+        r.res = reduce_partials(m, w, nt, true, s);
+        if (r.res <= o.tol_u) {
+            r.converged = true;
+            break;
         }
-    }
-    if (va != w.v0.p) {
-        HG_CHECK_HIP(hipMemcpyAsync(w.v0.p, va, (size_t)nv * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HG_CHECK_HIP(hipMemcpyAsync(w.e0.p, ea, (size_t)nv * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
     return r;
 }

@@ -73,6 +73,14 @@ __global__ void k_path_slots(int ns, const int32_t* vert, const int32_t* parent,
     vec[3 * k + 2] = (float)(pz[v] - pz[p]);
 }
 
+// the two face slots (3f + k) of each listed edge (-1 for a missing second face)
+__global__ void k_edge_slots(int n, const int32_t* edge, const int32_t* h01, int2* out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e = edge[i];
+    out[i] = make_int2(h01[2 * e], h01[2 * e + 1]);
+}
+
 // CSR of the slots per distinct id (edge or face), slots in increasing order.
 static void group_slots(const std::vector<int32_t>& id, std::vector<int32_t>& gptr, std::vector<int32_t>& gid,
                         std::vector<int32_t>& gslot) {
@@ -172,6 +180,13 @@ void build_source_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_intern
     P.eg_ptr.upload(gptr, s);
     P.eg_id.upload(gid, s);
     P.eg_slot.upload(gslot, s);
+    P.zslot.alloc(P.ns);
+    hipLaunchKernelGGL(k_edge_slots, dim3(grid_for(P.ns, kBlockP)), dim3(kBlockP), 0, s, P.ns, P.edge.p, m.h01.p,
+                       P.zslot.p);
+    P.gzslot.alloc(P.ng_edge);
+    hipLaunchKernelGGL(k_edge_slots, dim3(grid_for(P.ng_edge, kBlockP)), dim3(kBlockP), 0, s, P.ng_edge,
+                       P.eg_id.p, m.h01.p, P.gzslot.p);
+    HG_CHECK_HIP(hipGetLastError());
     group_slots(h_face, gptr, gid, gslot);
     P.ng_face = (int)gid.size();
     P.fg_ptr.upload(gptr, s);

@@ -258,6 +258,21 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
         }
     }
 
+    // ---- slot twins
+    {
+        T.h01.assign(2 * ne, -1);
+        for (int64_t h = 0; h < nh; ++h) {
+            uint32_t sl = T.fslot[h];
+            T.h01[2 * (sl >> 2) + (sl & 1u)] = (int32_t)h;
+        }
+        T.twin.assign(nh, -1);
+        for (int64_t e = 0; e < ne; ++e)
+            if (T.h01[2 * e + 1] >= 0) {
+                T.twin[T.h01[2 * e]] = T.h01[2 * e + 1];
+                T.twin[T.h01[2 * e + 1]] = T.h01[2 * e];
+            }
+    }
+
     // ---- canonical edge numbering: sort by (min caller id, max caller id)
     {
         std::vector<int32_t> c2(nv + 1, 0);

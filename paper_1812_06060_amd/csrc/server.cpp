@@ -50,7 +50,7 @@ static uint64_t work_estimate(const Mesh& m, int form, int nsrc) {
                  + 4 * ne + 12 * nf           // xe, gf
                  + 16 * nv + 8 * nv + 4 * nv; // shi/slo pairs, jp0/jp1, dprev
     if (form == HG_FORM_EDGE)
-        b += 16 * ne;                          // zeta pair, double-buffered
+        b += 36 * nf;                          // zeta per slot (double-buffered) and S per slot
     else
         b += 48 * ne + 24 * nf;                // z copies and g, double-buffered
     if (nsrc > 1) b += (uint64_t)nsrc * 4096 * 64 + 8 * ne;
