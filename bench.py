@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--cache", default=os.environ.get("HGEO_MESH_CACHE", "/tmp/hgeo_mesh_cache"))
     ap.add_argument("--cpu-sample-level", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default diffusion schedule instead of tuning it on the first query")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch measurement (256 small meshes in one solve)")
     ap.add_argument("--no-serving", action="store_true",
@@ -137,6 +139,16 @@ def main():
     print(f"[bench] mesh_create {t_create:.2f}s hbar={mesh.hbar:.4e}", file=sys.stderr, flush=True)
     opts = hg.default_opts(formulation=args.form)
     out = torch.empty(mesh.nv, dtype=torch.float32, device="cuda")
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tune = mesh.autotune(src, 0.0, opts)
+        ch = tune["candidates"][tune["chosen"]]
+        print(f"[bench] autotune ({time.perf_counter() - t0:.1f}s): " +
+              ", ".join(f"{'tiles/' + str(c['inner_sweeps']) if c['schedule'] == 2 else 'jacobi'}="
+                        f"{c['ms']:.0f}ms" for c in tune["candidates"]) +
+              f" -> {'tiles/' + str(ch['inner_sweeps']) if ch['schedule'] == 2 else 'jacobi'}",
+              file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         _, info = mesh.solve(src, 0.0, opts, out=out)
@@ -192,6 +204,8 @@ def main():
                                 "normalize": last.ms_normalize, "admm": last.ms_admm,
                                 "integrate": last.ms_integrate},
                    "mesh_create_s": t_create,
+                   "diffusion_schedule": (None if tune is None else
+                                          tune["candidates"][tune["chosen"]]),
                    "hbm_bytes_per_vertex": (mesh.stats["mesh_bytes"] + last.workspace_bytes) / mesh.nv,
                    "mesh_bytes": mesh.stats["mesh_bytes"], "query_workspace_bytes": last.workspace_bytes},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -278,6 +278,28 @@ double hg_server_clock(void);
 /* Runs the queued queries to completion, then frees the server. */
 void hg_server_destroy(hg_server_t server);
 
+/* ---- autotuning of the diffusion schedule ---- */
+typedef struct {
+    int32_t n_candidates;
+    int32_t chosen;              /* index into the arrays below */
+    int32_t schedule[8];         /* 1 = global Jacobi sweeps, 2 = LDS tiles */
+    int32_t inner_sweeps[8];     /* sweeps per tile pass (0 for Jacobi) */
+    float ms[8];                 /* time of the diffusion stage (converged) */
+    int32_t passes[8];
+    int32_t reserved[8];
+} hg_tune_report;
+
+/* Times the diffusion stage of a probe query (src/nsrc, t, opts as in
+ * hg_geodesic_solve) once per candidate schedule -- LDS tiles with 8, 16, 32,
+ * 48 and 64 in-tile sweeps per pass, and global Jacobi sweeps on meshes of at
+ * most 16 tiles -- on the mesh's default workspace and stream, and stores
+ * the fastest one that converges in the mesh: later queries whose
+ * diffusion_schedule / inner_sweeps options are 0 (auto) use it.  The
+ * arithmetic of every candidate has the same fixed point.  report
+ * (optional) receives the timings. */
+hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
+                           void* stream, hg_tune_report* report);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* hg_last_error(void);
 

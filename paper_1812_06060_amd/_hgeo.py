@@ -85,6 +85,14 @@ class ServerStats(C.Structure):
     ]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [
+        ("n_candidates", C.c_int32), ("chosen", C.c_int32), ("schedule", C.c_int32 * 8),
+        ("inner_sweeps", C.c_int32 * 8), ("ms", C.c_float * 8), ("passes", C.c_int32 * 8),
+        ("reserved", C.c_int32 * 8),
+    ]
+
+
 # (name, argtypes)
 _P = C.c_void_p
 _API = {
@@ -101,6 +109,7 @@ _API = {
     "hg_integrate_edge": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_integrate_face": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_mesh_edges": [_P, _P, _P],
+    "hg_mesh_autotune": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, C.POINTER(TuneReport)],
     "hg_server_create": [C.c_int32, C.c_uint64, C.POINTER(_P)],
     "hg_server_submit": [_P, _P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, C.POINTER(C.c_int64)],
     "hg_server_wait": [_P, C.POINTER(Result), C.c_int32],
@@ -245,6 +254,18 @@ class Mesh:
         if st != HG_E_NOT_CONVERGED or raise_on_nonconvergence:
             _check(st)
         return out, SolveInfo(info.as_dict())
+
+    def autotune(self, sources, t: float = 0.0, opts: Opts | None = None, stream=None) -> dict:
+        """Pick the fastest diffusion schedule for this mesh on a probe query
+        (hg_mesh_autotune); later solves with automatic options use it."""
+        a, p, n = _src_array(sources)
+        rep = TuneReport()
+        _check(_lib.hg_mesh_autotune(self._h, p, n, float(t), C.byref(opts) if opts else None, _stream(stream),
+                                     C.byref(rep)))
+        k = rep.n_candidates
+        return {"chosen": rep.chosen,
+                "candidates": [{"schedule": rep.schedule[i], "inner_sweeps": rep.inner_sweeps[i],
+                                "ms": rep.ms[i], "passes": rep.passes[i]} for i in range(k)]}
 
     # ---------------------------------------------------------------- stages
     def edges(self, stream=None):

@@ -443,6 +443,78 @@ hg_status hg_integrate_face(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, co
     return integrate_stage(mesh, src, nsrc, g_dev, d_dev, stream, HG_FORM_FACE);
 }
 
+hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
+                           void* stream, hg_tune_report* report) {
+    return guarded([&]() -> hg_status {
+        if (!mesh) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        hg_opts o = resolve_opts(opts);
+        auto si = map_sources(*m, src, nsrc);
+        std::vector<double> tt = resolve_t(*m, t, o);
+        Work& w = m->w;
+        w.ensure_pinned();
+        run_bfs(*m, w, si, s);
+        struct Cand {
+            int sched, inner;
+        };
+        // global Jacobi needs more sweeps than the breadth-first depth: it is a
+        // candidate only on meshes of a few tiles (or without tiles)
+        std::vector<Cand> cands;
+        if (!patch_supported(*m) || m->n_patches <= 16) cands.push_back({1, 0});
+        if (patch_supported(*m))
+            for (int inner : {8, 16, 32, 48, 64}) cands.push_back({2, inner});
+        hg_tune_report rep;
+        std::memset(&rep, 0, sizeof(rep));
+        rep.n_candidates = (int)cands.size();
+        rep.chosen = -1;
+        hipEvent_t a, b;
+        HG_CHECK_HIP(hipEventCreate(&a));
+        HG_CHECK_HIP(hipEventCreate(&b));
+        float best = 0.f;
+        const int saved_sched = m->tuned_schedule, saved_inner = m->tuned_inner;
+        try {
+            m->tuned_schedule = m->tuned_inner = 0;
+            for (size_t i = 0; i < cands.size(); ++i) {
+                hg_opts oc = o;
+                oc.diffusion_schedule = cands[i].sched;
+                oc.inner_sweeps = cands[i].inner;
+                HG_CHECK_HIP(hipEventRecord(a, s));
+                DiffusionResult dr = run_diffusion(*m, w, si, tt, oc, s);
+                HG_CHECK_HIP(hipEventRecord(b, s));
+                HG_CHECK_HIP(hipEventSynchronize(b));
+                float ms = 0.f;
+                HG_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
+                rep.schedule[i] = cands[i].sched;
+                rep.inner_sweeps[i] = cands[i].inner;
+                rep.ms[i] = ms;
+                rep.passes[i] = dr.passes;
+                if (dr.converged && (rep.chosen < 0 || ms < best)) {
+                    best = ms;
+                    rep.chosen = (int)i;
+                }
+            }
+        } catch (...) {
+            m->tuned_schedule = saved_sched;
+            m->tuned_inner = saved_inner;
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            throw;
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (rep.chosen >= 0) {
+            m->tuned_schedule = cands[rep.chosen].sched;
+            m->tuned_inner = cands[rep.chosen].inner;
+        } else {
+            m->tuned_schedule = saved_sched;
+            m->tuned_inner = saved_inner;
+        }
+        if (report) *report = rep;
+        return rep.chosen >= 0 ? HG_OK : fail(HG_E_NOT_CONVERGED, "no candidate schedule converged");
+    });
+}
+
 hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
                             float* d_dev, void* stream, hg_info* info) {
     return guarded([&]() -> hg_status {

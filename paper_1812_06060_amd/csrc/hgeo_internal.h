@@ -203,6 +203,9 @@ struct Mesh {
     std::vector<double> comp_hbar_host;
     DBuf<int32_t> comp_v, tile_comp;
 
+    // diffusion schedule picked by hg_mesh_autotune for options left at 0
+    // (auto): 0 = not tuned
+    int tuned_schedule = 0, tuned_inner = 0;
     // default per-query workspace of the synchronous entry points (also
     // used for the mesh's own reductions)
     Work w;

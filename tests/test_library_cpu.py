@@ -102,3 +102,7 @@ def test_server_rejects_null_arguments(lib):
     assert lib.hg_server_stats(None, None) == _hgeo.HG_E_INVALID_ARG
     lib.hg_server_destroy(None)
     assert lib.hg_server_clock() > 0.0
+
+
+def test_autotune_rejects_null_mesh(lib):
+    assert lib.hg_mesh_autotune(None, None, 0, 0.0, None, None, None) == _hgeo.HG_E_INVALID_ARG
