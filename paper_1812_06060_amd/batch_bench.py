@@ -80,12 +80,63 @@ def run(n_meshes: int = 256, form: str = "edge", reps: int = 3, log=print):
             "max_diff_vs_alone_over_diam": worst}
 
 
+def run_fields(n_fields: int = 64, slots: int = 8, log=print):
+    """64 single-source fields on the displaced level-9 icosphere (its 64
+    seeded sources, one query each) on one resident mesh: served
+    concurrently by an hg_server with `slots` slots (private workspaces,
+    overlapping on the device) against one query at a time."""
+    import torch
+
+    import meshgen
+    import paper_1812_06060_amd as hg
+    torch.cuda.set_device(0)
+    v, f, src = meshgen.config_mesh("bumpy9")
+    src = src[:n_fields]
+    mesh = hg.Mesh(v, f)
+    opts = hg.default_opts()
+    outs = [torch.empty(mesh.nv, dtype=torch.float32, device="cuda") for _ in src]
+    mesh.solve(src[:1], 0.0, opts, out=outs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for o, s in zip(outs, src):
+        mesh.solve(s, 0.0, opts, out=o)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    ref = [o.cpu().numpy() for o in outs]
+    srv = hg.Server(slots)
+    for o, s in zip(outs, src):           # warm the slots' workspaces
+        srv.submit(mesh, [s], out=o, opts=opts)
+    for _ in src:
+        srv.wait(-1)
+    t0 = time.perf_counter()
+    for o, s in zip(outs, src):
+        srv.submit(mesh, [s], out=o, opts=opts)
+    for _ in src:
+        srv.wait(-1)
+    t_srv = time.perf_counter() - t0
+    srv.close()
+    same = all(np.array_equal(o.cpu().numpy(), r) for o, r in zip(outs, ref))
+    log(f"[fields] {len(src)} single-source fields on L9: one at a time {t_seq:.2f} s, "
+        f"{slots}-slot server {t_srv:.2f} s, identical {same}")
+    mesh.close()
+    return {"fields": len(src), "vertices": int(v.shape[0]), "slots": slots,
+            "one_at_a_time": {"s": t_seq, "fields_per_s": len(src) / t_seq},
+            "served": {"s": t_srv, "fields_per_s": len(src) / t_srv}, "results_identical": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--meshes", type=int, default=256)
     ap.add_argument("--form", default="edge")
+    ap.add_argument("--fields", action="store_true",
+                    help="measure 64 single-source fields on the level-9 mesh instead")
+    ap.add_argument("--slots", type=int, default=8)
     a = ap.parse_args()
-    print(json.dumps(run(a.meshes, a.form, log=lambda s: print(s, file=sys.stderr, flush=True))), flush=True)
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    if a.fields:
+        print(json.dumps(run_fields(64, a.slots, log=log)), flush=True)
+    else:
+        print(json.dumps(run(a.meshes, a.form, log=log)), flush=True)
 
 
 if __name__ == "__main__":
