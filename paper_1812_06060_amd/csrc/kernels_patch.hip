@@ -37,7 +37,7 @@
 namespace hg {
 
 constexpr int kTile = 1024;    // vertices per tile at most (mesh_create uses the same)
-constexpr int kThreads = 256;  // 4 vertices per thread
+constexpr int kThreads = 1024;  // one vertex per thread: few registers (52), high occupancy
 constexpr int kPer = kTile / kThreads;
 
 __device__ inline double blk_max(double v, double* sh) {
