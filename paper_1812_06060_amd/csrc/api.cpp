@@ -211,7 +211,7 @@ hg_status hg_opts_default(hg_opts* o) {
     o->max_sweeps = 100000;
     o->max_admm = 50000;
     o->mu = 0.0;
-    o->relax = 1.8;
+    o->relax = 1.9;
     o->check_every = 32;
     o->diffusion_schedule = 0;
     o->inner_sweeps = 0;

@@ -57,7 +57,7 @@ def test_struct_layout_matches_header(tmp_path):
 def test_defaults(lib):
     o = _hgeo.Opts()
     assert lib.hg_opts_default(C.byref(o)) == 0
-    assert o.formulation == _hgeo.FORM_EDGE and o.mu == 0.0 and o.relax == 1.8 and o.m == 1.0
+    assert o.formulation == _hgeo.FORM_EDGE and o.mu == 0.0 and o.relax == 1.9 and o.m == 1.0
     assert o.source_paths == 1
     assert lib.hg_opts_default(None) == _hgeo.HG_E_INVALID_ARG
 
