@@ -73,6 +73,42 @@ def grid(n: int = 64, jitter: float = 0.2, seed: int = 1):
     return verts, tris
 
 
+def torus(nu: int = 48, nv: int = 24, R: float = 1.0, r: float = 0.4, jitter: float = 0.1, seed: int = 7):
+    """Closed torus of genus 1: vertex (i, j) at index j*nu + i, at angles
+    u = 2 pi (i + du)/nu around the axis and v = 2 pi (j + dv)/nv around the
+    tube, position ((R + r cos v) cos u, (R + r cos v) sin u, r sin v), with
+    du, dv ~ U(-jitter, jitter) (seeded).  Each quad is split along its
+    diagonal into two counter-clockwise (outward) triangles."""
+    rng = np.random.default_rng(seed)
+    jj, ii = np.meshgrid(np.arange(nv), np.arange(nu), indexing="ij")
+    du = rng.uniform(-jitter, jitter, size=nu * nv) if jitter > 0 else np.zeros(nu * nv)
+    dv = rng.uniform(-jitter, jitter, size=nu * nv) if jitter > 0 else np.zeros(nu * nv)
+    u = 2.0 * np.pi * (ii.reshape(-1) + du) / nu
+    v = 2.0 * np.pi * (jj.reshape(-1) + dv) / nv
+    verts = np.stack([(R + r * np.cos(v)) * np.cos(u), (R + r * np.cos(v)) * np.sin(u), r * np.sin(v)], axis=1)
+    i0, j0 = np.meshgrid(np.arange(nu), np.arange(nv), indexing="xy")
+    a = (j0 * nu + i0).reshape(-1)
+    b = (j0 * nu + (i0 + 1) % nu).reshape(-1)
+    c = (((j0 + 1) % nv) * nu + i0).reshape(-1)
+    d = (((j0 + 1) % nv) * nu + (i0 + 1) % nu).reshape(-1)
+    tris = np.concatenate([np.stack([a, b, d], axis=1), np.stack([a, d, c], axis=1)]).astype(np.int32)
+    return verts.astype(np.float64), tris
+
+
+def annulus(n: int = 32, hole: float = 0.2, jitter: float = 0.1, seed: int = 3):
+    """The n x n grid with the faces whose centroid lies within `hole` of
+    (0.5, 0.5) removed (unused vertices dropped, order kept): a disk with
+    one hole, i.e. two boundary loops."""
+    v, f = grid(n, jitter, seed)
+    c = v[f].mean(axis=1)
+    keep = (c[:, 0] - 0.5) ** 2 + (c[:, 1] - 0.5) ** 2 > hole * hole
+    f = f[keep]
+    used = np.unique(f)
+    remap = -np.ones(v.shape[0], dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return v[used], remap[f].astype(np.int32)
+
+
 def grid_center_source(verts, target=(0.5, 0.5)) -> int:
     """Index of the vertex nearest to ``target`` (lowest index on a tie)."""
     d2 = (verts[:, 0] - target[0]) ** 2 + (verts[:, 1] - target[1]) ** 2

@@ -223,6 +223,131 @@ def source_paths(verts, tris, topo, sources):
     return paths
 
 
+def cycle_constraints(verts, tris, topo):
+    """Cycle basis for global integrability on surfaces of genus g > 0 or
+    with several boundary loops (Sec. 5.1, Eqs. 22-23), by tree-cotree
+    (all ids are the caller's):
+
+    * primal tree T: the breadth-first tree of :mod:`oracle.bfs` (parent =
+      neighbour one level closer with the smallest id) grown from the
+      smallest vertex of each connected component;
+    * dual tree C: first-in-first-out breadth-first search over faces from
+      the smallest face of each component, visiting a face's edges in slot
+      order (tri[k], tri[k+1]) and crossing only interior edges not in T;
+    * generators: interior edges in neither tree, in increasing edge id,
+      of components without boundary (2g per closed component of genus g;
+      loops around holes of components with boundary are not covered).
+
+    For each generator e = (a, b), a < b:
+      edge form (Eq. 23): the loop a -> b along e, then back from b to a
+        through T (b up to the lowest common ancestor, down to a);
+        entries {"edge", "sign"} as for source paths (sign +1 where the loop
+        runs from the smaller to the larger vertex id);
+      face form (Eq. 22): the dual loop f0 -> f1 across e (f0 < f1 its two
+        faces), then back from f1 to f0 through C; per face of the loop the
+        polyline segment from the midpoint of the edge it is entered by to
+        the midpoint of the edge it is left by; entries {"face", "vec"}.
+    Returns (edge_cycles, face_cycles)."""
+    from collections import deque
+
+    from .bfs import bfs_levels_vec
+    from .mesh import vertex_adjacency
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    nv, nf, ne = topo.nv, tris.shape[0], topo.ne
+    row_ptr, col = vertex_adjacency(nv, topo.edges)
+    key = topo.edges[:, 0] * nv + topo.edges[:, 1]
+
+    def eid(a, b):
+        return int(np.searchsorted(key, min(a, b) * nv + max(a, b)))
+
+    # components (vertex adjacency) and their smallest vertex / face
+    comp = -np.ones(nv, dtype=np.int64)
+    roots = []
+    for v0 in range(nv):
+        if comp[v0] >= 0:
+            continue
+        comp[v0] = len(roots)
+        roots.append(v0)
+        q = deque([v0])
+        while q:
+            u = q.popleft()
+            for w in col[row_ptr[u]:row_ptr[u + 1]]:
+                if comp[w] < 0:
+                    comp[w] = comp[v0]
+                    q.append(int(w))
+    level, parent = bfs_levels_vec(nv, row_ptr, col, roots)
+    in_t = np.zeros(ne, dtype=bool)
+    for v in range(nv):
+        if parent[v] >= 0:
+            in_t[eid(v, int(parent[v]))] = True
+    # dual tree
+    other = topo.edge_faces
+    fpar = -np.ones(nf, dtype=np.int64)
+    fpar_e = -np.ones(nf, dtype=np.int64)
+    seen = np.zeros(nf, dtype=bool)
+    in_c = np.zeros(ne, dtype=bool)
+    for f0 in range(nf):
+        if seen[f0]:
+            continue
+        seen[f0] = True
+        q = deque([f0])
+        while q:
+            f = q.popleft()
+            for k in range(3):
+                e = int(topo.face_edges[f, k])
+                if topo.edge_nfaces[e] != 2 or in_t[e]:
+                    continue
+                g = int(other[e, 0] if other[e, 1] == f else other[e, 1])
+                if seen[g]:
+                    continue
+                seen[g] = True
+                fpar[g], fpar_e[g] = f, e
+                in_c[e] = True
+                q.append(g)
+    # closed components only: with boundary loops the tree-cotree count
+    # depends on how many boundary edges T takes (holes are not covered)
+    open_comp = np.zeros(len(roots), dtype=bool)
+    bnd = topo.edge_nfaces == 1
+    open_comp[comp[topo.edges[bnd, 0]]] = True
+    gens = [e for e in range(ne) if topo.edge_nfaces[e] == 2 and not in_t[e] and not in_c[e]
+            and not open_comp[comp[topo.edges[e, 0]]]]
+
+    def up(x, par):
+        out = [x]
+        while par[out[-1]] >= 0:
+            out.append(int(par[out[-1]]))
+        return out
+
+    def lca_loop(a, b, par):
+        pa, pb = up(a, par), up(b, par)
+        sa = set(pa)
+        c = next(x for x in pb if x in sa)
+        return pb[:pb.index(c) + 1] + pa[:pa.index(c)][::-1]     # b ... c ... a
+
+    mid = 0.5 * (verts[topo.edges[:, 0]] + verts[topo.edges[:, 1]])
+    edge_cycles, face_cycles = [], []
+    for e in gens:
+        a, b = (int(x) for x in topo.edges[e])
+        loop = [a] + lca_loop(a, b, parent)                     # a, b, ..., a
+        es = [eid(loop[i], loop[i + 1]) for i in range(len(loop) - 1)]
+        sg = [1.0 if loop[i] < loop[i + 1] else -1.0 for i in range(len(loop) - 1)]
+        edge_cycles.append({"edge": np.array(es, dtype=np.int64), "sign": np.array(sg)})
+        f0, f1 = sorted(int(x) for x in topo.edge_faces[e])
+        floop = [f0] + lca_loop(f0, f1, fpar)                   # f0, f1, ..., f0
+        cross = [e]
+        for i in range(1, len(floop) - 1):
+            x, y = floop[i], floop[i + 1]
+            cross.append(int(fpar_e[x]) if fpar[x] == y else int(fpar_e[y]))
+        faces, vecs = [], []
+        for i in range(len(cross)):
+            f = floop[i]
+            faces.append(f)
+            vecs.append(mid[cross[i]] - mid[cross[i - 1]])     # entered by cross[i-1], left by cross[i]
+        face_cycles.append({"face": np.array(faces, dtype=np.int64), "vec": np.array(vecs).reshape(-1, 3)})
+    return edge_cycles, face_cycles
+
+
 class EdgeADMM:
     """Edge-form ADMM.  `paths` (from :func:`source_paths`) adds the
     constraint of Eq. 25 for each path S: one more group of copies

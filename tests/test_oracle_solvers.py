@@ -402,6 +402,67 @@ def test_path_constraints_reach_the_dirichlet_poisson_distance(bumpy3, mu, alpha
         assert errs[0] < 1e-8 and errs[1] > 1e-3, (form, errs)
 
 
+@pytest.mark.parametrize("case, count", [("torus", 2), ("sphere", 0), ("annulus", 0), ("two_tori", 4)])
+def test_cycle_basis_sizes_and_loops(case, count):
+    """Tree-cotree leaves 2g generators per closed component (none for a
+    component with boundary, out of the scope of the genus constraints);
+    every edge cycle is a closed edge loop with signs along it, every face
+    cycle a closed chain of adjacent faces whose polyline segments sum to
+    zero."""
+    if case == "torus":
+        v, f = meshgen.torus()
+    elif case == "sphere":
+        v, f = meshgen.icosphere(3)
+    elif case == "annulus":
+        v, f = meshgen.annulus()
+    else:
+        v, f, _ = meshgen.disjoint_union([meshgen.torus(24, 12, seed=1), meshgen.torus(20, 10, seed=2)])
+    topo = mesh.build_topology(f, v.shape[0])
+    ec, fc = admm.cycle_constraints(v, f, topo)
+    assert len(ec) == len(fc) == count
+    for c in ec:
+        cur = None
+        start = None
+        for e, sg in zip(c["edge"], c["sign"]):
+            a, b = topo.edges[e]
+            tail, head = (a, b) if sg > 0 else (b, a)
+            if cur is None:
+                start = tail
+            else:
+                assert tail == cur
+            cur = head
+        assert cur == start
+    for c in fc:
+        faces = c["face"]
+        for i in range(faces.size):
+            fa, fb = faces[i], faces[(i + 1) % faces.size]
+            assert len(set(f[fa]) & set(f[fb])) == 2      # adjacent across an edge
+        assert np.abs(c["vec"].sum(axis=0)).max() < 1e-12
+
+
+def test_cycle_constraints_reach_poisson_on_torus():
+    """On a torus, locally compatible fields need not be gradients: with the
+    cycle constraints of Eqs. 22-23 the converged ADMM field integrates to
+    the Poisson distance (an independent sparse solve, globally integrable
+    by construction); without them both forms miss it by > 1e-4."""
+    v, f = meshgen.torus()
+    src = [5]
+    for form in ("edge", "face"):
+        r = pipeline.heat_method(v, f, src, form=form)
+        ec, fc = admm.cycle_constraints(v, f, r.topo)
+        errs = []
+        for use in (True, False):
+            if form == "edge":
+                Z = gradient.edge_targets(v, r.topo, r.h)
+                st = admm.EdgeADMM(r.topo, Z, 30, 1.8, paths=ec if use else ()).run(20000, 1e-13)
+                d = integrate.integrate_edge(r.topo, st.x, r.level, r.parent, src)
+            else:
+                st = admm.FaceADMM(v, f, r.topo, r.h, 30, 1.8, paths=fc if use else ()).run(20000, 1e-13, 1e-13)
+                d = integrate.integrate_face(v, r.topo, st.g, r.level, r.parent, src)
+            errs.append(metrics.parity(d, r.d))
+        assert errs[0][1] < 1e-8 and errs[1][0] > 1e-4, (form, errs)
+
+
 def test_admm_residuals_decrease(bumpy3):
     v, f = bumpy3
     r = pipeline.heat_method(v, f, [0], form="edge")
