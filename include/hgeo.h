@@ -104,7 +104,14 @@ typedef struct {
                                solve runs on a stream of its own, ordered
                                after the caller's work on the null stream;
                                0: plain launches */
-    int32_t reserved[3];
+    int32_t cycle_constraints; /* 1 (default): on a closed component of
+                               genus g > 0 the ADMM also constrains the
+                               field's circulation around 2g generator
+                               loops to zero (Sec. 5.1, Eq. 23 edge form,
+                               Eq. 22 face form), so that it is the gradient
+                               of a function there; 0 = without them.
+                               Components with boundary get none. */
+    int32_t reserved[2];
 } hg_opts;
 
 /* Per-solve report. */
@@ -129,7 +136,10 @@ typedef struct {
     uint64_t bytes_pass_kernel, bytes_admm_kernel;
     int32_t n_paths;        /* source paths constrained (Eqs. 24-25) */
     int32_t path_edges;     /* total edges over those paths */
-    int32_t reserved[6];
+    int32_t n_cycles;       /* generator loops constrained (Sec. 5.1) */
+    int32_t cycle_slots;    /* total edges (edge form) or faces (face form)
+                               over those loops */
+    int32_t reserved[4];
 } hg_info;
 
 /* Mesh statistics. */
@@ -142,7 +152,12 @@ typedef struct {
     uint64_t mesh_bytes;    /* device bytes held by the mesh */
     int32_t n_components;   /* connected components (vertex adjacency) */
     int32_t n_colors;       /* colours of the diffusion tiles */
-    int32_t reserved[6];
+    int32_t n_cycles;       /* generator loops: 2g per closed component of
+                               genus g (Sec. 5.1), 0 for a component with
+                               boundary */
+    int32_t cycle_edges;    /* edges over the edge loops */
+    int32_t cycle_faces;    /* faces over the face loops */
+    int32_t reserved[3];
 } hg_mesh_stats;
 
 /* Fill *opts with the defaults above. */
@@ -186,6 +201,32 @@ hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* stats);
  */
 hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
                             const hg_opts* opts, float* d_dev, void* stream, hg_info* info);
+
+/*
+ * The generator loops of the cycle constraints (Sec. 5.1), built with the
+ * mesh by a tree-cotree decomposition on the caller's ids: primal tree =
+ * breadth-first tree from the smallest vertex of each component (parent =
+ * the neighbour one level closer with the smallest id); dual tree =
+ * first-in-first-out breadth-first search over faces from the smallest face
+ * of each component, edges of a face in slot order, across interior edges
+ * not in the primal tree; one loop per interior edge in neither tree, in
+ * canonical edge order, on components without boundary.  For such an edge
+ * (a, b), a < b:
+ *   form HG_FORM_EDGE: a -> b, then back to a through the primal tree;
+ *     ids = canonical edge ids, coef = +1 where the loop runs from the
+ *     smaller to the larger vertex id, else -1 (1 float per slot);
+ *   form HG_FORM_FACE: across the edge from its smaller to its larger face,
+ *     then back through the dual tree; ids = caller face ids, coef = the
+ *     polyline segment inside the face, from the midpoint of the edge the
+ *     loop enters it by to the midpoint of the edge it leaves it by (3
+ *     floats per slot).
+ *   ptr  : HOST int32[n_cycles + 1] slot offsets of the loops;
+ *   ids  : HOST int32[capacity]; coef : HOST float[capacity or 3*capacity].
+ * n_cycles and the slot counts are in hg_mesh_stats; HG_E_INVALID_ARG if
+ * capacity is below the form's slot count or a pointer is NULL.
+ */
+hg_status hg_mesh_cycles(hg_mesh_t mesh, int32_t form, int32_t* ptr, int32_t* ids, float* coef,
+                         int64_t capacity);
 
 /* ---- the individual steps, each running the same kernels as the solve ---- */
 

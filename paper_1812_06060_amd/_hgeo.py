@@ -38,7 +38,8 @@ class Opts(C.Structure):
         ("tol_admm", C.c_double), ("max_sweeps", C.c_int32), ("max_admm", C.c_int32),
         ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
         ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("source_paths", C.c_int32),
-        ("t_per_component", C.c_int32), ("use_graphs", C.c_int32), ("reserved", C.c_int32 * 3),
+        ("t_per_component", C.c_int32), ("use_graphs", C.c_int32), ("cycle_constraints", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -53,7 +54,8 @@ class Info(C.Structure):
         ("converged_u", C.c_int32), ("converged_admm", C.c_int32),
         ("ms_pass_kernel", C.c_float), ("ms_admm_kernel", C.c_float),
         ("bytes_pass_kernel", C.c_uint64), ("bytes_admm_kernel", C.c_uint64),
-        ("n_paths", C.c_int32), ("path_edges", C.c_int32), ("reserved", C.c_int32 * 6),
+        ("n_paths", C.c_int32), ("path_edges", C.c_int32), ("n_cycles", C.c_int32), ("cycle_slots", C.c_int32),
+        ("reserved", C.c_int32 * 4),
     ]
 
     def as_dict(self):
@@ -65,7 +67,8 @@ class MeshStats(C.Structure):
         ("nv", C.c_int64), ("nf", C.c_int64), ("ne", C.c_int64), ("n_boundary_edges", C.c_int64),
         ("hbar", C.c_double), ("total_area", C.c_double), ("max_valence", C.c_int32),
         ("n_patches", C.c_int32), ("mesh_bytes", C.c_uint64), ("n_components", C.c_int32),
-        ("n_colors", C.c_int32), ("reserved", C.c_int32 * 6),
+        ("n_colors", C.c_int32), ("n_cycles", C.c_int32), ("cycle_edges", C.c_int32), ("cycle_faces", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -109,6 +112,7 @@ _API = {
     "hg_integrate_edge": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_integrate_face": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_mesh_edges": [_P, _P, _P],
+    "hg_mesh_cycles": [_P, C.c_int32, _P, _P, _P, C.c_int64],
     "hg_mesh_autotune": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, C.POINTER(TuneReport)],
     "hg_server_create": [C.c_int32, C.c_uint64, C.POINTER(_P)],
     "hg_server_submit": [_P, _P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, C.POINTER(C.c_int64)],
@@ -266,6 +270,24 @@ class Mesh:
         return {"chosen": rep.chosen,
                 "candidates": [{"schedule": rep.schedule[i], "inner_sweeps": rep.inner_sweeps[i],
                                 "ms": rep.ms[i], "passes": rep.passes[i]} for i in range(k)]}
+
+    def cycles(self, form: str = "edge"):
+        """The generator loops of the cycle constraints (hg_mesh_cycles), as a
+        list of (ids, coef): edge form canonical edge ids and signs, face form
+        caller face ids and [n, 3] polyline segments."""
+        fm = {"face": FORM_FACE, "edge": FORM_EDGE}[form]
+        n = self.stats["n_cycles"]
+        cap = self.stats["cycle_edges" if fm == FORM_EDGE else "cycle_faces"]
+        ptr = np.zeros(n + 1, dtype=np.int32)
+        ids = np.zeros(max(cap, 1), dtype=np.int32)
+        coef = np.zeros(max(cap, 1) * (1 if fm == FORM_EDGE else 3), dtype=np.float32)
+        _check(_lib.hg_mesh_cycles(self._h, fm, ptr.ctypes.data, ids.ctypes.data, coef.ctypes.data, cap))
+        out = []
+        for i in range(n):
+            a, b = int(ptr[i]), int(ptr[i + 1])
+            c = coef[a:b].copy() if fm == FORM_EDGE else coef[3 * a:3 * b].reshape(-1, 3).copy()
+            out.append((ids[a:b].copy(), c))
+        return out
 
     # ---------------------------------------------------------------- stages
     def edges(self, stream=None):

@@ -78,6 +78,8 @@ static hg_opts resolve_opts(const hg_opts* o) {
     if (!(r.mu >= 0.0) || !std::isfinite(r.mu)) throw Error{HG_E_INVALID_ARG, "mu must be >= 0 (0 = auto)"};
     if (!(r.relax > 0.0 && r.relax < 2.0)) throw Error{HG_E_INVALID_ARG, "relax must lie in (0, 2)"};
     if (r.source_paths != 0 && r.source_paths != 1) throw Error{HG_E_INVALID_ARG, "source_paths must be 0 or 1"};
+    if (r.cycle_constraints != 0 && r.cycle_constraints != 1)
+        throw Error{HG_E_INVALID_ARG, "cycle_constraints must be 0 or 1"};
     if (r.use_graphs != 0 && r.use_graphs != 1) throw Error{HG_E_INVALID_ARG, "use_graphs must be 0 or 1"};
     if (r.t_per_component != 0 && r.t_per_component != 1)
         throw Error{HG_E_INVALID_ARG, "t_per_component must be 0 or 1"};
@@ -143,8 +145,10 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
     std::vector<double> tt = resolve_t(*m, t, o);
     StageTimer tm(s);
     tm.mark();
-    const bool paths = nsrc > 1 && o.source_paths;
-    if (paths) build_source_paths(*m, w, si, s);
+    const bool src_paths = nsrc > 1 && o.source_paths;
+    const bool cycles = o.cycle_constraints && m->n_cycles > 0;
+    const bool paths = src_paths || cycles;
+    if (paths) build_constraint_paths(*m, w, si, src_paths, cycles, o.formulation, s);
     int depth = run_bfs(*m, w, si, s);
     tm.mark();
     DiffusionResult dr = run_diffusion(*m, w, si, tt, o, s);
@@ -156,7 +160,7 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
     // integrated along (measured, one source: best mu ~ 100 at depth 167,
     // ~ 300 at depth 663; several sources with path constraints: best mu
     // ~ 1 - 1.8 times the longest path's edge count); mu = 0 picks
-    // max(30, depth / 2, 1.5 * longest path)
+    // max(30, depth / 2, 1.5 * longest path or generator loop)
     if (o.mu == 0.0) {
         o.mu = std::max(30.0, 0.5 * depth);
         if (paths && w.paths.np > 0) o.mu = std::max(o.mu, 1.5 * w.paths.max_len);
@@ -191,8 +195,10 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
         info->bytes_pass_kernel = dr.bytes_per_pass;
         info->bytes_admm_kernel = ar.bytes_per_iter;
         info->bytes_alg = dr.bytes_per_pass * (uint64_t)dr.passes + ar.bytes_per_iter * (uint64_t)ar.iters;
-        info->n_paths = paths ? w.paths.np : 0;
-        info->path_edges = paths ? w.paths.ns : 0;
+        info->n_paths = paths ? w.paths.np_src : 0;
+        info->path_edges = paths ? w.paths.ns_src : 0;
+        info->n_cycles = paths ? w.paths.n_cyc : 0;
+        info->cycle_slots = paths ? w.paths.ns_cyc : 0;
     }
     if (!dr.converged) return {HG_E_NOT_CONVERGED, "diffusion sweep cap reached"};
     if (!ar.converged) return {HG_E_NOT_CONVERGED, "ADMM iteration cap reached"};
@@ -216,6 +222,7 @@ hg_status hg_opts_default(hg_opts* o) {
     o->diffusion_schedule = 0;
     o->inner_sweeps = 0;
     o->source_paths = 1;
+    o->cycle_constraints = 1;
     o->use_graphs = 1;
     return HG_OK;
 }
@@ -230,6 +237,7 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
         hipStream_t s = (hipStream_t)stream;
         HostTopo T;
         build_topology(xyz, nv, tri, nf, 1024, T);
+        build_cycles(T);
         auto* m = new Mesh();
         try {
             HG_CHECK_HIP(hipGetDevice(&m->device));
@@ -271,6 +279,17 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
             m->comp_v.upload(T.comp, s);
             m->tile_comp.upload(T.tile_comp, s);
             m->tile_order.upload(T.tile_order, s);
+            m->n_cycles = T.n_cycles;
+            m->cyc_e_ptr.swap(T.cyc_e_ptr);
+            m->cyc_e_edge.swap(T.cyc_e_edge);
+            m->cyc_e_sign.swap(T.cyc_e_sign);
+            m->cyc_e_face.swap(T.cyc_e_face);
+            m->cyc_e_canon.swap(T.cyc_e_canon);
+            m->cyc_f_caller.swap(T.cyc_f_caller);
+            m->cyc_f_ptr.swap(T.cyc_f_ptr);
+            m->cyc_f_face.swap(T.cyc_f_face);
+            m->cyc_f_edge.swap(T.cyc_f_edge);
+            m->cyc_f_vec.swap(T.cyc_f_vec);
             m->w.ensure_pinned();
             geometry_init(*m, s);
         } catch (...) {
@@ -300,6 +319,27 @@ hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* st) {
         st->mesh_bytes = m->mesh_bytes();
         st->n_components = m->n_comp;
         st->n_colors = (int32_t)m->color_ptr_host.size() - 1;
+        st->n_cycles = m->n_cycles;
+        st->cycle_edges = (int32_t)m->cyc_e_edge.size();
+        st->cycle_faces = (int32_t)m->cyc_f_face.size();
+        return HG_OK;
+    });
+}
+
+hg_status hg_mesh_cycles(hg_mesh_t mesh, int32_t form, int32_t* ptr, int32_t* ids, float* coef, int64_t capacity) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !ptr || !ids || !coef) return fail(HG_E_INVALID_ARG, "null argument");
+        if (form != HG_FORM_EDGE && form != HG_FORM_FACE)
+            return fail(HG_E_INVALID_ARG, "form must be HG_FORM_FACE or HG_FORM_EDGE");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        const bool ef = form == HG_FORM_EDGE;
+        const auto& p = ef ? m->cyc_e_ptr : m->cyc_f_ptr;
+        const auto& id = ef ? m->cyc_e_canon : m->cyc_f_caller;
+        const auto& cf = ef ? m->cyc_e_sign : m->cyc_f_vec;
+        if (capacity < (int64_t)id.size()) return fail(HG_E_INVALID_ARG, "capacity below the loops' slot count");
+        std::copy(p.begin(), p.end(), ptr);
+        std::copy(id.begin(), id.end(), ids);
+        std::copy(cf.begin(), cf.end(), coef);
         return HG_OK;
     });
 }
@@ -378,8 +418,12 @@ static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, const int32_t* s
         hipStream_t s = (hipStream_t)stream;
         hg_opts o = resolve_opts(opts);
         if (o.mu == 0.0) o.mu = 100.0;   // no breadth-first depth here: the paper's value
-        const bool paths = src && nsrc > 1 && o.source_paths;
-        if (paths) build_source_paths(*m, m->w, map_sources(*m, src, nsrc), s);
+        const bool src_paths = src && nsrc > 1 && o.source_paths;
+        const bool cycles = o.cycle_constraints && m->n_cycles > 0;
+        const bool paths = src_paths || cycles;
+        if (paths)
+            build_constraint_paths(*m, m->w, src_paths ? map_sources(*m, src, nsrc) : std::vector<int32_t>{},
+                                   src_paths, cycles, form, s);
         m->w.h.alloc((size_t)3 * m->nf);
         gather_faces_to_internal(*m, h_dev, m->w.h.p, s);
         AdmmResult r = form == HG_FORM_EDGE ? run_admm_edge(*m, m->w, iters, o, s, -1, paths)
@@ -395,8 +439,10 @@ static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, const int32_t* s
             info->res_primal = r.rp;
             info->res_dual = r.rd;
             info->converged_admm = r.converged;
-            info->n_paths = paths ? m->w.paths.np : 0;
-            info->path_edges = paths ? m->w.paths.ns : 0;
+            info->n_paths = paths ? m->w.paths.np_src : 0;
+            info->path_edges = paths ? m->w.paths.ns_src : 0;
+            info->n_cycles = paths ? m->w.paths.n_cyc : 0;
+            info->cycle_slots = paths ? m->w.paths.ns_cyc : 0;
         }
         return r.converged ? HG_OK : fail(HG_E_NOT_CONVERGED, "ADMM iteration cap reached");
     });

@@ -103,11 +103,22 @@ struct HostTopo {
     std::vector<double> comp_hbar;
     int max_halo = 0;
     int max_ell_width = 0;
+    // generator loops of closed components of genus > 0 (Sec. 5.1), see
+    // build_cycles: edge loops (internal edge, sign) and face loops
+    // (internal face, the edge the loop leaves it by, polyline segment);
+    // cyc_e_face: a face of each edge-loop slot's edge; cyc_e_canon,
+    // cyc_f_caller: the caller's ids of the loops' edges and faces
+    int n_cycles = 0;
+    std::vector<int32_t> cyc_e_ptr, cyc_e_edge, cyc_e_face, cyc_f_ptr, cyc_f_face, cyc_f_edge;
+    std::vector<int32_t> cyc_e_canon, cyc_f_caller;
+    std::vector<float> cyc_e_sign, cyc_f_vec;
 };
 
 // Builds the host topology; throws Error{HG_E_BAD_MESH} on invalid input.
 void build_topology(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, int patch_size,
                     HostTopo& out);
+// Fills the cyc_* loops of a built topology (tree-cotree, caller-id rules).
+void build_cycles(HostTopo& T);
 
 // Per-query device workspace.  A query runs on one Work and one stream; the
 // mesh data it reads is never written after mesh_create, so queries on the
@@ -157,6 +168,8 @@ struct Work {
     // and by face (CSR over the distinct ids, slots in increasing order)
     struct Paths {
         int np = 0, ns = 0, ng_edge = 0, ng_face = 0;
+        int np_src = 0, ns_src = 0;             // the source paths: groups [0, np_src), slots [0, ns_src)
+        int n_cyc = 0, ns_cyc = 0;              // the generator loops after them
         int max_len = 0;                        // edges on the longest path
         DBuf<int32_t> ptr, edge, face;
         DBuf<float> sign, vec;                  // [ns], [3*ns]
@@ -202,6 +215,13 @@ struct Mesh {
     int n_comp = 0;
     std::vector<double> comp_hbar_host;
     DBuf<int32_t> comp_v, tile_comp;
+
+    // generator loops of closed components of genus > 0 (host copies of
+    // HostTopo's cyc_*), added to a query's constraint groups
+    int n_cycles = 0;
+    std::vector<int32_t> cyc_e_ptr, cyc_e_edge, cyc_e_face, cyc_f_ptr, cyc_f_face, cyc_f_edge;
+    std::vector<int32_t> cyc_e_canon, cyc_f_caller;
+    std::vector<float> cyc_e_sign, cyc_f_vec;
 
     // diffusion schedule picked by hg_mesh_autotune for options left at 0
     // (auto): 0 = not tuned
@@ -319,10 +339,13 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                          bool use_paths = false);
 AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStream_t s, int depth = -1,
                          bool use_paths = false);
-// Builds m.w.paths from the (internal) source list; runs breadth-first
-// searches from single sources, so it overwrites level/parent/pslot: run the
-// query's own breadth-first search after it.
-void build_source_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s);
+// Builds w.paths: with source_paths, the paths between the (internal)
+// sources (Eqs. 24-25); with cycles, the mesh's generator loops in the given
+// form (Sec. 5.1).  The source paths come from breadth-first searches from
+// single sources, which overwrite level/parent/pslot: run the query's own
+// breadth-first search after it.
+void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, bool source_paths,
+                            bool cycles, int form, hipStream_t s);
 void integrate(Mesh& m, Work& w, int form, int depth, float* d_user, hipStream_t s);
 // integrates the given state (edge differences xe or face gradients g) and
 // returns max |d - d_prev| (inf on the first call) and max |d|; d_prev <- d

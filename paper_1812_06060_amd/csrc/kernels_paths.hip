@@ -15,8 +15,12 @@
 //          path's direction (the only face of a boundary edge) (Eq. 24),
 //   vec    the edge vector in the path's direction          (Eq. 24).
 // Sources that the tree does not reach start a new tree from the first of
-// them.  The slots are then grouped on the host by edge and by face, so that
-// the ADMM kernels can sum a group's copies in a fixed order.
+// them.  The generator loops of closed components of genus > 0 (Sec. 5.1,
+// built with the mesh) follow the paths as further groups of the query's
+// form: edge loops with their signs (Eq. 23) or face loops with their
+// polyline segments (Eq. 22).  The slots are then grouped on the host by
+// edge and by face, so that the ADMM kernels can sum a group's copies in a
+// fixed order.
 #include <algorithm>
 #include <numeric>
 
@@ -99,12 +103,15 @@ static void group_slots(const std::vector<int32_t>& id, std::vector<int32_t>& gp
     if (ns > 0) gptr.push_back(ns);
 }
 
-void build_source_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s) {
+void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, bool source_paths,
+                            bool cycles, int form, hipStream_t s) {
     auto& P = w.paths;
     P.np = P.ns = P.max_len = 0;
+    P.np_src = P.ns_src = P.n_cyc = P.ns_cyc = 0;
     std::vector<int32_t> todo;
-    for (int32_t v : src_internal)
-        if (std::find(todo.begin(), todo.end(), v) == todo.end()) todo.push_back(v);
+    if (source_paths)
+        for (int32_t v : src_internal)
+            if (std::find(todo.begin(), todo.end(), v) == todo.end()) todo.push_back(v);
     std::vector<int32_t> h_ptr{0}, h_edge, h_face;
     std::vector<float> h_sign, h_vec;
     DBuf<int32_t> d_src, d_lvl, d_base, d_len, d_vert, d_edge, d_face;
@@ -163,6 +170,29 @@ void build_source_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_intern
             for (int i = 0; i < np; ++i) h_ptr.push_back((int32_t)(o + base[i] + len[i]));
         }
         todo = unreached;
+    }
+    P.np_src = (int)h_ptr.size() - 1;
+    P.ns_src = (int)h_edge.size();
+    if (cycles && m.n_cycles > 0) {
+        // edge form: the loop's edges and signs (face and vector unused);
+        // face form: the loop's faces and segments (edge and sign unused)
+        const bool ef = form == HG_FORM_EDGE;
+        const auto& cptr = ef ? m.cyc_e_ptr : m.cyc_f_ptr;
+        const size_t o = h_edge.size(), n = (size_t)cptr.back();
+        if (ef) {
+            h_edge.insert(h_edge.end(), m.cyc_e_edge.begin(), m.cyc_e_edge.end());
+            h_sign.insert(h_sign.end(), m.cyc_e_sign.begin(), m.cyc_e_sign.end());
+            h_face.insert(h_face.end(), m.cyc_e_face.begin(), m.cyc_e_face.end());
+            h_vec.resize(3 * (o + n), 0.f);
+        } else {
+            h_face.insert(h_face.end(), m.cyc_f_face.begin(), m.cyc_f_face.end());
+            h_vec.insert(h_vec.end(), m.cyc_f_vec.begin(), m.cyc_f_vec.end());
+            h_edge.insert(h_edge.end(), m.cyc_f_edge.begin(), m.cyc_f_edge.end());
+            h_sign.resize(o + n, 0.f);
+        }
+        for (int c = 0; c < m.n_cycles; ++c) h_ptr.push_back((int32_t)(o + cptr[c + 1]));
+        P.n_cyc = m.n_cycles;
+        P.ns_cyc = (int)n;
     }
     P.np = (int)h_ptr.size() - 1;
     P.ns = (int)h_edge.size();

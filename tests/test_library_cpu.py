@@ -59,6 +59,7 @@ def test_defaults(lib):
     assert lib.hg_opts_default(C.byref(o)) == 0
     assert o.formulation == _hgeo.FORM_EDGE and o.mu == 0.0 and o.relax == 1.9 and o.m == 1.0
     assert o.source_paths == 1
+    assert o.cycle_constraints == 1
     assert lib.hg_opts_default(None) == _hgeo.HG_E_INVALID_ARG
 
 
