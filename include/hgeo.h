@@ -73,11 +73,12 @@ typedef struct {
     int32_t max_sweeps;     /* diffusion sweep cap; default 100000 */
     int32_t max_admm;       /* ADMM iteration cap; default 50000 */
     double mu;              /* ADMM penalty (the paper uses 100); default 0 =
-                               auto: max(30, depth/2, 1.5 L) in
+                               auto: max(30, depth/2, 1.5 L, C/2) in
                                hg_geodesic_solve (depth = breadth-first depth
                                of the query, L = edges on the longest source
-                               path, 0 without path constraints), 100 in the
-                               ADMM step entry points */
+                               path, C = edges on the longest generator loop
+                               of the cycle constraints, 0 without them), 100
+                               in the ADMM step entry points */
     int32_t check_every;    /* iterations between convergence checks; 32 */
     int32_t diffusion_schedule; /* 0 = auto, 1 = global Jacobi sweeps,
                                    2 = LDS-tiled patch sweeps */

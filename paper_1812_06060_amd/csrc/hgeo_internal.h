@@ -170,7 +170,8 @@ struct Work {
         int np = 0, ns = 0, ng_edge = 0, ng_face = 0;
         int np_src = 0, ns_src = 0;             // the source paths: groups [0, np_src), slots [0, ns_src)
         int n_cyc = 0, ns_cyc = 0;              // the generator loops after them
-        int max_len = 0;                        // edges on the longest path
+        int max_len = 0;                        // slots of the longest group
+        int max_len_src = 0, max_len_cyc = 0;   // of the longest source path / generator loop
         DBuf<int32_t> ptr, edge, face;
         DBuf<float> sign, vec;                  // [ns], [3*ns]
         DBuf<int32_t> eg_ptr, eg_id, eg_slot, fg_ptr, fg_id, fg_slot;

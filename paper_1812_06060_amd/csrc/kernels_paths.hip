@@ -196,8 +196,13 @@ void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_in
     }
     P.np = (int)h_ptr.size() - 1;
     P.ns = (int)h_edge.size();
-    P.max_len = 0;
-    for (int i = 0; i < P.np; ++i) P.max_len = std::max(P.max_len, h_ptr[i + 1] - h_ptr[i]);
+    P.max_len = P.max_len_src = P.max_len_cyc = 0;
+    for (int i = 0; i < P.np; ++i) {
+        const int len = h_ptr[i + 1] - h_ptr[i];
+        int& mx = i < P.np_src ? P.max_len_src : P.max_len_cyc;
+        mx = std::max(mx, len);
+        P.max_len = std::max(P.max_len, len);
+    }
     if (P.np == 0) return;
     P.ptr.upload(h_ptr, s);
     P.edge.upload(h_edge, s);
