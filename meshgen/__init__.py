@@ -10,6 +10,10 @@ Generators (all randomness from ``numpy.random.default_rng(seed)``):
 
 * :func:`grid` -- n x n vertex grid on [0,1]^2, each square split along its
   (i,j)-(i+1,j+1) diagonal, interior vertices jittered uniformly.
+* :func:`affine_grid` -- that grid sheared and squashed into a parallelogram
+  (a poorly shaped, non-Delaunay planar triangulation).
+* :func:`torus`, :func:`annulus` -- a jittered genus-1 torus; a grid with a
+  hole (two boundary loops).
 * :func:`icosphere` -- regular icosahedron refined by ``level`` rounds of
   1->4 midpoint subdivision, midpoints projected to the unit sphere each round.
 * :func:`tangential_jitter` -- move each sphere vertex inside its tangent plane
@@ -27,6 +31,7 @@ import numpy as np
 
 __all__ = [
     "grid",
+    "affine_grid",
     "grid_center_source",
     "icosphere",
     "mean_edge_length_raw",
@@ -107,6 +112,18 @@ def annulus(n: int = 32, hole: float = 0.2, jitter: float = 0.1, seed: int = 3):
     remap = -np.ones(v.shape[0], dtype=np.int64)
     remap[used] = np.arange(used.size)
     return v[used], remap[f].astype(np.int32)
+
+
+def affine_grid(n: int = 32, shear: float = 1.0, squash: float = 0.3, jitter: float = 0.1, seed: int = 1):
+    """:func:`grid` mapped by (x, y) -> (x + shear y, squash y): a flat
+    parallelogram whose cells are split along their long diagonal, so with
+    shear > 0 and squash < 1 most interior edges face two obtuse angles (a
+    poor, non-Delaunay triangulation of a convex planar domain)."""
+    v, f = grid(n, jitter, seed)
+    out = v.copy()
+    out[:, 0] = v[:, 0] + shear * v[:, 1]
+    out[:, 1] = squash * v[:, 1]
+    return out, f
 
 
 def grid_center_source(verts, target=(0.5, 0.5)) -> int:
