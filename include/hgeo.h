@@ -158,7 +158,11 @@ typedef struct {
                                boundary */
     int32_t cycle_edges;    /* edges over the edge loops */
     int32_t cycle_faces;    /* faces over the face loops */
-    int32_t reserved[3];
+    int32_t intrinsic;      /* 1: built by hg_mesh_create_intrinsic */
+    int32_t n_flips;        /* edge flips of the intrinsic Delaunay build */
+    int32_t n_nondelaunay;  /* interior edges left non-Delaunay (flip would
+                               have duplicated an edge) */
+    int32_t reserved[4];
 } hg_mesh_stats;
 
 /* Fill *opts with the defaults above. */
@@ -177,6 +181,33 @@ hg_status hg_opts_default(hg_opts* opts);
  */
 hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf,
                          void* stream, hg_mesh_t* out);
+
+/*
+ * The same on the intrinsic Delaunay triangulation of the mesh (Sec. 5.3):
+ * the surface is described by connectivity and edge lengths, and interior
+ * edges whose two facing angles sum beyond pi are flipped (first-in-first-
+ * out queue over interior edges, initially in canonical order; the new
+ * length from unfolding the two triangles into the plane; a flip that would
+ * join two already joined vertices is skipped and the edge counted in
+ * n_nondelaunay).  Breadth-first sets use the flipped connectivity; areas
+ * and cotangent weights come from the intrinsic lengths; gradients and edge
+ * targets (Eqs. 3, 18) are taken in each face's own frame (first vertex at
+ * the origin, first edge along +x, third vertex at y > 0); t = m hbar^2
+ * uses the mean edge length of the input mesh.  Only the edge form runs on
+ * such a mesh (HG_E_INVALID_ARG for the face form).  Faces and edges seen
+ * by the caller (face-indexed and edge-indexed arrays, hg_mesh_edges) are
+ * those of the flipped triangulation: face i is row i of the flipped
+ * triangle list.  The flips run on the host (time roughly linear in the
+ * mesh size).
+ */
+hg_status hg_mesh_create_intrinsic(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf,
+                                   void* stream, hg_mesh_t* out);
+/* The intrinsic triangulation of such a mesh: tri_out = HOST int32[nf*3]
+ * flipped triangles (caller vertex ids), length_out = HOST float64[ne]
+ * edge lengths in canonical edge order.  HG_E_INVALID_ARG for a mesh built
+ * by hg_mesh_create. */
+hg_status hg_mesh_intrinsic(hg_mesh_t mesh, int32_t* tri_out, double* length_out);
+
 void hg_mesh_destroy(hg_mesh_t mesh);
 hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* stats);
 
@@ -245,7 +276,9 @@ hg_status hg_diffuse(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t,
                      const hg_opts* opts, double* logu_dev, void* stream, hg_info* info);
 
 /* Normalisation (Eq. 3) from DEVICE float64[nv] log u: h_dev = DEVICE
- * float32[nf*3] unit vectors (0 where the gradient vanishes). */
+ * float32[nf*3] unit vectors (0 where the gradient vanishes); on an
+ * intrinsic mesh each in its face's own frame, z = 0 (the edge-form ADMM
+ * entry point reads it the same way). */
 hg_status hg_normalize(hg_mesh_t mesh, const double* logu_dev, float* h_dev, void* stream);
 
 /* Edge-form ADMM (Sec. 4.1) from DEVICE float32[nf*3] normalised field h:

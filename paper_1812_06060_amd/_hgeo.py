@@ -68,7 +68,7 @@ class MeshStats(C.Structure):
         ("hbar", C.c_double), ("total_area", C.c_double), ("max_valence", C.c_int32),
         ("n_patches", C.c_int32), ("mesh_bytes", C.c_uint64), ("n_components", C.c_int32),
         ("n_colors", C.c_int32), ("n_cycles", C.c_int32), ("cycle_edges", C.c_int32), ("cycle_faces", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("intrinsic", C.c_int32), ("n_flips", C.c_int32), ("n_nondelaunay", C.c_int32), ("reserved", C.c_int32 * 4),
     ]
 
 
@@ -101,6 +101,8 @@ _P = C.c_void_p
 _API = {
     "hg_opts_default": [C.POINTER(Opts)],
     "hg_mesh_create": [_P, C.c_int64, _P, C.c_int64, _P, C.POINTER(_P)],
+    "hg_mesh_create_intrinsic": [_P, C.c_int64, _P, C.c_int64, _P, C.POINTER(_P)],
+    "hg_mesh_intrinsic": [_P, _P, _P],
     "hg_mesh_destroy": [_P],
     "hg_mesh_get_stats": [_P, C.POINTER(MeshStats)],
     "hg_geodesic_solve": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
@@ -214,9 +216,10 @@ class SolveInfo:
 
 
 class Mesh:
-    """A resident device mesh (hg_mesh_create)."""
+    """A resident device mesh (hg_mesh_create; with intrinsic=True
+    hg_mesh_create_intrinsic, the intrinsic Delaunay triangulation)."""
 
-    def __init__(self, verts, tris, stream=None):
+    def __init__(self, verts, tris, stream=None, intrinsic: bool = False):
         load_library()
         _torch()
         v = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
@@ -224,8 +227,9 @@ class Mesh:
         if v.ndim != 2 or v.shape[1] != 3 or f.ndim != 2 or f.shape[1] != 3:
             raise ValueError("verts must be [V,3] and tris [F,3]")
         h = C.c_void_p()
-        _check(_lib.hg_mesh_create(v.ctypes.data_as(C.c_void_p), v.shape[0],
-                                   f.ctypes.data_as(C.c_void_p), f.shape[0], _stream(stream), C.byref(h)))
+        create = _lib.hg_mesh_create_intrinsic if intrinsic else _lib.hg_mesh_create
+        _check(create(v.ctypes.data_as(C.c_void_p), v.shape[0], f.ctypes.data_as(C.c_void_p), f.shape[0],
+                      _stream(stream), C.byref(h)))
         self._h = h
         st = MeshStats()
         _check(_lib.hg_mesh_get_stats(self._h, C.byref(st)))
@@ -270,6 +274,14 @@ class Mesh:
         return {"chosen": rep.chosen,
                 "candidates": [{"schedule": rep.schedule[i], "inner_sweeps": rep.inner_sweeps[i],
                                 "ms": rep.ms[i], "passes": rep.passes[i]} for i in range(k)]}
+
+    def intrinsic_triangulation(self):
+        """(flipped triangles int32[F, 3], edge lengths float64[E] in
+        canonical edge order) of an intrinsic mesh (hg_mesh_intrinsic)."""
+        tri = np.zeros((self.nf, 3), dtype=np.int32)
+        length = np.zeros(self.ne, dtype=np.float64)
+        _check(_lib.hg_mesh_intrinsic(self._h, tri.ctypes.data, length.ctypes.data))
+        return tri, length
 
     def cycles(self, form: str = "edge"):
         """The generator loops of the cycle constraints (hg_mesh_cycles), as a

@@ -16,6 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 SOURCES = [
     "mesh_build.cpp",
     "cycles.cpp",
+    "intrinsic.cpp",
     "api.cpp",
     "kernels_mesh.hip",
     "kernels_bfs.hip",

@@ -142,6 +142,8 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
         HG_CHECK_HIP(hipStreamWaitEvent(w.own_stream, w.ev, 0));
         s = w.own_stream;
     }
+    if (m->intrinsic && o.formulation == HG_FORM_FACE)
+        throw Error{HG_E_INVALID_ARG, "the face form needs an extrinsic mesh (hg_mesh_create)"};
     auto si = map_sources(*m, src, nsrc);
     std::vector<double> tt = resolve_t(*m, t, o);
     StageTimer tm(s);
@@ -232,18 +234,61 @@ hg_status hg_opts_default(hg_opts* o) {
 
 const char* hg_last_error(void) { return g_last_error.c_str(); }
 
-hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, void* stream,
-                         hg_mesh_t* out) {
+// Mesh creation: from the caller's triangles, or (intrinsic) from the
+// intrinsic Delaunay triangulation of them with the geometry taken from the
+// intrinsic edge lengths.
+static hg_status create_mesh(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, void* stream,
+                             hg_mesh_t* out, bool intrinsic) {
     return guarded([&]() -> hg_status {
         if (!xyz || !tri || !out) return fail(HG_E_INVALID_ARG, "null argument");
         *out = nullptr;
         hipStream_t s = (hipStream_t)stream;
+        IntrinsicTri idt;
+        if (intrinsic) build_intrinsic(xyz, nv, tri, nf, idt);
         HostTopo T;
-        build_topology(xyz, nv, tri, nf, 1024, T);
+        build_topology(xyz, nv, intrinsic ? idt.tri.data() : tri, nf, 1024, T);
         build_cycles(T);
+        std::vector<double> elen, floc;
+        if (intrinsic) {
+            // per internal edge length; per internal face its corners in its
+            // own plane, (0,0), (l01,0), (x2,y2) by the law of cosines
+            elen.resize(T.ne);
+            for (int64_t e = 0; e < T.ne; ++e)
+                elen[e] = idt.edge_length(T.perm_v[T.ev[2 * e]], T.perm_v[T.ev[2 * e + 1]]);
+            floc.resize(3 * T.nf);
+            for (int64_t f = 0; f < T.nf; ++f) {
+                double l[3];
+                for (int k = 0; k < 3; ++k) l[k] = elen[slot_edge(T.fslot[3 * f + k])];
+                const double x2 = (l[0] * l[0] + l[2] * l[2] - l[1] * l[1]) / (2.0 * l[0]);
+                const double y2 = std::sqrt(std::max(l[2] * l[2] - x2 * x2, 0.0));
+                floc[3 * f] = l[0];
+                floc[3 * f + 1] = x2;
+                floc[3 * f + 2] = y2;
+                if (!(y2 > 0.0)) throw Error{HG_E_BAD_MESH, "degenerate intrinsic triangle"};
+            }
+            // t = m hbar^2 from the input mesh's edges (per component too)
+            std::vector<double> len(T.n_comp, 0.0);
+            std::vector<int64_t> cnt(T.n_comp, 0);
+            for (size_t i = 0; i < idt.input_a.size(); ++i) {
+                const int c = T.comp[T.iperm_v[idt.input_a[i]]];
+                len[c] += idt.input_len[i];
+                cnt[c]++;
+            }
+            for (int c = 0; c < T.n_comp; ++c) T.comp_hbar[c] = cnt[c] ? len[c] / (double)cnt[c] : 0.0;
+        }
         auto* m = new Mesh();
         try {
             HG_CHECK_HIP(hipGetDevice(&m->device));
+            m->intrinsic = intrinsic;
+            if (intrinsic) {
+                m->n_flips = idt.n_flips;
+                m->n_nondelaunay = idt.n_nondelaunay;
+                m->hbar = idt.hbar_input;
+                m->floc.upload(floc, s);
+                m->idt_tri_host = idt.tri;
+                m->idt_len_canon.resize(T.ne);
+                for (int64_t e = 0; e < T.ne; ++e) m->idt_len_canon[T.perm_e[e]] = elen[e];
+            }
             m->nv = T.nv;
             m->nf = T.nf;
             m->ne = T.ne;
@@ -294,12 +339,33 @@ hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int6
             m->cyc_f_edge.swap(T.cyc_f_edge);
             m->cyc_f_vec.swap(T.cyc_f_vec);
             m->w.ensure_pinned();
-            geometry_init(*m, s);
+            geometry_init(*m, s, intrinsic ? &elen : nullptr);
         } catch (...) {
             delete m;
             throw;
         }
         *out = reinterpret_cast<hg_mesh_t>(m);
+        return HG_OK;
+    });
+}
+
+hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, void* stream,
+                         hg_mesh_t* out) {
+    return create_mesh(xyz, nv, tri, nf, stream, out, false);
+}
+
+hg_status hg_mesh_create_intrinsic(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, void* stream,
+                                   hg_mesh_t* out) {
+    return create_mesh(xyz, nv, tri, nf, stream, out, true);
+}
+
+hg_status hg_mesh_intrinsic(hg_mesh_t mesh, int32_t* tri_out, double* length_out) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || !tri_out || !length_out) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        if (!m->intrinsic) return fail(HG_E_INVALID_ARG, "mesh was not created with hg_mesh_create_intrinsic");
+        std::copy(m->idt_tri_host.begin(), m->idt_tri_host.end(), tri_out);
+        std::copy(m->idt_len_canon.begin(), m->idt_len_canon.end(), length_out);
         return HG_OK;
     });
 }
@@ -325,6 +391,9 @@ hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* st) {
         st->n_cycles = m->n_cycles;
         st->cycle_edges = (int32_t)m->cyc_e_edge.size();
         st->cycle_faces = (int32_t)m->cyc_f_face.size();
+        st->intrinsic = m->intrinsic ? 1 : 0;
+        st->n_flips = (int32_t)m->n_flips;
+        st->n_nondelaunay = (int32_t)m->n_nondelaunay;
         return HG_OK;
     });
 }
@@ -420,6 +489,8 @@ static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, const int32_t* s
         auto* m = reinterpret_cast<Mesh*>(mesh);
         hipStream_t s = (hipStream_t)stream;
         hg_opts o = resolve_opts(opts);
+        if (m->intrinsic && form == HG_FORM_FACE)
+            return fail(HG_E_INVALID_ARG, "the face form needs an extrinsic mesh (hg_mesh_create)");
         if (o.mu == 0.0) o.mu = 100.0;   // no breadth-first depth here: the paper's value
         const bool src_paths = src && nsrc > 1 && o.source_paths;
         const bool cycles = o.cycle_constraints && m->n_cycles > 0;
@@ -467,6 +538,8 @@ static hg_status integrate_stage(hg_mesh_t mesh, const int32_t* src, int32_t nsr
         if (!mesh || !in || !d_dev) return fail(HG_E_INVALID_ARG, "null argument");
         auto* m = reinterpret_cast<Mesh*>(mesh);
         hipStream_t s = (hipStream_t)stream;
+        if (m->intrinsic && form == HG_FORM_FACE)
+            return fail(HG_E_INVALID_ARG, "the face form needs an extrinsic mesh (hg_mesh_create)");
         auto si = map_sources(*m, src, nsrc);
         int depth = run_bfs(*m, m->w, si, s);
         if (form == HG_FORM_EDGE) {

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/hgeo.h"
@@ -120,6 +121,20 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri, int64_t n
 // Fills the cyc_* loops of a built topology (tree-cotree, caller-id rules).
 void build_cycles(HostTopo& T);
 
+// Intrinsic Delaunay triangulation (edge flips on intrinsic lengths) of a
+// caller mesh: the flipped triangles (caller vertex ids, rows in the input's
+// order) and the length of every edge of the result.
+struct IntrinsicTri {
+    std::vector<int32_t> tri;
+    std::unordered_map<uint64_t, double> length;   // key (min id << 32) | max id
+    int64_t n_flips = 0, n_nondelaunay = 0;
+    double hbar_input = 0.0;                       // mean edge length of the input mesh
+    std::vector<int32_t> input_a;                  // input edges: one endpoint and the length
+    std::vector<double> input_len;
+    double edge_length(int32_t a, int32_t b) const;
+};
+void build_intrinsic(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, IntrinsicTri& out);
+
 // Per-query device workspace.  A query runs on one Work and one stream; the
 // mesh data it reads is never written after mesh_create, so queries on the
 // same mesh with different Works may run concurrently on different streams.
@@ -224,6 +239,16 @@ struct Mesh {
     std::vector<int32_t> cyc_e_canon, cyc_f_caller;
     std::vector<float> cyc_e_sign, cyc_f_vec;
 
+    // intrinsic triangulation (hg_mesh_create_intrinsic): the faces are the
+    // flipped ones, floc[3f..3f+2] = (l_01, x_2, y_2) places face f's corners
+    // at (0, 0), (l_01, 0), (x_2, y_2) in its own plane; gradients and edge
+    // targets are taken in these frames
+    bool intrinsic = false;
+    int64_t n_flips = 0, n_nondelaunay = 0;
+    DBuf<double> floc;
+    std::vector<int32_t> idt_tri_host;                // caller vertex ids, [nf*3]
+    std::vector<double> idt_len_canon;                // per canonical edge
+
     // diffusion schedule picked by hg_mesh_autotune for options left at 0
     // (auto): 0 = not tuned
     int tuned_schedule = 0, tuned_inner = 0;
@@ -236,7 +261,8 @@ struct Mesh {
 };
 
 // ---- kernels / stage drivers (implemented in the .hip files) ----
-void geometry_init(Mesh& m, hipStream_t s);
+// elen: per internal edge length (intrinsic meshes; positions otherwise)
+void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen = nullptr);
 int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s);
 struct DiffusionResult {
     int sweeps = 0, passes = 0;

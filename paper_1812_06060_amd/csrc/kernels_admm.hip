@@ -60,7 +60,7 @@ __device__ inline double block_sum2(double v) {
 // proportional to sum_i u_i (n x e_i), n = (p1-p0)x(p2-p0), e_i the CCW edge
 // opposite corner i.
 __global__ void k_normalize(int nf, const int32_t* tri, const double* px, const double* py, const double* pz,
-                            const double* v, const int32_t* e, float* h) {
+                            const double* floc, const double* v, const int32_t* e, float* h) {
     int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int id[3] = {tri[3 * f], tri[3 * f + 1], tri[3 * f + 2]};
@@ -73,10 +73,19 @@ __global__ void k_normalize(int nf, const int32_t* tri, const double* px, const 
         if (vv[k] != 0.0) m = max(m, ee[k]);
     }
     double p[3][3];
-    for (int k = 0; k < 3; ++k) {
-        p[k][0] = px[id[k]];
-        p[k][1] = py[id[k]];
-        p[k][2] = pz[id[k]];
+    if (floc) {   // intrinsic: the face's own plane, h in that frame (z = 0)
+        p[0][0] = p[0][1] = p[0][2] = 0.0;
+        p[1][0] = floc[3 * f];
+        p[1][1] = p[1][2] = 0.0;
+        p[2][0] = floc[3 * f + 1];
+        p[2][1] = floc[3 * f + 2];
+        p[2][2] = 0.0;
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            p[k][0] = px[id[k]];
+            p[k][1] = py[id[k]];
+            p[k][2] = pz[id[k]];
+        }
     }
     double a[3], b[3], n[3];
     for (int c = 0; c < 3; ++c) {
@@ -127,10 +136,31 @@ __global__ void k_edge_targets(int ne, const int32_t* ev, const int32_t* ef, con
     sumz[e] = (float)s;
 }
 
+// Intrinsic meshes: per edge, the sum over its faces of h_f . (P_head -
+// P_tail) with the corners P in each face's own frame (Eq. 18).
+__global__ void k_edge_targets_local(int ne, const int32_t* ef, const uint32_t* fslot, const uint8_t* fsign,
+                                     const double* floc, const float* h, float* sumz) {
+    int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    double s = 0.0;
+    for (int q = 0; q < 2; ++q) {
+        int f = ef[2 * e + q];
+        if (f < 0) continue;
+        const double P[3][2] = {{0.0, 0.0}, {floc[3 * f], 0.0}, {floc[3 * f + 1], floc[3 * f + 2]}};
+        for (int k = 0; k < 3; ++k) {
+            if (slot_edge(fslot[3 * f + k]) != e) continue;
+            const double dx = P[(k + 1) % 3][0] - P[k][0], dy = P[(k + 1) % 3][1] - P[k][1];
+            const double z = (double)h[3 * f] * dx + (double)h[3 * f + 1] * dy;
+            s += ((fsign[f] >> k) & 1) ? z : -z;   // the slot runs tail -> head, or the reverse
+        }
+    }
+    sumz[e] = (float)s;
+}
+
 void run_normalize(Mesh& m, Work& w, hipStream_t s) {
     w.h.alloc((size_t)3 * m.nf);
     hipLaunchKernelGGL(k_normalize, dim3(grid_for(m.nf, kBlockA)), dim3(kBlockA), 0, s, (int)m.nf, m.tri.p, m.px.p,
-                       m.py.p, m.pz.p, w.v0.p, w.e0.p, w.h.p);
+                       m.py.p, m.pz.p, m.intrinsic ? m.floc.p : nullptr, w.v0.p, w.e0.p, w.h.p);
     HG_CHECK_HIP(hipGetLastError());
 }
 
@@ -458,8 +488,12 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const float mu = (float)o.mu, inv1mu = 1.0f / (1.0f + mu), mu_relax = (float)(o.mu * o.relax);
     const int gf = grid_for(nf, kBlockA), ge = grid_for(ne, kBlockA);
     if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
-    hipLaunchKernelGGL(k_edge_targets, dim3(ge), dim3(kBlockA), 0, s, ne, m.ev.p, m.ef.p, m.px.p, m.py.p, m.pz.p,
-                       w.h.p, w.sumz.p);
+    if (m.intrinsic)
+        hipLaunchKernelGGL(k_edge_targets_local, dim3(ge), dim3(kBlockA), 0, s, ne, m.ef.p, m.fslot.p, m.fsign.p,
+                           m.floc.p, w.h.p, w.sumz.p);
+    else
+        hipLaunchKernelGGL(k_edge_targets, dim3(ge), dim3(kBlockA), 0, s, ne, m.ev.p, m.ef.p, m.px.p, m.py.p,
+                           m.pz.p, w.h.p, w.sumz.p);
     hipLaunchKernelGGL(k_zeta_init, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, w.sumz.p, mu, w.z0.p, w.sumd.p);
     HG_CHECK_HIP(hipGetLastError());
     auto& P = w.paths;

@@ -65,14 +65,30 @@ __device__ inline void cross3(const double a[3], const double b[3], double r[3])
 }
 __device__ inline double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+// Corner positions of face f: from the vertex positions, or (intrinsic
+// meshes, floc != null) the face's own plane: (0,0,0), (l01,0,0), (x2,y2,0).
+__device__ inline void face_corners(int f, const int32_t* tri, const double* px, const double* py, const double* pz,
+                                    const double* floc, double p[3][3]) {
+    if (floc) {
+        p[0][0] = p[0][1] = p[0][2] = 0.0;
+        p[1][0] = floc[3 * f];
+        p[1][1] = p[1][2] = 0.0;
+        p[2][0] = floc[3 * f + 1];
+        p[2][1] = floc[3 * f + 2];
+        p[2][2] = 0.0;
+    } else {
+        for (int k = 0; k < 3; ++k) load3(px, py, pz, tri[3 * f + k], p[k]);
+    }
+}
+
 // Per face: area and the cotangent of each corner angle; flags degenerate faces.
 __global__ void k_face_geom(int nf, const int32_t* tri, const double* px, const double* py, const double* pz,
-                            double* farea, double* fcot, int* bad, double* partial) {
+                            const double* floc, double* farea, double* fcot, int* bad, double* partial) {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
     double a2 = 0.0;
     if (f < nf) {
         double p[3][3];
-        for (int k = 0; k < 3; ++k) load3(px, py, pz, tri[3 * f + k], p[k]);
+        face_corners(f, tri, px, py, pz, floc, p);
         double e1[3], e2[3], n[3];
         sub3(p[1], p[0], e1);
         sub3(p[2], p[0], e2);
@@ -96,7 +112,7 @@ __global__ void k_face_geom(int nf, const int32_t* tri, const double* px, const 
 // the edge length (partial sums for the mean).
 __global__ void k_edge_theta(int ne, const int32_t* ev, const int32_t* ef, const uint32_t* fslot,
                              const double* fcot, const double* px, const double* py, const double* pz,
-                             double* theta_e, float* ebar, double* partial) {
+                             const double* elen, double* theta_e, float* ebar, double* partial) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     double len = 0.0;
     if (e < ne) {
@@ -108,14 +124,19 @@ __global__ void k_edge_theta(int ne, const int32_t* ev, const int32_t* ef, const
                 if (slot_edge(fslot[3 * f + k]) == e) th += 0.5 * fcot[3 * f + (k + 2) % 3];
         }
         theta_e[e] = th;
-        double a[3], b[3], d[3];
-        load3(px, py, pz, ev[2 * e], a);
-        load3(px, py, pz, ev[2 * e + 1], b);
-        sub3(b, a, d);
-        len = sqrt(dot3(d, d));
-        ebar[3 * e] = (float)(d[0] / len);
-        ebar[3 * e + 1] = (float)(d[1] / len);
-        ebar[3 * e + 2] = (float)(d[2] / len);
+        if (elen) {   // intrinsic: no embedding, no unit edge vectors (face form only)
+            len = elen[e];
+            ebar[3 * e] = ebar[3 * e + 1] = ebar[3 * e + 2] = 0.f;
+        } else {
+            double a[3], b[3], d[3];
+            load3(px, py, pz, ev[2 * e], a);
+            load3(px, py, pz, ev[2 * e + 1], b);
+            sub3(b, a, d);
+            len = sqrt(dot3(d, d));
+            ebar[3 * e] = (float)(d[0] / len);
+            ebar[3 * e + 1] = (float)(d[1] / len);
+            ebar[3 * e + 2] = (float)(d[2] / len);
+        }
     }
     double s = block_reduce(len, false);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -143,9 +164,10 @@ __global__ void k_vertex_fill(int nv, const int32_t* row_ptr, const int32_t* csr
     Av[j] = ar / 6.0;
 }
 
-void geometry_init(Mesh& m, hipStream_t s) {
+void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host) {
     const int nf = (int)m.nf, ne = (int)m.ne, nv = (int)m.nv;
-    DBuf<double> fcot, theta_e;
+    DBuf<double> fcot, theta_e, elen;
+    if (elen_host) elen.upload(*elen_host, s);
     DBuf<int> bad;
     fcot.alloc((size_t)3 * nf);
     theta_e.alloc(ne);
@@ -158,17 +180,18 @@ void geometry_init(Mesh& m, hipStream_t s) {
     m.ebar.alloc((size_t)3 * ne);
     int gf = grid_for(nf, kBlock), ge = grid_for(ne, kBlock);
     m.w.partial.alloc((size_t)std::max(gf, ge) + 8);
-    hipLaunchKernelGGL(k_face_geom, dim3(gf), dim3(kBlock), 0, s, nf, m.tri.p, m.px.p, m.py.p, m.pz.p, m.farea.p,
-                       fcot.p, bad.p, m.w.partial.p);
+    hipLaunchKernelGGL(k_face_geom, dim3(gf), dim3(kBlock), 0, s, nf, m.tri.p, m.px.p, m.py.p, m.pz.p,
+                       m.intrinsic ? m.floc.p : nullptr, m.farea.p, fcot.p, bad.p, m.w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
     m.total_area = reduce_partials(m, m.w, gf, false, s);
     int hbad = 0;
     HG_CHECK_HIP(hipMemcpy(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost));
     if (hbad) throw Error{HG_E_BAD_MESH, "zero-area face"};
     hipLaunchKernelGGL(k_edge_theta, dim3(ge), dim3(kBlock), 0, s, ne, m.ev.p, m.ef.p, m.fslot.p, fcot.p, m.px.p,
-                       m.py.p, m.pz.p, theta_e.p, m.ebar.p, m.w.partial.p);
+                       m.py.p, m.pz.p, elen_host ? elen.p : nullptr, theta_e.p, m.ebar.p, m.w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
-    m.hbar = reduce_partials(m, m.w, ge, false, s) / (double)ne;
+    const double hb = reduce_partials(m, m.w, ge, false, s) / (double)ne;
+    if (!m.intrinsic) m.hbar = hb;   // intrinsic: the input mesh's mean edge length, set by the caller
     hipLaunchKernelGGL(k_vertex_fill, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, nv, m.row_ptr.p,
                        m.csr_edge.p, m.ef.p, theta_e.p, m.farea.p, m.theta.p, m.sum_theta.p, m.Av.p);
     HG_CHECK_HIP(hipGetLastError());
