@@ -14,7 +14,6 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/hgeo.h"
@@ -124,9 +123,22 @@ void build_cycles(HostTopo& T);
 // Intrinsic Delaunay triangulation (edge flips on intrinsic lengths) of a
 // caller mesh: the flipped triangles (caller vertex ids, rows in the input's
 // order) and the length of every edge of the result.
+struct EdgeTable {   // edge key (min id << 32 | max id) -> record, open addressing
+    static constexpr uint64_t kEmpty = ~0ull, kTomb = ~0ull - 1;
+    std::vector<uint64_t> key;
+    std::vector<int32_t> val;
+    size_t used = 0, tomb = 0;
+    void init(size_t n_keys);
+    size_t slot_of(uint64_t k) const;
+    int32_t find(uint64_t k) const;   // -1 if absent
+    void insert(uint64_t k, int32_t v);
+    void erase(uint64_t k);
+    void rehash();
+};
 struct IntrinsicTri {
     std::vector<int32_t> tri;
-    std::unordered_map<uint64_t, double> length;   // key (min id << 32) | max id
+    EdgeTable index;                               // edge -> record
+    std::vector<double> rec_len;                   // length per record
     int64_t n_flips = 0, n_nondelaunay = 0;
     double hbar_input = 0.0;                       // mean edge length of the input mesh
     std::vector<int32_t> input_a;                  // input edges: one endpoint and the length
