@@ -84,6 +84,30 @@ def test_bad_meshes_rejected_before_any_device_work(lib, tris, what):
     assert st == _hgeo.HG_E_BAD_MESH and what in msg
 
 
+@pytest.mark.parametrize("tris, what", [
+    ([[0, 1, 5]], "out of range"),
+    ([[0, 1, 1]], "repeats"),
+    ([[0, 1, 2], [0, 1, 3]], "inconsistent"),
+    ([[0, 1, 2], [1, 0, 3], [0, 1, 4]], "non-manifold"),
+])
+def test_bad_meshes_rejected_by_intrinsic_build(lib, tris, what):
+    """The host edge-flip build validates its input before any device work."""
+    v = np.random.default_rng(0).standard_normal((5, 3))
+    f = np.ascontiguousarray(np.asarray(tris, dtype=np.int32))
+    h = C.c_void_p()
+    st = lib.hg_mesh_create_intrinsic(v.ctypes.data_as(C.c_void_p), v.shape[0], f.ctypes.data_as(C.c_void_p),
+                                      f.shape[0], None, C.byref(h))
+    assert st == _hgeo.HG_E_BAD_MESH and what in lib.hg_last_error().decode()
+
+
+def test_mesh_readback_rejects_null_arguments(lib):
+    buf_i = (C.c_int32 * 4)()
+    buf_f = (C.c_float * 4)()
+    buf_d = (C.c_double * 4)()
+    assert lib.hg_mesh_cycles(None, _hgeo.FORM_EDGE, buf_i, buf_i, buf_f, 4) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_mesh_intrinsic(None, buf_i, buf_d) == _hgeo.HG_E_INVALID_ARG
+
+
 def test_null_and_empty_arguments(lib):
     h = C.c_void_p()
     assert lib.hg_mesh_create(None, 3, None, 1, None, C.byref(h)) == _hgeo.HG_E_INVALID_ARG
