@@ -206,6 +206,11 @@ struct Work {
         DBuf<int2> gzslot;                      // per edge group: the same
         DBuf<float> z;                          // folded copies: [ns] edge form, [3*ns] face form
         DBuf<float> seff;                       // edge form: [ne] effective target sums
+        // edge form: each group's slots cut into chunks of kPathChunk; a
+        // chunk's partial sum of the projection, the path of each slot
+        int nch = 0;
+        DBuf<int32_t> spath, cptr, chunk_path;  // [ns], [np+1], [nch]
+        DBuf<double> pc;                        // [nch]
         size_t bytes() const;
     } paths;
     size_t bytes() const;
@@ -440,6 +445,10 @@ void edges_to_user(Mesh& m, int32_t* edges_user, hipStream_t s);
 double reduce_partials(Mesh& m, Work& w, int nblocks, bool is_max, hipStream_t s);
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+// slots of a constraint group summed by one workgroup of the edge-form
+// projection (several workgroups per long path or loop)
+constexpr int kPathChunk = 1024;
 
 // Blocks are dealt round-robin to the 8 XCDs of an MI355X; remap so that
 // each XCD processes one contiguous range of the index space (consecutive

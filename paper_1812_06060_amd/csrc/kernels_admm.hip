@@ -297,13 +297,15 @@ __global__ void k_edge_x(int ne, const int32_t* h01, const int32_t* ef, const fl
 }
 
 // ------------------------------------------------- source paths (Eqs. 24-25)
-// Each path S of w.paths adds a group of copies with the constraint of
-// Eq. 25 (edge form) or Eq. 24 (face form); their duals are folded like the
-// face copies.  One iteration = the form's face kernel, then
-// k_path_*_proj (one block per path: the group's projection, from the same
-// state the face kernel read), then k_path_*_fix (one thread per edge or
-// face that carries path copies: completes the update the face kernel did
-// without them).
+// Each path S of w.paths (a source path, or a generator loop of Sec. 5.1)
+// adds a group of copies with the constraint of Eq. 25 / 23 (edge form) or
+// Eq. 24 / 22 (face form); their duals are folded like the face copies.
+// Edge form: one launch holds the face update and the chunk sums of every
+// group's projection (from the state the face kernel read), then
+// k_path_edge_fix (one thread per edge carrying copies) projects the copies
+// and completes the X-update.  Face form: the face kernel, k_path_face_proj
+// (one block per group), k_path_face_fix (one thread per face carrying
+// copies).
 //
 // Edge form.  Per path slot keep zeta_S = kappa + mu v_hat; with n_e path
 // slots on edge e the X-update becomes
@@ -341,60 +343,82 @@ __global__ void k_path_edge_zinit(int ns, const int32_t* edge, const int32_t* ef
     zp[k] = mu * (sumz[e] / nh);   // kappa = 0, v = x = mean target
 }
 
-__device__ inline void path_edge_proj_block(int p, const int32_t* __restrict__ ptr, const int32_t* __restrict__ edge,
-                                            const float* __restrict__ sign, const int2* __restrict__ zslot,
-                                            const float* __restrict__ seff, const float* __restrict__ zin,
-                                            float* zp, float mu, float inv1mu, float mu_relax, double* sh) {
-    const int b = ptr[p], n = ptr[p + 1] - b;
+// Edge-form projection, first half: chunk c of path p sums s . t over its
+// slots (t = 2 x - zeta_S / mu with x from the previous state), one
+// workgroup per chunk of kPathChunk slots; pc[c] = the chunk's sum.
+__device__ inline void path_edge_chunk_block(int c, const int32_t* __restrict__ chunk_path,
+                                             const int32_t* __restrict__ cptr, const int32_t* __restrict__ ptr,
+                                             const int32_t* __restrict__ edge, const float* __restrict__ sign,
+                                             const int2* __restrict__ zslot, const float* __restrict__ seff,
+                                             const float* __restrict__ zin, const float* __restrict__ zp,
+                                             double* __restrict__ pc, float mu, float inv1mu, double* sh) {
+    const int p = chunk_path[c];
+    const int b = ptr[p] + (c - cptr[p]) * kPathChunk;
+    const int end = min(ptr[p + 1], b + kPathChunk);
     double acc = 0.0;
-    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
+    for (int k = b + threadIdx.x; k < end; k += blockDim.x) {
         const int e = edge[k];
         const int2 hh = zslot[k];
-        float x = edge_x(seff[e], zin[hh.x], hh.y >= 0 ? zin[hh.y] : 0.f, hh.y < 0, inv1mu);
+        const float x = edge_x(seff[e], zin[hh.x], hh.y >= 0 ? zin[hh.y] : 0.f, hh.y < 0, inv1mu);
         acc += (double)sign[k] * (double)(2.f * x - zp[k] / mu);
     }
-    const float c = (float)(block_sum_all(acc, sh) / n);
-    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
-        const int e = edge[k];
-        const int2 hh = zslot[k];
-        float x = edge_x(seff[e], zin[hh.x], hh.y >= 0 ? zin[hh.y] : 0.f, hh.y < 0, inv1mu);
-        float t = 2.f * x - zp[k] / mu;
-        float v = t - c * sign[k];
-        zp[k] = zp[k] + mu_relax * (v - x);
-    }
+    acc = block_sum_all(acc, sh);
+    if (threadIdx.x == 0) pc[c] = acc;
 }
 
-// The face update and the path projections of one iteration in one launch:
-// blocks [0, np) project one path each -- long, latency-bound blocks, so
-// they are dispatched first and overlap the many short face blocks
-// [np, np + nfb) (both read the previous state only and write disjoint
-// outputs).
+// The face update and the chunk sums of one iteration in one launch: blocks
+// [0, nch) sum one chunk each, blocks [nch, nch + nfb) update faces (both
+// read the previous state only and write disjoint outputs).
 __global__ void __launch_bounds__(kBlockA) k_admm_edge_paths(
-    int nf, int nfb, int np, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
+    int nf, int nfb, int nch, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
     const float* __restrict__ sumd, const float* __restrict__ zin, float* __restrict__ zout,
-    const int32_t* __restrict__ ptr, const int32_t* __restrict__ edge, const float* __restrict__ sign,
-    const int2* __restrict__ zslot, const float* __restrict__ seff, float* zp, float mu, float inv1mu,
+    const int32_t* __restrict__ chunk_path, const int32_t* __restrict__ cptr, const int32_t* __restrict__ ptr,
+    const int32_t* __restrict__ edge, const float* __restrict__ sign, const int2* __restrict__ zslot,
+    const float* __restrict__ seff, const float* __restrict__ zp, double* __restrict__ pc, float mu, float inv1mu,
     float mu_relax) {
     __shared__ double sh[kBlockA / 64];
-    if ((int)blockIdx.x < np) {
-        path_edge_proj_block((int)blockIdx.x, ptr, edge, sign, zslot, seff, zin, zp, mu, inv1mu, mu_relax, sh);
+    if ((int)blockIdx.x < nch) {
+        path_edge_chunk_block((int)blockIdx.x, chunk_path, cptr, ptr, edge, sign, zslot, seff, zin, zp, pc, mu,
+                              inv1mu, sh);
         return;
     }
-    const int f = xcd_block((int)blockIdx.x - np, nfb) * blockDim.x + threadIdx.x;
+    const int f = xcd_block((int)blockIdx.x - nch, nfb) * blockDim.x + threadIdx.x;
     if (f < nf) admm_edge_face(f, twin, fsign, sumd, zin, zout, mu, inv1mu, mu_relax);
 }
 
+// Second half, one thread per edge carrying path slots: each slot's copy is
+// projected with its path's mean c = (sum of the path's chunk sums) / |S|,
+//   v = t - c s,  zeta_S' = zeta_S + mu alpha (v - x),
+// then the edge's X-update with those copies included gives the effective
+// target sum S' that the face kernel reads next (FP64: both terms are ~mu^2
+// times larger than their difference).
 __global__ void k_path_edge_fix(int ng, const int32_t* gptr, const int32_t* gid, const int32_t* gslot,
-                                const float* zp, const float* sumz, const float* zout, const int2* gzslot,
-                                double mu, float* seff, float* sumd) {
+                                const int32_t* spath, const int32_t* ptr, const int32_t* cptr, const double* pc,
+                                const float* sign, float* zp, const float* sumz, const float* zin, const float* zout,
+                                const int2* gzslot, float muf, float inv1mu, float mu_relax, float* seff,
+                                float* sumd) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const int e = gid[g];
-    double P = 0.0;
-    for (int j = gptr[g]; j < gptr[g + 1]; ++j) P += zp[gslot[j]];
-    const int n = gptr[g + 1] - gptr[g];
     const int h0 = gzslot[g].x, h1 = gzslot[g].y;
     const bool bnd = h1 < 0;
+    const float xo = edge_x(seff[e], zin[h0], bnd ? 0.f : zin[h1], bnd, inv1mu);
+    double P = 0.0;
+    for (int j = gptr[g]; j < gptr[g + 1]; ++j) {
+        const int k = gslot[j];
+        const int p = spath[k];
+        double sum = 0.0;
+        for (int c = cptr[p]; c < cptr[p + 1]; ++c) sum += pc[c];
+        const float cc = (float)(sum / (double)(ptr[p + 1] - ptr[p]));
+        const float z = zp[k];
+        const float t = 2.f * xo - z / muf;
+        const float v = t - cc * sign[k];
+        const float zn = z + mu_relax * (v - xo);
+        zp[k] = zn;
+        P += zn;
+    }
+    const int n = gptr[g + 1] - gptr[g];
+    const double mu = muf;
     const double Z = (double)zout[h0] + (bnd ? 0.0 : (double)zout[h1]);
     const double D0 = (bnd ? 1.0 : 2.0) * (1.0 + mu);
     const double x = ((double)sumz[e] + P + Z) / (D0 + mu * n);
@@ -519,9 +543,13 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     // and twin slots and its sign byte read, its three zeta written (the
     // twins' zeta are the same array, read by their own faces)
     r.bytes_per_iter = (uint64_t)49 * nf;
-    // path kernels: per slot its edge, sign, copy (read + write), the edge's
-    // zeta pair, S' and ef; per group its slot list, copies, S, zeta pair, S'
-    if (use_paths) r.bytes_per_iter += (uint64_t)32 * P.ns + (uint64_t)8 * P.ns + (uint64_t)28 * P.ng_edge;
+    // path kernels: chunk sums read per slot its edge, slot pair, S', zeta
+    // pair, sign and copy (28 B) and write 8 B per chunk; the fix reads per
+    // slot its index, path, sign and copy and writes the copy (20 B), per
+    // group its slot range, id, slot pair, S', old and new zeta pairs and S
+    // and writes S' three times (52 B)
+    if (use_paths)
+        r.bytes_per_iter += (uint64_t)48 * P.ns + (uint64_t)8 * P.nch + (uint64_t)52 * P.ng_edge;
     RunTimer rt;
     int run_len = 0;
     DistStop stop;
@@ -541,12 +569,12 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
             hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.twin.p, m.fsign.p, w.sumd.p, zi, zo,
                                mu, inv1mu, mu_relax);
         } else {
-            hipLaunchKernelGGL(k_admm_edge_paths, dim3(gf + P.np), dim3(kBlockA), 0, s, nf, gf, P.np, m.twin.p, m.fsign.p,
-                               w.sumd.p, zi, zo, P.ptr.p, P.edge.p, P.sign.p, P.zslot.p, S, P.z.p, mu, inv1mu,
-                               mu_relax);
+            hipLaunchKernelGGL(k_admm_edge_paths, dim3(gf + P.nch), dim3(kBlockA), 0, s, nf, gf, P.nch, m.twin.p,
+                               m.fsign.p, w.sumd.p, zi, zo, P.chunk_path.p, P.cptr.p, P.ptr.p, P.edge.p, P.sign.p,
+                               P.zslot.p, S, P.z.p, P.pc.p, mu, inv1mu, mu_relax);
             hipLaunchKernelGGL(k_path_edge_fix, dim3(grid_for(P.ng_edge, kBlockA)), dim3(kBlockA), 0, s, P.ng_edge,
-                               P.eg_ptr.p, P.eg_id.p, P.eg_slot.p, P.z.p, w.sumz.p, zo, P.gzslot.p, (double)mu, P.seff.p,
-                               w.sumd.p);
+                               P.eg_ptr.p, P.eg_id.p, P.eg_slot.p, P.spath.p, P.ptr.p, P.cptr.p, P.pc.p, P.sign.p,
+                               P.z.p, w.sumz.p, zi, zo, P.gzslot.p, mu, inv1mu, mu_relax, P.seff.p, w.sumd.p);
         }
     };
     // runs of `check` iterations between two checks; with an even count the

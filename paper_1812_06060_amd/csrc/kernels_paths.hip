@@ -205,6 +205,21 @@ void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_in
     }
     if (P.np == 0) return;
     P.ptr.upload(h_ptr, s);
+    {
+        // chunks of the edge-form projection, and the group of each slot
+        std::vector<int32_t> spath(P.ns), cptr(P.np + 1, 0), chunk_path;
+        for (int i = 0; i < P.np; ++i) {
+            for (int k = h_ptr[i]; k < h_ptr[i + 1]; ++k) spath[k] = i;
+            const int nc = (h_ptr[i + 1] - h_ptr[i] + kPathChunk - 1) / kPathChunk;
+            cptr[i + 1] = cptr[i] + nc;
+            for (int c = 0; c < nc; ++c) chunk_path.push_back(i);
+        }
+        P.nch = cptr[P.np];
+        P.spath.upload(spath, s);
+        P.cptr.upload(cptr, s);
+        P.chunk_path.upload(chunk_path, s);
+        P.pc.alloc(P.nch);
+    }
     P.edge.upload(h_edge, s);
     P.face.upload(h_face, s);
     P.sign.upload(h_sign, s);
