@@ -112,6 +112,16 @@ typedef struct {
                                Eq. 22 face form), so that it is the gradient
                                of a function there; 0 = without them.
                                Components with boundary get none. */
+    double tol_seam;        /* hg_geodesic_solve: at each distance check also
+                               measure the seam, max over edges of
+                               |d_head - d_tail - x_e| / hbar (d the field
+                               integrated along the breadth-first tree, x_e
+                               the edge difference of the optimised field;
+                               zero on the tree's edges, elsewhere the jump
+                               left by what is still not a gradient), and
+                               stop only once it is <= tol_seam as well;
+                               default 0 = not required (it is reported in
+                               hg_info.seam either way) */
     int32_t reserved[2];
 } hg_opts;
 
@@ -140,7 +150,9 @@ typedef struct {
     int32_t n_cycles;       /* generator loops constrained (Sec. 5.1) */
     int32_t cycle_slots;    /* total edges (edge form) or faces (face form)
                                over those loops */
-    int32_t reserved[4];
+    float seam;             /* hg_geodesic_solve: the last check's largest
+                               seam / hbar (see hg_opts.tol_seam) */
+    int32_t reserved[3];
 } hg_info;
 
 /* Mesh statistics. */

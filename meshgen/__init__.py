@@ -152,7 +152,7 @@ def _icosahedron():
     return v, f
 
 
-def icosphere(level: int):
+def icosphere(level: int, progress=None):
     """Unit icosphere after ``level`` rounds of 1->4 midpoint subdivision.
 
     V = 10*4^L + 2, F = 20*4^L.  Vertex order: the parent vertices first, then
@@ -183,6 +183,8 @@ def icosphere(level: int):
             np.stack([m01, m12, m20], axis=1),
         ], axis=0)
         del e, key, ukey, inv, mid
+        if progress is not None:
+            progress(f"icosphere: subdivision round done, {v.shape[0]} vertices")
     return np.ascontiguousarray(v), np.ascontiguousarray(f.astype(np.int32))
 
 
@@ -230,25 +232,40 @@ def _real_sph_harm(l: int, m: int, theta, phi):
     return np.sqrt(2.0) * (-1.0) ** m * np.imag(y)
 
 
+def _harmonic_sum(args):
+    p, ls, ms, cs = args
+    theta = np.arccos(np.clip(p[:, 2], -1.0, 1.0))
+    phi = np.arctan2(p[:, 1], p[:, 0])
+    acc = np.zeros(p.shape[0])
+    for l, m, c in zip(ls, ms, cs):
+        acc += c * _real_sph_harm(int(l), int(m), theta, phi)
+    return acc
+
+
 def harmonic_displacement(verts, seed: int, n_terms: int = 8, lmax: int = 16,
-                          amp: float = 0.05, chunk: int = 1 << 22):
+                          amp: float = 0.05, chunk: int = 1 << 22, workers: int = 1, progress=None):
     """Radially displace unit-sphere vertices: r = 1 + amp * S / max|S| with
     S = sum_k c_k Y_{l_k}^{m_k}, l_k ~ U{1..lmax}, m_k ~ U{-l..l},
-    c_k ~ U(-1, 1)."""
+    c_k ~ U(-1, 1).  `workers` > 1 evaluates the chunks in a process pool
+    (same values)."""
     rng = np.random.default_rng(seed)
     ls = rng.integers(1, lmax + 1, size=n_terms)
     ms = np.array([rng.integers(-l, l + 1) for l in ls])
     cs = rng.uniform(-1.0, 1.0, size=n_terms)
     n = verts / np.linalg.norm(verts, axis=1, keepdims=True)
     S = np.empty(n.shape[0], dtype=np.float64)
-    for s in range(0, n.shape[0], chunk):
-        p = n[s:s + chunk]
-        theta = np.arccos(np.clip(p[:, 2], -1.0, 1.0))
-        phi = np.arctan2(p[:, 1], p[:, 0])
-        acc = np.zeros(p.shape[0])
-        for l, m, c in zip(ls, ms, cs):
-            acc += c * _real_sph_harm(int(l), int(m), theta, phi)
-        S[s:s + chunk] = acc
+    starts = list(range(0, n.shape[0], chunk))
+    jobs = ((n[s:s + chunk], ls, ms, cs) for s in starts)
+    if workers > 1 and len(starts) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            for i, (s, acc) in enumerate(zip(starts, pool.imap(_harmonic_sum, jobs))):
+                S[s:s + chunk] = acc
+                if progress is not None and (i + 1) % 8 == 0:
+                    progress(f"harmonic displacement: {i + 1}/{len(starts)} chunks")
+    else:
+        for s, job in zip(starts, jobs):
+            S[s:s + chunk] = _harmonic_sum(job)
     r = 1.0 + amp * S / np.max(np.abs(S))
     return n * r[:, None]
 

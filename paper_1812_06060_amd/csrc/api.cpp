@@ -84,6 +84,7 @@ static hg_opts resolve_opts(const hg_opts* o) {
     if (r.use_graphs != 0 && r.use_graphs != 1) throw Error{HG_E_INVALID_ARG, "use_graphs must be 0 or 1"};
     if (r.t_per_component != 0 && r.t_per_component != 1)
         throw Error{HG_E_INVALID_ARG, "t_per_component must be 0 or 1"};
+    if (!(r.tol_seam >= 0.0) || !std::isfinite(r.tol_seam)) throw Error{HG_E_INVALID_ARG, "tol_seam must be >= 0"};
     if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
         throw Error{HG_E_INVALID_ARG, "iteration caps must be positive"};
     return r;
@@ -204,6 +205,7 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
         info->path_edges = paths ? w.paths.ns_src : 0;
         info->n_cycles = paths ? w.paths.n_cyc : 0;
         info->cycle_slots = paths ? w.paths.ns_cyc : 0;
+        info->seam = (float)ar.seam;
     }
     if (!dr.converged) return {HG_E_NOT_CONVERGED, "diffusion sweep cap reached"};
     if (!ar.converged) return {HG_E_NOT_CONVERGED, "ADMM iteration cap reached"};

@@ -302,6 +302,7 @@ void normalize_from_logu(Mesh& m, Work& w, const double* logu_user, hipStream_t 
 struct AdmmResult {
     int iters = 0;
     double rp = 0.0, rd = 0.0;
+    double seam = 0.0;           // last check's largest seam / hbar (distance monitor only)
     bool converged = false;
     double kernel_ms = 0.0;
     int timed_launches = 0;
@@ -392,9 +393,10 @@ void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_in
                             bool cycles, int form, hipStream_t s);
 void integrate(Mesh& m, Work& w, int form, int depth, float* d_user, hipStream_t s);
 // integrates the given state (edge differences xe or face gradients g) and
-// returns max |d - d_prev| (inf on the first call) and max |d|; d_prev <- d
+// returns max |d - d_prev| (inf on the first call) and max |d|; d_prev <- d;
+// with seam, also the largest |d_head - d_tail - x_e| over the edges
 void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
-                 double& delta, double& dmax);
+                 double& delta, double& dmax, double* seam = nullptr);
 
 // Stopping rule on the distance field: with delta_k the largest change of d
 // between two checks and r = delta_k / delta_{k-1} < 1, the remaining change

@@ -615,8 +615,11 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                 hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
                                    w.xe.p);
                 double delta, dmax;
-                dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax);
+                double seam;
+                dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax, &seam);
+                r.seam = seam / m.hbar;
                 done = stop.update(delta, dmax, o.tol_admm);
+                done = done && (o.tol_seam <= 0.0 || r.seam <= o.tol_seam);
             } else {
                 residuals(zb, za);
                 done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;
@@ -853,8 +856,11 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
             bool done;
             if (monitor) {
                 double delta, dmax;
-                dist_change(m, w, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax);
+                double seam;
+                dist_change(m, w, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax, &seam);
+                r.seam = seam / m.hbar;
                 done = stop.update(delta, dmax, o.tol_admm);
+                done = done && (o.tol_seam <= 0.0 || r.seam <= o.tol_seam);
             } else {
                 face_residuals(m, w, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
                 done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;

@@ -194,8 +194,44 @@ __global__ void k_reduce_pairs_max(double* partial, int n) {
     }
 }
 
+// Largest disagreement over the edges between the integrated distance and
+// the optimised field, |d_head - d_tail - x_e| (face form: x_e = the mean of
+// g_f . (p_head - p_tail) over the edge's faces).  It is zero on the edges
+// the integration followed; elsewhere it is the jump of d across the edge
+// left by what is still not a gradient in the field, the seam between
+// branches of the breadth-first tree.  partial[block] = the block's largest.
+__global__ void k_seam(int ne, const int32_t* ev, const int32_t* ef, const int32_t* jp, const float* d,
+                       const float* xe, const float* g, const double* px, const double* py, const double* pz,
+                       double* partial) {
+    __shared__ double sh[kBlockI / 64];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double sm = 0.0;
+    if (e < ne) {
+        const int a = ev[2 * e], b = ev[2 * e + 1];
+        if (jp[a] >= 0 && jp[b] >= 0) {
+            double x = 0.0;
+            if (xe) {
+                x = xe[e];
+            } else {
+                const double dx = px[b] - px[a], dy = py[b] - py[a], dz = pz[b] - pz[a];
+                int n = 0;
+                for (int q = 0; q < 2; ++q) {
+                    const int f = ef[2 * e + q];
+                    if (f < 0) continue;
+                    x += (double)g[3 * f] * dx + (double)g[3 * f + 1] * dy + (double)g[3 * f + 2] * dz;
+                    ++n;
+                }
+                x /= n;
+            }
+            sm = fabs((double)d[b] - (double)d[a] - x);
+        }
+    }
+    sm = blk_max2(sm, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sm;
+}
+
 void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
-                 double& delta, double& dmax) {
+                 double& delta, double& dmax, double* seam) {
     const int nv = (int)m.nv;
     w.dprev.alloc(nv);
     const int grid = grid_for(nv, kBlockI);
@@ -209,6 +245,14 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
     HG_CHECK_HIP(hipStreamSynchronize(s));
     delta = w.pinned[0];
     dmax = w.pinned[1];
+    if (seam) {
+        const int ge = grid_for(m.ne, kBlockI);
+        if ((int)w.partial.n < ge + 8) w.partial.alloc((size_t)ge + 8);
+        hipLaunchKernelGGL(k_seam, dim3(ge), dim3(kBlockI), 0, s, (int)m.ne, m.ev.p, m.ef.p, r.jp, w.dprev.p,
+                           form == HG_FORM_EDGE ? xe : nullptr, g, m.px.p, m.py.p, m.pz.p, w.partial.p);
+        HG_CHECK_HIP(hipGetLastError());
+        *seam = reduce_partials(m, w, ge, true, s);
+    }
 }
 
 }  // namespace hg

@@ -117,3 +117,22 @@ def test_source_paths_off_reports_none(case, hg):
     d, info = mesh.solve(src, 0.0, hg.default_opts(source_paths=0))
     assert info.n_paths == 0 and info.path_edges == 0
     assert np.all(np.isfinite(d.cpu().numpy()))
+
+
+def test_seam_reported_and_required(hg):
+    """The distance check's seam (largest |d_head - d_tail - x_e| / hbar,
+    zero on the integration tree's edges) is reported; with tol_seam the
+    ADMM runs on until it is met.  A loose distance tolerance leaves a
+    visible seam on a level-7 sphere."""
+    v, f = meshgen.icosphere(7)
+    v = meshgen.harmonic_displacement(v, seed=3)
+    src = meshgen.random_sources(v.shape[0], 1, seed=104)
+    mesh = hg.Mesh(v, f)
+    try:
+        d0, i0 = mesh.solve(src, 0.0, hg.default_opts(tol_admm=1e-3))
+        d1, i1 = mesh.solve(src, 0.0, hg.default_opts(tol_admm=1e-3, tol_seam=0.5 * i0.seam))
+    finally:
+        mesh.close()
+    _say("seam loose", i0.seam, i0.admm_iters, "required", i1.seam, i1.admm_iters)
+    assert i0.seam > 0.0 and i1.converged_admm
+    assert i1.seam <= 0.5 * i0.seam and i1.admm_iters > i0.admm_iters
