@@ -397,6 +397,9 @@ void integrate(Mesh& m, Work& w, int form, int depth, float* d_user, hipStream_t
 // with seam, also the largest |d_head - d_tail - x_e| over the edges
 void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
                  double& delta, double& dmax, double* seam = nullptr);
+// the largest |d_head - d_tail - x_e| for the d of the last dist_change and
+// the given field (the same state)
+double seam_now(Mesh& m, Work& w, int form, const float* xe, const float* g, hipStream_t s);
 
 // Stopping rule on the distance field: with delta_k the largest change of d
 // between two checks and r = delta_k / delta_{k-1} < 1, the remaining change
@@ -405,15 +408,24 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
 // rounding floor (<= tol * max|d| / 100; the rounding noise of d is orders of
 // magnitude lower, and a slowly converging iteration -- time constant tau
 // iterations -- is only stopped early by this rule if tau >~ 64 * 100).
+//
+// Checks run every chunk of iterations; while the estimated remaining change
+// is far above the tolerance (> 300 tol max|d|) they run every
+// kCoarseChecks chunks instead, back to every chunk once it is within
+// 30 tol max|d|.  restart() drops the ratio at a switch, so that a decision
+// always compares two intervals of the same length.
 struct DistStop {
     bool first = true;
     double prev = 0.0;
+    double est = INFINITY;   // last estimate of the remaining change
     bool update(double delta, double dmax, double tol) {
         bool done = false;
+        est = INFINITY;
         if (!first && std::isfinite(delta)) {
             if (std::isfinite(prev) && prev > 0.0 && delta < prev) {
                 double r = delta / prev;
-                done = delta * r / (1.0 - r) <= tol * dmax;
+                est = delta * r / (1.0 - r);
+                done = est <= tol * dmax;
             }
             if (delta <= 0.01 * tol * dmax) done = true;
         }
@@ -421,7 +433,11 @@ struct DistStop {
         prev = delta;
         return done;
     }
+    bool near(double dmax, double tol) const { return est <= 30.0 * tol * dmax; }
+    bool far(double dmax, double tol) const { return std::isfinite(est) && est > 300.0 * tol * dmax; }
+    void restart() { prev = NAN; }
 };
+constexpr int kCoarseChecks = 4;   // chunks between checks far from convergence
 
 // One whole query (the body of hg_geodesic_solve) on a given workspace and
 // stream; throws Error for invalid arguments and device failures.

@@ -537,6 +537,9 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const bool monitor = !fixed && depth >= 0;
     const int cap = fixed ? iters : o.max_admm;
     const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
+    // iterations between two checks: one chunk, or kCoarseChecks chunks far
+    // from convergence (DistStop)
+    int interval = check, next_check = check;
     float* za = w.z0.p;
     float* zb = w.z1.p;
     // algorithmic bytes of one iteration: per face its three zeta, S copies
@@ -608,22 +611,31 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         run_len = n;
         r.kernel_ms += rt.stop(s);
         r.timed_launches += run_len;
-        const bool want = (it % check) == 0 || it == cap;
+        const bool want = it >= next_check || it == cap;
         if (!fixed && want) {
             bool done;
             if (monitor) {
                 hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
                                    w.xe.p);
                 double delta, dmax;
-                double seam;
-                dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax, &seam);
+                double seam = 0.0;
+                dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax,
+                            o.tol_seam > 0.0 ? &seam : nullptr);
                 r.seam = seam / m.hbar;
                 done = stop.update(delta, dmax, o.tol_admm);
                 done = done && (o.tol_seam <= 0.0 || r.seam <= o.tol_seam);
+                if (!done && interval == check && stop.far(dmax, o.tol_admm)) {
+                    interval = kCoarseChecks * check;
+                    stop.restart();
+                } else if (!done && interval > check && stop.near(dmax, o.tol_admm)) {
+                    interval = check;
+                    stop.restart();
+                }
             } else {
                 residuals(zb, za);
                 done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;
             }
+            next_check = it + interval;
             if (done) {
                 r.converged = true;
                 break;
@@ -638,6 +650,9 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     if (r.iters > 0) residuals(zb, za);
     hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu, w.xe.p);
     HG_CHECK_HIP(hipGetLastError());
+    // the seam of the final state (its d is the last check's), once
+    if (monitor && !stop.first && o.tol_seam <= 0.0)
+        r.seam = seam_now(m, w, HG_FORM_EDGE, w.xe.p, nullptr, s) / m.hbar;
     if (za != w.z0.p)
         HG_CHECK_HIP(hipMemcpyAsync(w.z0.p, za, (size_t)3 * nf * sizeof(float), hipMemcpyDeviceToDevice, s));
     return r;
@@ -799,6 +814,9 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const bool monitor = !fixed && depth >= 0;
     const int cap = fixed ? iters : o.max_admm;
     const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
+    // iterations between two checks: one chunk, or kCoarseChecks chunks far
+    // from convergence (DistStop)
+    int interval = check, next_check = check;
     float *ga = w.g0.p, *gb = w.g1.p, *za = w.z0.p, *zb = w.z1.p;
     // algorithmic bytes of one iteration: per face g, h, fslot, area read and
     // g written; per edge ef, unit vector and both z copies read, z written
@@ -851,20 +869,29 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         run_len = n;
         r.kernel_ms += rt.stop(s);
         r.timed_launches += run_len;
-        const bool want = (it % check) == 0 || it == cap;
+        const bool want = it >= next_check || it == cap;
         if (!fixed && want) {
             bool done;
             if (monitor) {
                 double delta, dmax;
-                double seam;
-                dist_change(m, w, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax, &seam);
+                double seam = 0.0;
+                dist_change(m, w, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax,
+                            o.tol_seam > 0.0 ? &seam : nullptr);
                 r.seam = seam / m.hbar;
                 done = stop.update(delta, dmax, o.tol_admm);
                 done = done && (o.tol_seam <= 0.0 || r.seam <= o.tol_seam);
+                if (!done && interval == check && stop.far(dmax, o.tol_admm)) {
+                    interval = kCoarseChecks * check;
+                    stop.restart();
+                } else if (!done && interval > check && stop.near(dmax, o.tol_admm)) {
+                    interval = check;
+                    stop.restart();
+                }
             } else {
                 face_residuals(m, w, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
                 done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;
             }
+            next_check = it + interval;
             if (done) {
                 r.converged = true;
                 break;
@@ -876,6 +903,7 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         r.timed_launches += run_len;
     }
     if (fixed) r.converged = true;
+    if (monitor && !stop.first && o.tol_seam <= 0.0) r.seam = seam_now(m, w, HG_FORM_FACE, nullptr, ga, s) / m.hbar;
     if (r.iters > 0) face_residuals(m, w, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
     HG_CHECK_HIP(hipMemcpyAsync(w.gf.p, ga, (size_t)3 * nf * sizeof(float), hipMemcpyDeviceToDevice, s));
     return r;

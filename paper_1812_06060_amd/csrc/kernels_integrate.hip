@@ -200,7 +200,7 @@ __global__ void k_reduce_pairs_max(double* partial, int n) {
 // the integration followed; elsewhere it is the jump of d across the edge
 // left by what is still not a gradient in the field, the seam between
 // branches of the breadth-first tree.  partial[block] = the block's largest.
-__global__ void k_seam(int ne, const int32_t* ev, const int32_t* ef, const int32_t* jp, const float* d,
+__global__ void k_seam(int ne, const int32_t* ev, const int32_t* ef, const int32_t* level, const float* d,
                        const float* xe, const float* g, const double* px, const double* py, const double* pz,
                        double* partial) {
     __shared__ double sh[kBlockI / 64];
@@ -208,7 +208,7 @@ __global__ void k_seam(int ne, const int32_t* ev, const int32_t* ef, const int32
     double sm = 0.0;
     if (e < ne) {
         const int a = ev[2 * e], b = ev[2 * e + 1];
-        if (jp[a] >= 0 && jp[b] >= 0) {
+        if (level[a] >= 0 && level[b] >= 0) {
             double x = 0.0;
             if (xe) {
                 x = xe[e];
@@ -245,14 +245,16 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
     HG_CHECK_HIP(hipStreamSynchronize(s));
     delta = w.pinned[0];
     dmax = w.pinned[1];
-    if (seam) {
-        const int ge = grid_for(m.ne, kBlockI);
-        if ((int)w.partial.n < ge + 8) w.partial.alloc((size_t)ge + 8);
-        hipLaunchKernelGGL(k_seam, dim3(ge), dim3(kBlockI), 0, s, (int)m.ne, m.ev.p, m.ef.p, r.jp, w.dprev.p,
-                           form == HG_FORM_EDGE ? xe : nullptr, g, m.px.p, m.py.p, m.pz.p, w.partial.p);
-        HG_CHECK_HIP(hipGetLastError());
-        *seam = reduce_partials(m, w, ge, true, s);
-    }
+    if (seam) *seam = seam_now(m, w, form, xe, g, s);
+}
+
+double seam_now(Mesh& m, Work& w, int form, const float* xe, const float* g, hipStream_t s) {
+    const int ge = grid_for(m.ne, kBlockI);
+    if ((int)w.partial.n < ge + 8) w.partial.alloc((size_t)ge + 8);
+    hipLaunchKernelGGL(k_seam, dim3(ge), dim3(kBlockI), 0, s, (int)m.ne, m.ev.p, m.ef.p, w.level.p, w.dprev.p,
+                       form == HG_FORM_EDGE ? xe : nullptr, g, m.px.p, m.py.p, m.pz.p, w.partial.p);
+    HG_CHECK_HIP(hipGetLastError());
+    return reduce_partials(m, w, ge, true, s);
 }
 
 }  // namespace hg
