@@ -29,7 +29,7 @@ import time
 import numpy as np
 
 
-def build_pool(levels, n_meshes: int, seed: int = 5):
+def build_pool(levels, n_meshes: int, seed: int = 5, workers: int = 1):
     import meshgen
     lo, hi = levels
     rng = np.random.default_rng(seed)
@@ -43,7 +43,7 @@ def build_pool(levels, n_meshes: int, seed: int = 5):
         if L not in base:
             base[L] = meshgen.icosphere(L)
         v, f = base[L]
-        pool.append((L, meshgen.harmonic_displacement(v, seed=5000 + i), f))
+        pool.append((L, meshgen.harmonic_displacement(v, seed=5000 + i, workers=workers), f))
     return pool
 
 
@@ -62,13 +62,18 @@ def _pct(x, p):
     return float(np.percentile(np.asarray(x), p)) if len(x) else float("nan")
 
 
-def run(levels=(4, 8), n_meshes=32, n_queries=150, n_warm=16, rate_frac=0.9, slots=4, seed=6, log=print):
+def run(levels=(4, 8), n_meshes=32, n_queries=150, n_warm=16, rate_frac=0.9, slots=4, seed=6, log=print,
+        rate_fracs=None, workers=1):
+    """Serve the same seeded query stream at each rate in `rate_fracs`
+    (default: just `rate_frac`); the pool, the queries and the references
+    (one plain solve per query) are built once.  Returns one result per rate
+    (a single dict when one rate is asked for)."""
     import torch
 
     import paper_1812_06060_amd as hg
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    pool = build_pool(levels, n_meshes)
+    pool = build_pool(levels, n_meshes, workers=workers)
     meshes = [hg.Mesh(v, f) for _, v, f in pool]
     log(f"[serve] pool of {len(meshes)} meshes (levels {levels[0]}-{levels[1]}, "
         f"{sum(m.nv for m in meshes)} vertices) ready in {time.perf_counter() - t0:.1f}s")
@@ -84,69 +89,79 @@ def run(levels=(4, 8), n_meshes=32, n_queries=150, n_warm=16, rate_frac=0.9, slo
         meshes[i].solve(src, 0.0, opts, out=outs[j])
         torch.cuda.synchronize()
         service.append(time.perf_counter() - a)
+        if (j + 1) % 25 == 0:
+            log(f"[serve] reference solves: {j + 1}/{len(qs)}")
     ref = [o.cpu().numpy() for o in outs]
     svc = np.array(service[n_warm:])
     sat = 1.0 / svc.mean()
-    rate = rate_frac * sat
     log(f"[serve] plain service time mean {1e3 * svc.mean():.1f} ms (p50 {1e3 * _pct(svc, 50):.1f}, "
-        f"p99 {1e3 * _pct(svc, 99):.1f}); saturation {sat:.2f} q/s; offered {rate:.2f} q/s")
-    rng = np.random.default_rng(seed + 1)
-    gaps = rng.exponential(1.0 / rate, size=n_queries)
-    arrivals = np.cumsum(gaps) - gaps[0]
+        f"p99 {1e3 * _pct(svc, 99):.1f}); saturation {sat:.2f} q/s")
     timed = list(range(n_warm, n_warm + n_queries))
+    results = []
+    for rf in (rate_fracs if rate_fracs else [rate_frac]):
+        rate = rf * sat
+        rng = np.random.default_rng(seed + 1)
+        gaps = rng.exponential(1.0 / rate, size=n_queries)
+        arrivals = np.cumsum(gaps) - gaps[0]
 
-    # plain: one query at a time, in arrival order, on the arrival clock
-    lat_plain = []
-    start = time.perf_counter()
-    for k, j in enumerate(timed):
-        now = time.perf_counter() - start
-        if now < arrivals[k]:
-            time.sleep(arrivals[k] - now)
-        i, src = qs[j]
-        meshes[i].solve(src, 0.0, opts, out=outs[j])
-        torch.cuda.synchronize()
-        lat_plain.append(time.perf_counter() - start - arrivals[k])
-    span_plain = time.perf_counter() - start
-    same_plain = all(np.array_equal(outs[j].cpu().numpy(), ref[j]) for j in timed)
+        # plain: one query at a time, in arrival order, on the arrival clock
+        lat_plain = []
+        start = time.perf_counter()
+        for k, j in enumerate(timed):
+            now = time.perf_counter() - start
+            if now < arrivals[k]:
+                time.sleep(arrivals[k] - now)
+            i, src = qs[j]
+            meshes[i].solve(src, 0.0, opts, out=outs[j])
+            torch.cuda.synchronize()
+            lat_plain.append(time.perf_counter() - start - arrivals[k])
+            if (k + 1) % 25 == 0:
+                log(f"[serve] rate x{rf}: plain {k + 1}/{n_queries}")
+        span_plain = time.perf_counter() - start
+        same_plain = all(np.array_equal(outs[j].cpu().numpy(), ref[j]) for j in timed)
 
-    # served: submitted at the arrival times, completions taken by a thread
-    # (the server stamps each query at submit: latency = t_end - t_submit)
-    srv = hg.Server(slots)
-    lat_srv = {}
-    t_end = {}
-    clock0 = hg.Server.clock()
-    base = time.perf_counter()
+        # served: submitted at the arrival times, completions taken by a thread
+        # (the server stamps each query at submit: latency = t_end - t_submit)
+        srv = hg.Server(slots)
+        lat_srv = {}
+        t_end = {}
+        clock0 = hg.Server.clock()
+        base = time.perf_counter()
 
-    def collect():
-        for _ in timed:
-            r = srv.wait(-1)
-            lat_srv[r["ticket"]] = r["t_end"] - r["t_submit"]
-            t_end[r["ticket"]] = r["t_end"]
+        def collect():
+            for c in range(len(timed)):
+                r = srv.wait(-1)
+                lat_srv[r["ticket"]] = r["t_end"] - r["t_submit"]
+                t_end[r["ticket"]] = r["t_end"]
+                if (c + 1) % 25 == 0:
+                    log(f"[serve] rate x{rf}: served {c + 1}/{n_queries}")
 
-    th = threading.Thread(target=collect)
-    th.start()
-    for k, j in enumerate(timed):
-        now = time.perf_counter() - base
-        if now < arrivals[k]:
-            time.sleep(arrivals[k] - now)
-        i, src = qs[j]
-        srv.submit(meshes[i], src, out=outs[j], opts=opts)
-    th.join()
-    span_srv = max(t_end.values()) - clock0
-    srv.close()
-    same_srv = all(np.array_equal(outs[j].cpu().numpy(), ref[j]) for j in timed)
-    lat_s = list(lat_srv.values())
-    res = {
-        "queries": n_queries, "pool_levels": list(levels), "pool_meshes": len(meshes), "slots": slots,
-        "offered_qps": rate, "plain_saturation_qps": sat,
-        "served": {"qps": n_queries / span_srv, "p50_ms": 1e3 * _pct(lat_s, 50), "p99_ms": 1e3 * _pct(lat_s, 99)},
-        "plain": {"qps": n_queries / span_plain, "p50_ms": 1e3 * _pct(lat_plain, 50),
-                  "p99_ms": 1e3 * _pct(lat_plain, 99)},
-        "results_identical": bool(same_plain and same_srv),
-    }
+        th = threading.Thread(target=collect)
+        th.start()
+        for k, j in enumerate(timed):
+            now = time.perf_counter() - base
+            if now < arrivals[k]:
+                time.sleep(arrivals[k] - now)
+            i, src = qs[j]
+            srv.submit(meshes[i], src, out=outs[j], opts=opts)
+        th.join()
+        span_srv = max(t_end.values()) - clock0
+        srv.close()
+        same_srv = all(np.array_equal(outs[j].cpu().numpy(), ref[j]) for j in timed)
+        lat_s = list(lat_srv.values())
+        res = {
+            "queries": n_queries, "pool_levels": list(levels), "pool_meshes": len(meshes), "slots": slots,
+            "rate_frac": rf, "offered_qps": rate, "plain_saturation_qps": sat,
+            "served": {"qps": n_queries / span_srv, "p50_ms": 1e3 * _pct(lat_s, 50), "p99_ms": 1e3 * _pct(lat_s, 99)},
+            "plain": {"qps": n_queries / span_plain, "p50_ms": 1e3 * _pct(lat_plain, 50),
+                      "p99_ms": 1e3 * _pct(lat_plain, 99)},
+            "results_identical": bool(same_plain and same_srv),
+        }
+        log(f"[serve] rate x{rf}: served {res['served']}, plain {res['plain']}, identical {res['results_identical']}")
+        results.append(res)
     for m in meshes:
         m.close()
-    return res
+    return results if rate_fracs else results[0]
 
 
 def main():
@@ -157,12 +172,12 @@ def main():
     ap.add_argument("--warm", type=int, default=16)
     ap.add_argument("--rates", default="0.9")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=1, help="processes for the mesh displacement")
     a = ap.parse_args()
     lo, hi = (int(x) for x in a.levels.split("-"))
-    for rf in (float(x) for x in a.rates.split(",")):
-        r = run((lo, hi), a.meshes, a.queries, a.warm, rf, a.slots,
-                log=lambda s: print(s, file=sys.stderr, flush=True))
-        r["rate_frac"] = rf
+    rates = [float(x) for x in a.rates.split(",")]
+    for r in run((lo, hi), a.meshes, a.queries, a.warm, slots=a.slots, rate_fracs=rates, workers=a.workers,
+                 log=lambda s: print(s, file=sys.stderr, flush=True)):
         print(json.dumps(r), flush=True)
 
 
