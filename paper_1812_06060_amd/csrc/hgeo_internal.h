@@ -206,11 +206,11 @@ struct Work {
         DBuf<int2> gzslot;                      // per edge group: the same
         DBuf<float> z;                          // folded copies: [ns] edge form, [3*ns] face form
         DBuf<float> seff;                       // edge form: [ne] effective target sums
-        // edge form: each group's slots cut into chunks of kPathChunk; a
-        // chunk's partial sum of the projection, the path of each slot
+        // each group's slots cut into chunks of kPathChunk; a chunk's
+        // partial sums of the projection, the group of each slot
         int nch = 0;
         DBuf<int32_t> spath, cptr, chunk_path;  // [ns], [np+1], [nch]
-        DBuf<double> pc;                        // [nch]
+        DBuf<double> pc;                        // [2 nch]
         size_t bytes() const;
     } paths;
     size_t bytes() const;

@@ -300,12 +300,11 @@ __global__ void k_edge_x(int ne, const int32_t* h01, const int32_t* ef, const fl
 // Each path S of w.paths (a source path, or a generator loop of Sec. 5.1)
 // adds a group of copies with the constraint of Eq. 25 / 23 (edge form) or
 // Eq. 24 / 22 (face form); their duals are folded like the face copies.
-// Edge form: one launch holds the face update and the chunk sums of every
-// group's projection (from the state the face kernel read), then
-// k_path_edge_fix (one thread per edge carrying copies) projects the copies
-// and completes the X-update.  Face form: the face kernel, k_path_face_proj
-// (one block per group), k_path_face_fix (one thread per face carrying
-// copies).
+// In both forms one launch holds the face update and the chunk sums of
+// every group's projection (chunks of kPathChunk slots, from the state the
+// face kernel reads), then k_path_*_fix (one thread per edge or face
+// carrying copies) projects the copies with their group's sums and
+// completes the update the face kernel did without them.
 //
 // Edge form.  Per path slot keep zeta_S = kappa + mu v_hat; with n_e path
 // slots on edge e the X-update becomes
@@ -321,7 +320,6 @@ __global__ void k_edge_x(int ne, const int32_t* h01, const int32_t* ef, const fl
 // sum_j e_j . y_j = 0 is y_j = q_j - (c / A_j) e_j with
 // c = sum_j e_j . q_j / sum_j |e_j|^2 / A_j, z_S' = z_S + alpha (y - g_f), and the
 // fix kernel redoes the G-update of a face with its path copies included.
-constexpr int kBlockPath = 1024;
 
 __device__ inline double block_sum_all(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -435,45 +433,18 @@ __global__ void k_path_face_zinit(int ns, const int32_t* face, const float* h, f
     for (int c = 0; c < 3; ++c) zp[3 * k + c] = h[3 * f + c];   // y = g = h, kappa = 0
 }
 
-__global__ void __launch_bounds__(kBlockPath) k_path_face_proj(const int32_t* __restrict__ ptr,
-                                                               const int32_t* __restrict__ face,
-                                                               const float* __restrict__ vec,
-                                                               const double* __restrict__ farea,
-                                                               const float* __restrict__ gin, float* zp, float relax) {
-    __shared__ double sh[kBlockPath / 64];
-    const int b = ptr[blockIdx.x], n = ptr[blockIdx.x + 1] - b;
-    double dot = 0.0, den = 0.0;
-    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
-        int f = face[k];
-        double ee = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            double ec = vec[3 * k + c];
-            dot += ec * (double)(2.f * gin[3 * f + c] - zp[3 * k + c]);
-            ee += ec * ec;
-        }
-        den += ee / farea[f];
-    }
-    dot = block_sum_all(dot, sh);
-    den = block_sum_all(den, sh);
-    const double cc = dot / den;
-    for (int k = b + threadIdx.x; k < b + n; k += blockDim.x) {
-        int f = face[k];
-        const float ca = (float)(cc / farea[f]);
-        for (int c = 0; c < 3; ++c) {
-            float g = gin[3 * f + c];
-            float q = 2.f * g - zp[3 * k + c];
-            float y = q - ca * vec[3 * k + c];
-            zp[3 * k + c] = zp[3 * k + c] + relax * (y - g);
-        }
-    }
-}
-
+// Second half, one thread per face carrying group copies: each copy is
+// projected with its group's c = (sum e.q) / (sum |e|^2 / A):
+//   y = q - (c / A_f) e,  z_S' = z_S + alpha (y - g_f),
+// then the face's G-update is redone with those copies included.
 __global__ void k_path_face_fix(int ng, const int32_t* gptr, const int32_t* gid, const int32_t* gslot,
-                                const float* zp, const uint32_t* fslot, const float* zout, const float* h, float mu,
-                                float* gout) {
+                                const int32_t* spath, const int32_t* cptr, const double* pc, const float* vec,
+                                const double* farea, const float* gin, float* zp, const uint32_t* fslot,
+                                const float* zout, const float* h, float mu, float relax, float* gout) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const int f = gid[g];
+    const float go[3] = {gin[3 * f], gin[3 * f + 1], gin[3 * f + 2]};
     float acc[3] = {0.f, 0.f, 0.f};
     int cnt = 0;
     for (int k = 0; k < 3; ++k) {
@@ -484,12 +455,26 @@ __global__ void k_path_face_fix(int ng, const int32_t* gptr, const int32_t* gid,
         ++cnt;
     }
     for (int j = gptr[g]; j < gptr[g + 1]; ++j) {
-        const float* z = zp + 3 * gslot[j];
-        for (int c = 0; c < 3; ++c) acc[c] += z[c];
+        const int k = gslot[j];
+        const int p = spath[k];
+        double dot = 0.0, den = 0.0;
+        for (int c = cptr[p]; c < cptr[p + 1]; ++c) {
+            dot += pc[2 * c];
+            den += pc[2 * c + 1];
+        }
+        const float ca = (float)(dot / den / farea[f]);
+        float* z = zp + 3 * k;
+        for (int c = 0; c < 3; ++c) {
+            const float q = 2.f * go[c] - z[c];
+            const float y = q - ca * vec[3 * k + c];
+            const float zn = z[c] + relax * (y - go[c]);
+            z[c] = zn;
+            acc[c] += zn;
+        }
         ++cnt;
     }
-    const float den = 1.f / (2.f + mu * (float)cnt);
-    for (int c = 0; c < 3; ++c) gout[3 * f + c] = (2.f * h[3 * f + c] + mu * acc[c]) * den;
+    const float dn = 1.f / (2.f + mu * (float)cnt);
+    for (int c = 0; c < 3; ++c) gout[3 * f + c] = (2.f * h[3 * f + c] + mu * acc[c]) * dn;
 }
 
 static void reduce_pair(Mesh& m, Work& w, int nblocks, hipStream_t s, double& a, double& b) {
@@ -682,15 +667,11 @@ __global__ void k_face_init(int nf, int ne, const int32_t* ef, const float* h, f
     }
 }
 
-__global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* __restrict__ fslot,
-                                                       const int32_t* __restrict__ ef,
-                                                       const float* __restrict__ ebar,
-                                                       const double* __restrict__ farea,
-                                                       const float* __restrict__ h, const float* __restrict__ gin,
-                                                       const float* __restrict__ zin, float* __restrict__ gout,
-                                                       float* __restrict__ zout, float mu, float relax) {
-    int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
+__device__ inline void admm_face_one(int f, const uint32_t* __restrict__ fslot, const int32_t* __restrict__ ef,
+                                     const float* __restrict__ ebar, const double* __restrict__ farea,
+                                     const float* __restrict__ h, const float* __restrict__ gin,
+                                     const float* __restrict__ zin, float* __restrict__ gout,
+                                     float* __restrict__ zout, float mu, float relax) {
     const float g0 = gin[3 * f], g1 = gin[3 * f + 1], g2 = gin[3 * f + 2];
     const float Af = (float)farea[f];
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
@@ -727,6 +708,66 @@ __global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* _
     gout[3 * f] = (2.f * h[3 * f] + mu * acc0) * den;
     gout[3 * f + 1] = (2.f * h[3 * f + 1] + mu * acc1) * den;
     gout[3 * f + 2] = (2.f * h[3 * f + 2] + mu * acc2) * den;
+}
+
+__global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* __restrict__ fslot,
+                                                       const int32_t* __restrict__ ef,
+                                                       const float* __restrict__ ebar,
+                                                       const double* __restrict__ farea,
+                                                       const float* __restrict__ h, const float* __restrict__ gin,
+                                                       const float* __restrict__ zin, float* __restrict__ gout,
+                                                       float* __restrict__ zout, float mu, float relax) {
+    int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    admm_face_one(f, fslot, ef, ebar, farea, h, gin, zin, gout, zout, mu, relax);
+}
+
+// Face-form projection of the constraint groups, first half: chunk c of
+// group p sums e_j . (2 g_f - z_j) and |e_j|^2 / A_f over its slots (from
+// the state the face kernel reads); pc[2c], pc[2c+1] = the two sums.
+__device__ inline void path_face_chunk_block(int c, const int32_t* __restrict__ chunk_path,
+                                             const int32_t* __restrict__ cptr, const int32_t* __restrict__ ptr,
+                                             const int32_t* __restrict__ face, const float* __restrict__ vec,
+                                             const double* __restrict__ farea, const float* __restrict__ gin,
+                                             const float* __restrict__ zp, double* __restrict__ pc, double* sh) {
+    const int p = chunk_path[c];
+    const int b = ptr[p] + (c - cptr[p]) * kPathChunk;
+    const int end = min(ptr[p + 1], b + kPathChunk);
+    double dot = 0.0, den = 0.0;
+    for (int k = b + threadIdx.x; k < end; k += blockDim.x) {
+        const int f = face[k];
+        double ee = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            const double ec = vec[3 * k + q];
+            dot += ec * (double)(2.f * gin[3 * f + q] - zp[3 * k + q]);
+            ee += ec * ec;
+        }
+        den += ee / farea[f];
+    }
+    dot = block_sum_all(dot, sh);
+    den = block_sum_all(den, sh);
+    if (threadIdx.x == 0) {
+        pc[2 * c] = dot;
+        pc[2 * c + 1] = den;
+    }
+}
+
+// The face update and the chunk sums in one launch: blocks [0, nch) sum one
+// chunk each, blocks [nch, nch + nfb) update faces.
+__global__ void __launch_bounds__(kBlockA) k_admm_face_paths(
+    int nf, int nfb, int nch, const uint32_t* __restrict__ fslot, const int32_t* __restrict__ ef,
+    const float* __restrict__ ebar, const double* __restrict__ farea, const float* __restrict__ h,
+    const float* __restrict__ gin, const float* __restrict__ zin, float* __restrict__ gout, float* __restrict__ zout,
+    const int32_t* __restrict__ chunk_path, const int32_t* __restrict__ cptr, const int32_t* __restrict__ ptr,
+    const int32_t* __restrict__ face, const float* __restrict__ vec, const float* __restrict__ zp,
+    double* __restrict__ pc, float mu, float relax) {
+    __shared__ double sh[kBlockA / 64];
+    if ((int)blockIdx.x < nch) {
+        path_face_chunk_block((int)blockIdx.x, chunk_path, cptr, ptr, face, vec, farea, gin, zp, pc, sh);
+        return;
+    }
+    const int f = xcd_block((int)blockIdx.x - nch, nfb) * blockDim.x + threadIdx.x;
+    if (f < nf) admm_face_one(f, fslot, ef, ebar, farea, h, gin, zin, gout, zout, mu, relax);
 }
 
 // Per copy k of face i: r_p = sqrt(A_i) (y' - g') with y' = g + (z' - z)/alpha
@@ -821,20 +862,26 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     // algorithmic bytes of one iteration: per face g, h, fslot, area read and
     // g written; per edge ef, unit vector and both z copies read, z written
     r.bytes_per_iter = (uint64_t)56 * nf + (uint64_t)68 * ne;
-    // path kernels: per slot face, vector, area, g, copy (read + write); per
-    // group its slot list, the face's slots, z copies, path copies, h, g
-    if (use_paths) r.bytes_per_iter += (uint64_t)60 * P.ns + (uint64_t)16 * P.ns + (uint64_t)72 * P.ng_face;
+    // group kernels: the chunk sums read per slot its face, vector, area, g
+    // and copy (48 B) and write 16 B per chunk; the fix reads per slot its
+    // index, group, vector and copy and writes the copy (44 B), per face its
+    // slot range, id, slots, z copies, h, old g and area and writes g (100 B)
+    if (use_paths)
+        r.bytes_per_iter += (uint64_t)92 * P.ns + (uint64_t)16 * P.nch + (uint64_t)100 * P.ng_face;
     RunTimer rt;
     int run_len = 0;
     DistStop stop;
     auto iterate = [&](float* gi, float* zi, float* go, float* zo) {
-        hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.ef.p, m.ebar.p, m.farea.p,
-                           w.h.p, gi, zi, go, zo, mu, (float)o.relax);
-        if (use_paths) {
-            hipLaunchKernelGGL(k_path_face_proj, dim3(P.np), dim3(kBlockPath), 0, s, P.ptr.p, P.face.p, P.vec.p,
-                               m.farea.p, gi, P.z.p, (float)o.relax);
+        if (!use_paths) {
+            hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.ef.p, m.ebar.p,
+                               m.farea.p, w.h.p, gi, zi, go, zo, mu, (float)o.relax);
+        } else {
+            hipLaunchKernelGGL(k_admm_face_paths, dim3(gf + P.nch), dim3(kBlockA), 0, s, nf, gf, P.nch, m.fslot.p,
+                               m.ef.p, m.ebar.p, m.farea.p, w.h.p, gi, zi, go, zo, P.chunk_path.p, P.cptr.p, P.ptr.p,
+                               P.face.p, P.vec.p, P.z.p, P.pc.p, mu, (float)o.relax);
             hipLaunchKernelGGL(k_path_face_fix, dim3(grid_for(P.ng_face, kBlockA)), dim3(kBlockA), 0, s, P.ng_face,
-                               P.fg_ptr.p, P.fg_id.p, P.fg_slot.p, P.z.p, m.fslot.p, zo, w.h.p, mu, go);
+                               P.fg_ptr.p, P.fg_id.p, P.fg_slot.p, P.spath.p, P.cptr.p, P.pc.p, P.vec.p, m.farea.p,
+                               gi, P.z.p, m.fslot.p, zo, w.h.p, mu, (float)o.relax, go);
         }
     };
     // runs of `check` iterations between checks, one captured graph for every

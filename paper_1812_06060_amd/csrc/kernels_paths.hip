@@ -218,7 +218,7 @@ void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_in
         P.spath.upload(spath, s);
         P.cptr.upload(cptr, s);
         P.chunk_path.upload(chunk_path, s);
-        P.pc.alloc(P.nch);
+        P.pc.alloc((size_t)2 * P.nch);   // edge form: one sum per chunk, face form: two
     }
     P.edge.upload(h_edge, s);
     P.face.upload(h_face, s);
