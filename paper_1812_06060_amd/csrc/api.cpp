@@ -32,6 +32,7 @@ uint64_t Mesh::mesh_bytes() const {
     return px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() + ebar.bytes() +
+           sgeo.bytes() +
            tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
            theta_ell.bytes() + tile_order.bytes() + twin.bytes() + h01.bytes() + comp_v.bytes() + tile_comp.bytes();
 }

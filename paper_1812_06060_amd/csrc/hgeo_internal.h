@@ -233,7 +233,8 @@ struct Mesh {
     DBuf<uint8_t> fsign;
     DBuf<double> farea;                     // per face (FP64)
     DBuf<int32_t> ev, ef;
-    DBuf<float> ebar;                       // [ne*3] unit edge vectors (face form)
+    DBuf<float> ebar;                       // [ne*3] unit edge vectors (released after geometry_init)
+    DBuf<float4> sgeo;                      // [nf*3] per face slot: unit edge vector, A_nb / (A_own + A_nb)
     DBuf<int32_t> twin, h01;
 
     // patch tiles

@@ -27,6 +27,10 @@
 // g_i = (2 h_i + mu sum_k z_k) / (2 + mu |Y(i)|).  Each face computes its own
 // copies' Y-update (it reads the neighbour's g and z across the edge), so
 // one kernel per face performs Y, G and lambda updates.  z = h initially.
+// Layout, as in the edge form: the copies per face slot (3f + k), with each
+// slot's unit edge vector and neighbour weight A_nb / (A_own + A_nb) (sgeo)
+// and its twin slot, so a face reads and writes its own data contiguously
+// and gathers only the neighbours' g and copies: 168 bytes per face.
 //
 // g, z and zeta are double-buffered (Jacobi semantics, deterministic).
 // Residuals are those of the paper, recovered exactly from two consecutive
@@ -450,7 +454,7 @@ __global__ void k_path_face_fix(int ng, const int32_t* gptr, const int32_t* gid,
     for (int k = 0; k < 3; ++k) {
         uint32_t sl = fslot[3 * f + k];
         if (slot_bnd(sl)) continue;
-        const float* z = zout + 3 * (2 * slot_edge(sl) + slot_side(sl));
+        const float* z = zout + 9 * f + 3 * k;
         for (int c = 0; c < 3; ++c) acc[c] += z[c];
         ++cnt;
     }
@@ -644,58 +648,52 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
 }
 
 // ---------------------------------------------------------------- face form
-// z buffer layout: [2*ne][3], copy (e, side).
-__global__ void k_face_init(int nf, int ne, const int32_t* ef, const float* h, float* g, float* z) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nf) {
-        g[3 * i] = h[3 * i];
-        g[3 * i + 1] = h[3 * i + 1];
-        g[3 * i + 2] = h[3 * i + 2];
-    }
-    if (i < ne) {
-        for (int s = 0; s < 2; ++s) {
-            int f = ef[2 * i + s];
-            float* zz = z + 3 * (2 * i + s);
-            if (f >= 0) {
-                zz[0] = h[3 * f];
-                zz[1] = h[3 * f + 1];
-                zz[2] = h[3 * f + 2];
-            } else {
-                zz[0] = zz[1] = zz[2] = 0.f;
-            }
-        }
+// z layout: slot-major, the copy of face f on its slot k at z[3 (3f + k)];
+// every copy starts at h_f (a boundary slot's copy is never read).
+__global__ void k_face_init(int nf, const float* h, float* g, float* z) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    for (int d = 0; d < 3; ++d) {
+        const float v = h[3 * f + d];
+        g[3 * f + d] = v;
+        z[9 * f + d] = v;
+        z[9 * f + 3 + d] = v;
+        z[9 * f + 6 + d] = v;
     }
 }
 
-__device__ inline void admm_face_one(int f, const uint32_t* __restrict__ fslot, const int32_t* __restrict__ ef,
-                                     const float* __restrict__ ebar, const double* __restrict__ farea,
+// One face's Y/Z/G update.  Per slot k with a neighbour (twin slot t, face
+// t / 3): the two copies' W-projection onto the compatibility of Eq. 10 is
+// y_own = q_own + w (e . (q_nb - q_own)) e with q = 2 g - z, e the unit edge
+// vector and w = A_nb / (A_own + A_nb) (sgeo[slot] = (e, w)); then
+// z' = z + alpha (y - g) and g' = (2 h + mu sum z') / (2 + mu n).
+__device__ inline void admm_face_one(int f, const int32_t* __restrict__ twin, const float4* __restrict__ sgeo,
                                      const float* __restrict__ h, const float* __restrict__ gin,
                                      const float* __restrict__ zin, float* __restrict__ gout,
                                      float* __restrict__ zout, float mu, float relax) {
     const float g0 = gin[3 * f], g1 = gin[3 * f + 1], g2 = gin[3 * f + 2];
-    const float Af = (float)farea[f];
+    int tw[3];
+    float zo[9];
+    for (int k = 0; k < 3; ++k) tw[k] = twin[3 * f + k];
+    for (int i = 0; i < 9; ++i) zo[i] = zin[9 * f + i];
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     int cnt = 0;
     for (int k = 0; k < 3; ++k) {
-        uint32_t sl = fslot[3 * f + k];
-        if (slot_bnd(sl)) continue;
-        int e = slot_edge(sl), side = slot_side(sl);
-        int nb = ef[2 * e + (side ^ 1)];
-        const float* zo = zin + 3 * (2 * e + side);
-        const float* zn = zin + 3 * (2 * e + (side ^ 1));
-        float qo0 = 2.f * g0 - zo[0], qo1 = 2.f * g1 - zo[1], qo2 = 2.f * g2 - zo[2];
+        const int t = tw[k];
+        if (t < 0) continue;
+        const int nb = t / 3;
+        const float4 sg = sgeo[3 * f + k];
+        const float* zn = zin + 3 * t;
+        float qo0 = 2.f * g0 - zo[3 * k], qo1 = 2.f * g1 - zo[3 * k + 1], qo2 = 2.f * g2 - zo[3 * k + 2];
         float qn0 = 2.f * gin[3 * nb] - zn[0];
         float qn1 = 2.f * gin[3 * nb + 1] - zn[1];
         float qn2 = 2.f * gin[3 * nb + 2] - zn[2];
-        float e0 = ebar[3 * e], e1 = ebar[3 * e + 1], e2 = ebar[3 * e + 2];
-        float An = (float)farea[nb];
-        float sdot = e0 * (qn0 - qo0) + e1 * (qn1 - qo1) + e2 * (qn2 - qo2);
-        float c = An / (Af + An) * sdot;
-        // y_own = q_own + A_nb/(A_own + A_nb) e (e.(q_nb - q_own)); z' = z + alpha (y - g)
-        float z0n = zo[0] + relax * (qo0 + c * e0 - g0);
-        float z1n = zo[1] + relax * (qo1 + c * e1 - g1);
-        float z2n = zo[2] + relax * (qo2 + c * e2 - g2);
-        float* zw = zout + 3 * (2 * e + side);
+        float sdot = sg.x * (qn0 - qo0) + sg.y * (qn1 - qo1) + sg.z * (qn2 - qo2);
+        float c = sg.w * sdot;
+        float z0n = zo[3 * k] + relax * (qo0 + c * sg.x - g0);
+        float z1n = zo[3 * k + 1] + relax * (qo1 + c * sg.y - g1);
+        float z2n = zo[3 * k + 2] + relax * (qo2 + c * sg.z - g2);
+        float* zw = zout + 9 * f + 3 * k;
         zw[0] = z0n;
         zw[1] = z1n;
         zw[2] = z2n;
@@ -710,16 +708,14 @@ __device__ inline void admm_face_one(int f, const uint32_t* __restrict__ fslot, 
     gout[3 * f + 2] = (2.f * h[3 * f + 2] + mu * acc2) * den;
 }
 
-__global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const uint32_t* __restrict__ fslot,
-                                                       const int32_t* __restrict__ ef,
-                                                       const float* __restrict__ ebar,
-                                                       const double* __restrict__ farea,
+__global__ void __launch_bounds__(kBlockA) k_admm_face(int nf, const int32_t* __restrict__ twin,
+                                                       const float4* __restrict__ sgeo,
                                                        const float* __restrict__ h, const float* __restrict__ gin,
                                                        const float* __restrict__ zin, float* __restrict__ gout,
                                                        float* __restrict__ zout, float mu, float relax) {
     int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
-    admm_face_one(f, fslot, ef, ebar, farea, h, gin, zin, gout, zout, mu, relax);
+    admm_face_one(f, twin, sgeo, h, gin, zin, gout, zout, mu, relax);
 }
 
 // Face-form projection of the constraint groups, first half: chunk c of
@@ -755,8 +751,8 @@ __device__ inline void path_face_chunk_block(int c, const int32_t* __restrict__ 
 // The face update and the chunk sums in one launch: blocks [0, nch) sum one
 // chunk each, blocks [nch, nch + nfb) update faces.
 __global__ void __launch_bounds__(kBlockA) k_admm_face_paths(
-    int nf, int nfb, int nch, const uint32_t* __restrict__ fslot, const int32_t* __restrict__ ef,
-    const float* __restrict__ ebar, const double* __restrict__ farea, const float* __restrict__ h,
+    int nf, int nfb, int nch, const int32_t* __restrict__ twin, const float4* __restrict__ sgeo,
+    const double* __restrict__ farea, const float* __restrict__ h,
     const float* __restrict__ gin, const float* __restrict__ zin, float* __restrict__ gout, float* __restrict__ zout,
     const int32_t* __restrict__ chunk_path, const int32_t* __restrict__ cptr, const int32_t* __restrict__ ptr,
     const int32_t* __restrict__ face, const float* __restrict__ vec, const float* __restrict__ zp,
@@ -767,7 +763,7 @@ __global__ void __launch_bounds__(kBlockA) k_admm_face_paths(
         return;
     }
     const int f = xcd_block((int)blockIdx.x - nch, nfb) * blockDim.x + threadIdx.x;
-    if (f < nf) admm_face_one(f, fslot, ef, ebar, farea, h, gin, zin, gout, zout, mu, relax);
+    if (f < nf) admm_face_one(f, twin, sgeo, h, gin, zin, gout, zout, mu, relax);
 }
 
 // Per copy k of face i: r_p = sqrt(A_i) (y' - g') with y' = g + (z' - z)/alpha
@@ -783,7 +779,7 @@ __global__ void k_resid_face(int nf, const uint32_t* fslot, const double* farea,
         for (int k = 0; k < 3; ++k) {
             uint32_t sl = fslot[3 * f + k];
             if (slot_bnd(sl)) continue;
-            int c = 2 * slot_edge(sl) + slot_side(sl);
+            const int c = 3 * f + k;   // the copy's slot
             for (int d = 0; d < 3; ++d) {
                 double yn = (double)ga[3 * f + d] + ((double)zb[3 * c + d] - (double)za[3 * c + d]) / relax;
                 double p = al * (yn - (double)gb[3 * f + d]);
@@ -830,14 +826,13 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const int nf = (int)m.nf, ne = (int)m.ne;
     w.g0.alloc((size_t)3 * nf);
     w.g1.alloc((size_t)3 * nf);
-    w.z0.alloc((size_t)6 * ne);
-    w.z1.alloc((size_t)6 * ne);
+    w.z0.alloc((size_t)9 * nf);
+    w.z1.alloc((size_t)9 * nf);
     w.gf.alloc((size_t)3 * nf);
     const float mu = (float)o.mu;
     const int gf = grid_for(nf, kBlockA);
-    const int gi = grid_for(std::max(nf, ne), kBlockA);
     if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
-    hipLaunchKernelGGL(k_face_init, dim3(gi), dim3(kBlockA), 0, s, nf, ne, m.ef.p, w.h.p, w.g0.p, w.z0.p);
+    hipLaunchKernelGGL(k_face_init, dim3(gf), dim3(kBlockA), 0, s, nf, w.h.p, w.g0.p, w.z0.p);
     auto& P = w.paths;
     use_paths = use_paths && P.np > 0;
     if (use_paths) {
@@ -859,9 +854,11 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     // from convergence (DistStop)
     int interval = check, next_check = check;
     float *ga = w.g0.p, *gb = w.g1.p, *za = w.z0.p, *zb = w.z1.p;
-    // algorithmic bytes of one iteration: per face g, h, fslot, area read and
-    // g written; per edge ef, unit vector and both z copies read, z written
-    r.bytes_per_iter = (uint64_t)56 * nf + (uint64_t)68 * ne;
+    // algorithmic bytes of one iteration: per face g, h, its three twin
+    // slots, copies and slot geometry (e, w) read, g and the copies written
+    // (the neighbours' g and copies are the same arrays, read by their own
+    // faces)
+    r.bytes_per_iter = (uint64_t)168 * nf;
     // group kernels: the chunk sums read per slot its face, vector, area, g
     // and copy (48 B) and write 16 B per chunk; the fix reads per slot its
     // index, group, vector and copy and writes the copy (44 B), per face its
@@ -873,11 +870,11 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     DistStop stop;
     auto iterate = [&](float* gi, float* zi, float* go, float* zo) {
         if (!use_paths) {
-            hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.fslot.p, m.ef.p, m.ebar.p,
-                               m.farea.p, w.h.p, gi, zi, go, zo, mu, (float)o.relax);
+            hipLaunchKernelGGL(k_admm_face, dim3(gf), dim3(kBlockA), 0, s, nf, m.twin.p, m.sgeo.p, w.h.p, gi, zi,
+                               go, zo, mu, (float)o.relax);
         } else {
-            hipLaunchKernelGGL(k_admm_face_paths, dim3(gf + P.nch), dim3(kBlockA), 0, s, nf, gf, P.nch, m.fslot.p,
-                               m.ef.p, m.ebar.p, m.farea.p, w.h.p, gi, zi, go, zo, P.chunk_path.p, P.cptr.p, P.ptr.p,
+            hipLaunchKernelGGL(k_admm_face_paths, dim3(gf + P.nch), dim3(kBlockA), 0, s, nf, gf, P.nch, m.twin.p,
+                               m.sgeo.p, m.farea.p, w.h.p, gi, zi, go, zo, P.chunk_path.p, P.cptr.p, P.ptr.p,
                                P.face.p, P.vec.p, P.z.p, P.pc.p, mu, (float)o.relax);
             hipLaunchKernelGGL(k_path_face_fix, dim3(grid_for(P.ng_face, kBlockA)), dim3(kBlockA), 0, s, P.ng_face,
                                P.fg_ptr.p, P.fg_id.p, P.fg_slot.p, P.spath.p, P.cptr.p, P.pc.p, P.vec.p, m.farea.p,

@@ -164,6 +164,22 @@ __global__ void k_vertex_fill(int nv, const int32_t* row_ptr, const int32_t* csr
     Av[j] = ar / 6.0;
 }
 
+// Per face slot (face form): the unit vector of the slot's edge and the
+// weight A_nb / (A_own + A_nb) of the neighbour across it (0 on the boundary).
+__global__ void k_slot_geom(int nf, const uint32_t* fslot, const int32_t* twin, const float* ebar,
+                            const double* farea, float4* sgeo) {
+    int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= 3 * nf) return;
+    const int e = slot_edge(fslot[h]);
+    const int t = twin[h];
+    float w = 0.f;
+    if (t >= 0) {
+        const float Af = (float)farea[h / 3], An = (float)farea[t / 3];
+        w = An / (Af + An);
+    }
+    sgeo[h] = make_float4(ebar[3 * e], ebar[3 * e + 1], ebar[3 * e + 2], w);
+}
+
 void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host) {
     const int nf = (int)m.nf, ne = (int)m.ne, nv = (int)m.nv;
     DBuf<double> fcot, theta_e, elen;
@@ -196,7 +212,12 @@ void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host)
                        m.csr_edge.p, m.ef.p, theta_e.p, m.farea.p, m.theta.p, m.sum_theta.p, m.Av.p);
     HG_CHECK_HIP(hipGetLastError());
     build_theta_ell(m, s);
+    m.sgeo.alloc((size_t)3 * nf);
+    hipLaunchKernelGGL(k_slot_geom, dim3(grid_for(3 * (int64_t)nf, kBlock)), dim3(kBlock), 0, s, nf, m.fslot.p,
+                       m.twin.p, m.ebar.p, m.farea.p, m.sgeo.p);
+    HG_CHECK_HIP(hipGetLastError());
     HG_CHECK_HIP(hipStreamSynchronize(s));
+    m.ebar.release();   // only the per-slot copy is read from here on
 }
 
 // -------------------------------------------------------------- permutations
