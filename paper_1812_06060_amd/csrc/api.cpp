@@ -29,10 +29,14 @@ size_t Work::Paths::bytes() const {
 }
 
 uint64_t Mesh::mesh_bytes() const {
-    return px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
+    uint64_t face_form = 0;
+    {
+        std::lock_guard<std::mutex> lock(sgeo_mu);
+        face_form = sgeo.bytes();
+    }
+    return face_form + px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
-           tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() + ebar.bytes() +
-           sgeo.bytes() +
+           tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() +
            tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
            theta_ell.bytes() + tile_order.bytes() + twin.bytes() + h01.bytes() + comp_v.bytes() + tile_comp.bytes();
 }

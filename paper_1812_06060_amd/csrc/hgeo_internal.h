@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -233,8 +234,10 @@ struct Mesh {
     DBuf<uint8_t> fsign;
     DBuf<double> farea;                     // per face (FP64)
     DBuf<int32_t> ev, ef;
-    DBuf<float> ebar;                       // [ne*3] unit edge vectors (released after geometry_init)
-    DBuf<float4> sgeo;                      // [nf*3] per face slot: unit edge vector, A_nb / (A_own + A_nb)
+    // face form only, built by the first face-form iteration (ensure_sgeo):
+    // per face slot the unit edge vector and A_nb / (A_own + A_nb)
+    DBuf<float4> sgeo;
+    mutable std::mutex sgeo_mu;
     DBuf<int32_t> twin, h01;
 
     // patch tiles
@@ -275,6 +278,7 @@ struct Mesh {
     Work w;
 
     uint64_t mesh_bytes() const;
+    void ensure_sgeo(hipStream_t s);
     ~Mesh();
 };
 

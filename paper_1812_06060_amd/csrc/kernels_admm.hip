@@ -824,6 +824,7 @@ static void face_residuals(Mesh& m, Work& w, int gf, const float* gprev, const f
 
 AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStream_t s, int depth, bool use_paths) {
     const int nf = (int)m.nf, ne = (int)m.ne;
+    m.ensure_sgeo(s);
     w.g0.alloc((size_t)3 * nf);
     w.g1.alloc((size_t)3 * nf);
     w.z0.alloc((size_t)9 * nf);

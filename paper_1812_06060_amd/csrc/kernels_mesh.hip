@@ -112,7 +112,7 @@ __global__ void k_face_geom(int nf, const int32_t* tri, const double* px, const 
 // the edge length (partial sums for the mean).
 __global__ void k_edge_theta(int ne, const int32_t* ev, const int32_t* ef, const uint32_t* fslot,
                              const double* fcot, const double* px, const double* py, const double* pz,
-                             const double* elen, double* theta_e, float* ebar, double* partial) {
+                             const double* elen, double* theta_e, double* partial) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     double len = 0.0;
     if (e < ne) {
@@ -124,18 +124,14 @@ __global__ void k_edge_theta(int ne, const int32_t* ev, const int32_t* ef, const
                 if (slot_edge(fslot[3 * f + k]) == e) th += 0.5 * fcot[3 * f + (k + 2) % 3];
         }
         theta_e[e] = th;
-        if (elen) {   // intrinsic: no embedding, no unit edge vectors (face form only)
+        if (elen) {   // intrinsic: the lengths of the flipped triangulation
             len = elen[e];
-            ebar[3 * e] = ebar[3 * e + 1] = ebar[3 * e + 2] = 0.f;
         } else {
             double a[3], b[3], d[3];
             load3(px, py, pz, ev[2 * e], a);
             load3(px, py, pz, ev[2 * e + 1], b);
             sub3(b, a, d);
             len = sqrt(dot3(d, d));
-            ebar[3 * e] = (float)(d[0] / len);
-            ebar[3 * e + 1] = (float)(d[1] / len);
-            ebar[3 * e + 2] = (float)(d[2] / len);
         }
     }
     double s = block_reduce(len, false);
@@ -164,20 +160,39 @@ __global__ void k_vertex_fill(int nv, const int32_t* row_ptr, const int32_t* csr
     Av[j] = ar / 6.0;
 }
 
-// Per face slot (face form): the unit vector of the slot's edge and the
-// weight A_nb / (A_own + A_nb) of the neighbour across it (0 on the boundary).
-__global__ void k_slot_geom(int nf, const uint32_t* fslot, const int32_t* twin, const float* ebar,
-                            const double* farea, float4* sgeo) {
+// Per face slot (face form): the unit vector of the slot's edge (along its
+// orientation halfedge) and the weight A_nb / (A_own + A_nb) of the
+// neighbour across it (0 on the boundary).
+__global__ void k_slot_geom(int nf, const uint32_t* fslot, const int32_t* twin, const int32_t* ev, const double* px,
+                            const double* py, const double* pz, const double* farea, float4* sgeo) {
     int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= 3 * nf) return;
     const int e = slot_edge(fslot[h]);
+    double a[3], b[3], d[3];
+    load3(px, py, pz, ev[2 * e], a);
+    load3(px, py, pz, ev[2 * e + 1], b);
+    sub3(b, a, d);
+    const double len = sqrt(dot3(d, d));
     const int t = twin[h];
     float w = 0.f;
     if (t >= 0) {
         const float Af = (float)farea[h / 3], An = (float)farea[t / 3];
         w = An / (Af + An);
     }
-    sgeo[h] = make_float4(ebar[3 * e], ebar[3 * e + 1], ebar[3 * e + 2], w);
+    sgeo[h] = make_float4((float)(d[0] / len), (float)(d[1] / len), (float)(d[2] / len), w);
+}
+
+void Mesh::ensure_sgeo(hipStream_t s) {
+    std::lock_guard<std::mutex> lock(sgeo_mu);
+    if (sgeo.p) return;
+    DBuf<float4> tmp;
+    tmp.alloc((size_t)3 * nf);
+    hipLaunchKernelGGL(k_slot_geom, dim3(grid_for(3 * nf, kBlock)), dim3(kBlock), 0, s, (int)nf, fslot.p, twin.p,
+                       ev.p, px.p, py.p, pz.p, farea.p, tmp.p);
+    HG_CHECK_HIP(hipGetLastError());
+    HG_CHECK_HIP(hipStreamSynchronize(s));   // other queries may read it as soon as the lock is released
+    std::swap(sgeo.p, tmp.p);
+    std::swap(sgeo.n, tmp.n);
 }
 
 void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host) {
@@ -193,7 +208,6 @@ void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host)
     m.theta.alloc((size_t)2 * ne);
     m.sum_theta.alloc(nv);
     m.Av.alloc(nv);
-    m.ebar.alloc((size_t)3 * ne);
     int gf = grid_for(nf, kBlock), ge = grid_for(ne, kBlock);
     m.w.partial.alloc((size_t)std::max(gf, ge) + 8);
     hipLaunchKernelGGL(k_face_geom, dim3(gf), dim3(kBlock), 0, s, nf, m.tri.p, m.px.p, m.py.p, m.pz.p,
@@ -204,7 +218,7 @@ void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host)
     HG_CHECK_HIP(hipMemcpy(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost));
     if (hbad) throw Error{HG_E_BAD_MESH, "zero-area face"};
     hipLaunchKernelGGL(k_edge_theta, dim3(ge), dim3(kBlock), 0, s, ne, m.ev.p, m.ef.p, m.fslot.p, fcot.p, m.px.p,
-                       m.py.p, m.pz.p, elen_host ? elen.p : nullptr, theta_e.p, m.ebar.p, m.w.partial.p);
+                       m.py.p, m.pz.p, elen_host ? elen.p : nullptr, theta_e.p, m.w.partial.p);
     HG_CHECK_HIP(hipGetLastError());
     const double hb = reduce_partials(m, m.w, ge, false, s) / (double)ne;
     if (!m.intrinsic) m.hbar = hb;   // intrinsic: the input mesh's mean edge length, set by the caller
@@ -212,12 +226,7 @@ void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host)
                        m.csr_edge.p, m.ef.p, theta_e.p, m.farea.p, m.theta.p, m.sum_theta.p, m.Av.p);
     HG_CHECK_HIP(hipGetLastError());
     build_theta_ell(m, s);
-    m.sgeo.alloc((size_t)3 * nf);
-    hipLaunchKernelGGL(k_slot_geom, dim3(grid_for(3 * (int64_t)nf, kBlock)), dim3(kBlock), 0, s, nf, m.fslot.p,
-                       m.twin.p, m.ebar.p, m.farea.p, m.sgeo.p);
-    HG_CHECK_HIP(hipGetLastError());
     HG_CHECK_HIP(hipStreamSynchronize(s));
-    m.ebar.release();   // only the per-slot copy is read from here on
 }
 
 // -------------------------------------------------------------- permutations
