@@ -80,7 +80,7 @@ def run(n_meshes: int = 256, form: str = "edge", reps: int = 3, log=print):
             "max_diff_vs_alone_over_diam": worst}
 
 
-def run_fields(n_fields: int = 64, slots: int = 8, log=print):
+def run_fields(n_fields: int = 64, slots: int = 8, log=print, batched: bool = False):
     """64 single-source fields on the displaced level-9 icosphere (its 64
     seeded sources, one query each) on one resident mesh: served
     concurrently by an hg_server with `slots` slots (private workspaces,
@@ -119,9 +119,34 @@ def run_fields(n_fields: int = 64, slots: int = 8, log=print):
     log(f"[fields] {len(src)} single-source fields on L9: one at a time {t_seq:.2f} s, "
         f"{slots}-slot server {t_srv:.2f} s, identical {same}")
     mesh.close()
-    return {"fields": len(src), "vertices": int(v.shape[0]), "slots": slots,
-            "one_at_a_time": {"s": t_seq, "fields_per_s": len(src) / t_seq},
-            "served": {"s": t_srv, "fields_per_s": len(src) / t_srv}, "results_identical": same}
+    out = {"fields": len(src), "vertices": int(v.shape[0]), "slots": slots,
+           "one_at_a_time": {"s": t_seq, "fields_per_s": len(src) / t_seq},
+           "served": {"s": t_srv, "fields_per_s": len(src) / t_srv}, "results_identical": same}
+    if batched:
+        # the same fields as one batched solve: one instance of the mesh per
+        # field, placed side by side as the components of one resident mesh,
+        # so that every step of the solve is one launch for all of them (the
+        # mesh data is duplicated per field)
+        from .batch import MeshBatch
+        t0 = time.perf_counter()
+        b = MeshBatch([(v, f)] * len(src))
+        log(f"[fields] batch of {len(src)} mesh instances built in {time.perf_counter() - t0:.1f} s "
+            f"({b.mesh.stats['mesh_bytes'] / 1e9:.1f} GB)")
+        srcs = [[int(x)] for x in src]
+        ds, info = b.solve(srcs, opts=hg.default_opts())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ds, info = b.solve(srcs, opts=hg.default_opts())
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        worst = max(float(np.abs(d.cpu().numpy() - r).max() / r.max()) for d, r in zip(ds, ref))
+        log(f"[fields] one batched solve: {t_b:.2f} s (passes {info.passes}, ADMM {info.admm_iters}); "
+            f"largest difference from the fields alone {worst:.2e} of the diameter")
+        out["batched"] = {"s": t_b, "fields_per_s": len(src) / t_b, "passes": info.passes,
+                          "admm_iters": info.admm_iters, "mesh_bytes": int(b.mesh.stats["mesh_bytes"]),
+                          "max_diff_vs_alone_over_diam": worst}
+        b.close()
+    return out
 
 
 def main():
@@ -131,10 +156,12 @@ def main():
     ap.add_argument("--fields", action="store_true",
                     help="measure 64 single-source fields on the level-9 mesh instead")
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--batched", action="store_true",
+                    help="with --fields: also solve the 64 fields as one batch of 64 mesh instances")
     a = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)
     if a.fields:
-        print(json.dumps(run_fields(64, a.slots, log=log)), flush=True)
+        print(json.dumps(run_fields(64, a.slots, log=log, batched=a.batched)), flush=True)
     else:
         print(json.dumps(run(a.meshes, a.form, log=log)), flush=True)
 
