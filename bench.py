@@ -101,6 +101,8 @@ def main():
                     help="skip the batch measurement (256 small meshes in one solve)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement (Poisson stream over a pool of resident meshes)")
+    ap.add_argument("--admm-block", type=int, default=0,
+                    help="edge-form ADMM iterations per launch (hg_opts.admm_block; 0 = auto)")
     ap.add_argument("--serve-levels", default="4-8")
     ap.add_argument("--serve-queries", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=1.5,
@@ -137,7 +139,7 @@ def main():
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
     print(f"[bench] mesh_create {t_create:.2f}s hbar={mesh.hbar:.4e}", file=sys.stderr, flush=True)
-    opts = hg.default_opts(formulation=args.form)
+    opts = hg.default_opts(formulation=args.form, admm_block=args.admm_block)
     out = torch.empty(mesh.nv, dtype=torch.float32, device="cuda")
     tune = None
     if not args.no_autotune:
@@ -170,17 +172,24 @@ def main():
 
     # dominant kernel: the one with the larger share of device time
     diff_ms = float(np.mean([i.ms_pass_kernel * i.passes for i in infos]))
-    admm_ms = float(np.mean([i.ms_admm_kernel * i.admm_iters for i in infos]))
+    admm_ms = float(np.mean([i.ms_admm_kernel * i.admm_launches for i in infos]))
+    block = infos[-1].admm_block
     if diff_ms >= admm_ms:
         name = "diffusion pass"
         kms = float(np.mean([i.ms_pass_kernel for i in infos]))
         kbytes = infos[-1].bytes_pass_kernel
     else:
-        name = f"{args.form} ADMM iteration"
+        name = (f"{args.form} ADMM launch ({block} iterations over LDS tiles)" if block > 1
+                else f"{args.form} ADMM iteration")
         kms = float(np.mean([i.ms_admm_kernel for i in infos]))
         kbytes = infos[-1].bytes_admm_kernel
     achieved = kbytes / (kms * 1e-3) / 1e9
-    kname = "k_patch_pass" if name == "diffusion pass" else ("k_admm_edge" if args.form == "edge" else "k_admm_face")
+    if name == "diffusion pass":
+        kname = "k_patch_pass"
+    elif args.form == "face":
+        kname = "k_admm_face"
+    else:
+        kname = "k_admm_edge_tiled" if block > 1 else "k_admm_edge"
     traffic = _measured_traffic(kname, "pass" if kname == "k_patch_pass" else "launch")
     last = infos[-1]
     result = {
@@ -199,7 +208,8 @@ def main():
         "config": {"workload": f"displaced icosphere L{args.level} ({mesh.nv} vertices, {mesh.nf} faces), "
                                f"1 source, t=hbar^2, {args.form} form, tol_u={opts.tol_u:g}, "
                                f"tol_admm={opts.tol_admm:g}",
-                   "sweeps": last.sweeps, "admm_iters": last.admm_iters, "bfs_depth": last.bfs_depth,
+                   "sweeps": last.sweeps, "admm_iters": last.admm_iters, "admm_block": last.admm_block,
+                   "admm_launches": last.admm_launches, "bfs_depth": last.bfs_depth,
                    "stage_ms": {"bfs": last.ms_bfs, "diffusion": last.ms_diffusion,
                                 "normalize": last.ms_normalize, "admm": last.ms_admm,
                                 "integrate": last.ms_integrate},

@@ -122,7 +122,17 @@ typedef struct {
                                stop only once it is <= tol_seam as well;
                                default 0 = not required (it is reported in
                                hg_info.seam either way) */
-    int32_t reserved[2];
+    int32_t admm_block;     /* edge form without constraint groups: ADMM
+                               iterations per launch, 1..8.  k > 1 runs k
+                               iterations over face tiles held in LDS with a
+                               halo of k rings of faces, with the result of k
+                               single-iteration launches (the same
+                               arithmetic) for fewer HBM bytes per
+                               iteration; a mesh whose tiles do not fit in
+                               LDS, and every solve with source paths or
+                               generator loops, runs one iteration per
+                               launch.  0 = auto (default, 2) */
+    int32_t reserved[1];
 } hg_opts;
 
 /* Per-solve report. */
@@ -140,9 +150,10 @@ typedef struct {
     uint64_t bytes_alg;     /* algorithmic HBM bytes of the solve's kernels */
     uint64_t workspace_bytes; /* device bytes held for this mesh's queries */
     int32_t converged_u, converged_admm;
-    /* average device time of one diffusion-pass kernel and of one ADMM
-       iteration kernel, from HIP events around back-to-back launches on the
-       solve's stream, and the algorithmic HBM bytes one such launch moves */
+    /* average device time of one diffusion-pass kernel and of one launch
+       of the main ADMM kernel (admm_block iterations), from HIP events
+       around back-to-back launches on the solve's stream, and the
+       algorithmic HBM bytes one such launch moves */
     float ms_pass_kernel, ms_admm_kernel;
     uint64_t bytes_pass_kernel, bytes_admm_kernel;
     int32_t n_paths;        /* source paths constrained (Eqs. 24-25) */
@@ -152,7 +163,11 @@ typedef struct {
                                over those loops */
     float seam;             /* hg_geodesic_solve: the last check's largest
                                seam / hbar (see hg_opts.tol_seam) */
-    int32_t reserved[3];
+    int32_t admm_launches;  /* launches of the main ADMM kernel, each of
+                               admm_block iterations (ms_admm_kernel and
+                               bytes_admm_kernel are per such launch) */
+    int32_t admm_block;     /* iterations per launch actually used */
+    int32_t reserved[1];
 } hg_info;
 
 /* Mesh statistics. */

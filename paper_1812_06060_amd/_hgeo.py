@@ -39,7 +39,7 @@ class Opts(C.Structure):
         ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
         ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("source_paths", C.c_int32),
         ("t_per_component", C.c_int32), ("use_graphs", C.c_int32), ("cycle_constraints", C.c_int32),
-        ("tol_seam", C.c_double), ("reserved", C.c_int32 * 2),
+        ("tol_seam", C.c_double), ("admm_block", C.c_int32), ("reserved", C.c_int32 * 1),
     ]
 
 
@@ -55,7 +55,8 @@ class Info(C.Structure):
         ("ms_pass_kernel", C.c_float), ("ms_admm_kernel", C.c_float),
         ("bytes_pass_kernel", C.c_uint64), ("bytes_admm_kernel", C.c_uint64),
         ("n_paths", C.c_int32), ("path_edges", C.c_int32), ("n_cycles", C.c_int32), ("cycle_slots", C.c_int32),
-        ("seam", C.c_float), ("reserved", C.c_int32 * 3),
+        ("seam", C.c_float), ("admm_launches", C.c_int32), ("admm_block", C.c_int32),
+        ("reserved", C.c_int32 * 1),
     ]
 
     def as_dict(self):

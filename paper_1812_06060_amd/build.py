@@ -17,6 +17,7 @@ SOURCES = [
     "mesh_build.cpp",
     "cycles.cpp",
     "intrinsic.cpp",
+    "admm_tiles.cpp",
     "api.cpp",
     "kernels_mesh.hip",
     "kernels_bfs.hip",

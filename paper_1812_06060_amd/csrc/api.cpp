@@ -34,7 +34,12 @@ uint64_t Mesh::mesh_bytes() const {
         std::lock_guard<std::mutex> lock(sgeo_mu);
         face_form = sgeo.bytes();
     }
-    return face_form + px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
+    uint64_t blocked = 0;
+    {
+        std::lock_guard<std::mutex> lock(et_mu);
+        for (const auto& t : etiles) blocked += t->f0.bytes() + t->rptr.bytes() + t->halo.bytes() + t->rec.bytes();
+    }
+    return face_form + blocked + floc.bytes() + px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() +
            tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
@@ -90,6 +95,9 @@ static hg_opts resolve_opts(const hg_opts* o) {
     if (r.t_per_component != 0 && r.t_per_component != 1)
         throw Error{HG_E_INVALID_ARG, "t_per_component must be 0 or 1"};
     if (!(r.tol_seam >= 0.0) || !std::isfinite(r.tol_seam)) throw Error{HG_E_INVALID_ARG, "tol_seam must be >= 0"};
+    if (r.admm_block < 0 || r.admm_block > kMaxAdmmBlock)
+        throw Error{HG_E_INVALID_ARG, "admm_block must lie in 0..8 (0 = auto)"};
+    if (r.admm_block == 0) r.admm_block = kAutoAdmmBlock;
     if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
         throw Error{HG_E_INVALID_ARG, "iteration caps must be positive"};
     return r;
@@ -205,7 +213,9 @@ QueryOutcome hg::solve_query(Mesh& mesh_ref, Work& w, const int32_t* src, int32_
         info->ms_admm_kernel = ar.timed_launches ? (float)(ar.kernel_ms / ar.timed_launches) : 0.f;
         info->bytes_pass_kernel = dr.bytes_per_pass;
         info->bytes_admm_kernel = ar.bytes_per_iter;
-        info->bytes_alg = dr.bytes_per_pass * (uint64_t)dr.passes + ar.bytes_per_iter * (uint64_t)ar.iters;
+        info->bytes_alg = dr.bytes_per_pass * (uint64_t)dr.passes + ar.bytes_per_iter * (uint64_t)ar.launches;
+        info->admm_launches = ar.launches;
+        info->admm_block = ar.block;
         info->n_paths = paths ? w.paths.np_src : 0;
         info->path_edges = paths ? w.paths.ns_src : 0;
         info->n_cycles = paths ? w.paths.n_cyc : 0;
@@ -524,6 +534,8 @@ static hg_status admm_stage(hg_mesh_t mesh, const float* h_dev, const int32_t* s
             info->path_edges = paths ? m->w.paths.ns_src : 0;
             info->n_cycles = paths ? m->w.paths.n_cyc : 0;
             info->cycle_slots = paths ? m->w.paths.ns_cyc : 0;
+            info->admm_launches = r.launches;
+            info->admm_block = r.block;
         }
         return r.converged ? HG_OK : fail(HG_E_NOT_CONVERGED, "ADMM iteration cap reached");
     });

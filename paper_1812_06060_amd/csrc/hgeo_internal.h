@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -148,6 +149,25 @@ struct IntrinsicTri {
 };
 void build_intrinsic(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, IntrinsicTri& out);
 
+// Face tiles with halos for the blocked edge-ADMM launch (admm_tiles.cpp):
+// tile p owns faces [f0[p], f0[p+1]); its region is those faces followed by
+// the halo faces halo[rptr[p] - f0[p] ..] up to `rings` edge-adjacency steps
+// away; rec[rptr[p] + r] is region face r's record (twin copies, signs).
+constexpr int kMaxAdmmBlock = 8;    // iterations per blocked launch at most
+constexpr int kAutoAdmmBlock = 2;   // hg_opts.admm_block = 0
+constexpr uint32_t kTwinNone = 0xFFFF;   // boundary slot: no twin
+constexpr uint32_t kTwinOut = 0xFFFE;    // twin outside the region
+struct EdgeTiles {
+    int rings = 0, max_region = 0;
+    std::vector<int32_t> f0, rptr, halo;
+    std::vector<uint64_t> rec;
+};
+// false if a region would exceed max_region faces or the faces are not in
+// tile order
+bool build_edge_tiles(int64_t nf, const std::vector<int32_t>& tri, const std::vector<int32_t>& twin,
+                      const std::vector<uint8_t>& fsign, const std::vector<int32_t>& tile_ptr, int rings,
+                      int max_region, EdgeTiles& out);
+
 // Per-query device workspace.  A query runs on one Work and one stream; the
 // mesh data it reads is never written after mesh_create, so queries on the
 // same mesh with different Works may run concurrently on different streams.
@@ -177,10 +197,12 @@ struct Work {
     DBuf<double> tcomp, tile_t;         // diffusion time per component and per tile
     DBuf<int32_t> e0, e1;               // diffusion exponents
     DBuf<double> logu;
-    DBuf<float> h;                      // [nf*3] internal order
+    DBuf<float> h;                      // [nf*3] internal order; the edge form reads it only
+                                        // for the targets and then keeps the blocked ADMM's
+                                        // state one iteration back in it
     DBuf<float> sumz;                   // [ne] edge-form target sums
     DBuf<float> sumd;                   // [3nf] target sum of each slot's edge
-    DBuf<float> z0, z1;                 // edge form: zeta [2*ne]; face form: z [2*ne*3]
+    DBuf<float> z0, z1;                 // edge form: zeta [3*nf]; face form: z [9*nf]
     DBuf<float> g0, g1;                 // face form gradients [nf*3]
     DBuf<float> xe;                     // [ne] final edge differences (internal)
     DBuf<float> gf;                     // [nf*3] final face gradients (internal)
@@ -239,6 +261,18 @@ struct Mesh {
     DBuf<float4> sgeo;
     mutable std::mutex sgeo_mu;
     DBuf<int32_t> twin, h01;
+    // edge form, blocked launches: face tiles with halos, one set per halo
+    // depth used, built by the first blocked iteration with that depth
+    // (ensure_edge_tiles) and kept until the mesh is destroyed, so that
+    // concurrent queries never see a set replaced
+    struct EdgeTileSet {
+        int rings = 0, max_region = 0, n = 0;
+        bool ok = false;   // false: a region does not fit in LDS
+        DBuf<int32_t> f0, rptr, halo;
+        DBuf<uint64_t> rec;
+    };
+    std::vector<std::unique_ptr<EdgeTileSet>> etiles;
+    mutable std::mutex et_mu;
 
     // patch tiles
     int patch_size = 0, n_patches = 0, max_halo = 0, max_ell_width = 0;
@@ -279,6 +313,9 @@ struct Mesh {
 
     uint64_t mesh_bytes() const;
     void ensure_sgeo(hipStream_t s);
+    // the blocked edge-ADMM tiles for `rings` (nullptr if the mesh's regions
+    // do not fit in LDS)
+    const EdgeTileSet* ensure_edge_tiles(int rings, hipStream_t s);
     ~Mesh();
 };
 
@@ -311,7 +348,9 @@ struct AdmmResult {
     bool converged = false;
     double kernel_ms = 0.0;
     int timed_launches = 0;
-    uint64_t bytes_per_iter = 0;
+    uint64_t bytes_per_iter = 0;  // algorithmic bytes of one launch of the main kernel
+    int launches = 0;             // launches of the main kernel (blocked: several iterations each)
+    int block = 1;                // iterations per launch of the main kernel
 };
 
 // Events around runs of back-to-back launches of one kernel (between two

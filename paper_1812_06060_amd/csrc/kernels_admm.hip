@@ -212,20 +212,12 @@ __device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1m
     return bnd ? (S + z0) * inv1mu : 0.5f * (S + z0 + z1) * inv1mu;
 }
 
-__device__ inline void admm_edge_face(int f, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
-                                      const float* __restrict__ sumd, const float* __restrict__ zin,
-                                      float* __restrict__ zout, float mu, float inv1mu, float mu_relax) {
-    float x[3], zo[3];
-    int tw[3];
-    for (int k = 0; k < 3; ++k) {
-        tw[k] = twin[3 * f + k];
-        zo[k] = zin[3 * f + k];
-    }
-    for (int k = 0; k < 3; ++k) {
-        const float tz = tw[k] >= 0 ? zin[tw[k]] : 0.f;
-        x[k] = edge_x(sumd[3 * f + k], zo[k], tz, tw[k] < 0, inv1mu);
-    }
-    uint8_t sg = fsign[f];
+// One folded iteration of a face from its three copies zo, the twins'
+// copies tz (0 on boundary slots, flagged in bnd) and the target sums S.
+__device__ inline void edge_face_update(const float zo[3], const float tz[3], const float S[3], const int bnd[3],
+                                        uint32_t sg, float mu, float inv1mu, float mu_relax, float zn[3]) {
+    float x[3];
+    for (int k = 0; k < 3; ++k) x[k] = edge_x(S[k], zo[k], tz[k], bnd[k], inv1mu);
     float q[3], v[3];
     float qv = 0.f;
     for (int k = 0; k < 3; ++k) {
@@ -236,8 +228,26 @@ __device__ inline void admm_edge_face(int f, const int32_t* __restrict__ twin, c
     qv *= (1.f / 3.f);
     for (int k = 0; k < 3; ++k) {
         float w = v[k] - qv * q[k];
-        zout[3 * f + k] = zo[k] + mu_relax * (w - x[k]);
+        zn[k] = zo[k] + mu_relax * (w - x[k]);
     }
+}
+
+__device__ inline void admm_edge_face(int f, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
+                                      const float* __restrict__ sumd, const float* __restrict__ zin,
+                                      float* __restrict__ zout, float mu, float inv1mu, float mu_relax) {
+    float zo[3], tz[3], S[3], zn[3];
+    int tw[3], bnd[3];
+    for (int k = 0; k < 3; ++k) {
+        tw[k] = twin[3 * f + k];
+        zo[k] = zin[3 * f + k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        tz[k] = tw[k] >= 0 ? zin[tw[k]] : 0.f;
+        bnd[k] = tw[k] < 0;
+        S[k] = sumd[3 * f + k];
+    }
+    edge_face_update(zo, tz, S, bnd, fsign[f], mu, inv1mu, mu_relax, zn);
+    for (int k = 0; k < 3; ++k) zout[3 * f + k] = zn[k];
 }
 
 __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const int32_t* __restrict__ twin,
@@ -248,6 +258,78 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const int32_t* __
     int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     admm_edge_face(f, twin, fsign, sumd, zin, zout, mu, inv1mu, mu_relax);
+}
+
+// `iters` iterations per launch over LDS-resident regions (face tiles with
+// halos of `iters` rings, see admm_tiles.cpp): one workgroup per tile loads
+// its region's copies, target sums and records, runs the iterations with two
+// LDS buffers, and writes back its own faces (and, with zprev, their state
+// one iteration before the last).  Every face update is the one of
+// k_admm_edge, so the result is that of `iters` plain launches.  A halo face
+// whose twin lies outside the region uses its own copy in its place; such
+// faces are at the region's edge and, like every face d rings out, are
+// exact only for iters - d iterations, which the tile's faces never read
+// beyond.
+constexpr int kBlockT = 1024;
+template <int PER>
+__global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
+    const int32_t* __restrict__ f0, const int32_t* __restrict__ rptr, const int32_t* __restrict__ halo,
+    const uint64_t* __restrict__ rec, const float* __restrict__ sumd, const float* __restrict__ zin,
+    float* __restrict__ zout, float* __restrict__ zprev, int iters, int stride, float mu, float inv1mu,
+    float mu_relax) {
+    extern __shared__ float zl[];
+    const int p = xcd_block(blockIdx.x, gridDim.x);
+    const int a = f0[p], nint = f0[p + 1] - a;
+    const int rb = rptr[p], nreg = rptr[p + 1] - rb;
+    if (nint == 0) return;   // the same for the whole workgroup
+    const int hb = rb - a;
+    const int tid = threadIdx.x;
+    float* cur = zl;
+    float* nxt = zl + stride;
+    uint64_t R[PER];
+    float S[PER][3];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int r = tid + j * kBlockT;
+        R[j] = 0;
+        S[j][0] = S[j][1] = S[j][2] = 0.f;
+        if (r < nreg) {
+            const int g = r < nint ? a + r : halo[hb + r - nint];
+            R[j] = rec[rb + r];
+            for (int k = 0; k < 3; ++k) {
+                S[j][k] = sumd[3 * g + k];
+                cur[3 * r + k] = zin[3 * g + k];
+            }
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int r = tid + j * kBlockT;
+            if (r >= nreg) continue;
+            float zo[3], tz[3], zn[3];
+            int bnd[3];
+            for (int k = 0; k < 3; ++k) zo[k] = cur[3 * r + k];
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t c = (uint32_t)(R[j] >> (16 * k)) & 0xFFFFu;
+                bnd[k] = c == kTwinNone;
+                tz[k] = c == kTwinNone ? 0.f : (c == kTwinOut ? zo[k] : cur[c]);
+            }
+            edge_face_update(zo, tz, S[j], bnd, (uint32_t)(R[j] >> 48), mu, inv1mu, mu_relax, zn);
+            for (int k = 0; k < 3; ++k) nxt[3 * r + k] = zn[k];
+        }
+        __syncthreads();
+        float* t = cur;
+        cur = nxt;
+        nxt = t;
+        if (zprev && it == iters - 2) {
+            for (int r = tid; r < nint; r += kBlockT)
+                for (int k = 0; k < 3; ++k) zprev[3 * (a + r) + k] = cur[3 * r + k];
+        }
+    }
+    for (int r = tid; r < nint; r += kBlockT)
+        for (int k = 0; k < 3; ++k) zout[3 * (a + r) + k] = cur[3 * r + k];
 }
 
 // r_p = w' - x' with w' = x + (zeta' - zeta)/(mu alpha) (from the zeta
@@ -531,10 +613,19 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     int interval = check, next_check = check;
     float* za = w.z0.p;
     float* zb = w.z1.p;
-    // algorithmic bytes of one iteration: per face its three zeta, S copies
+    // blocked launches (several iterations each) without constraint groups
+    const Mesh::EdgeTileSet* tiles = nullptr;
+    if (!use_paths && o.admm_block > 1) tiles = m.ensure_edge_tiles(o.admm_block, s);
+    const int K = tiles ? o.admm_block : 1;
+    const int per = tiles ? (tiles->max_region + kBlockT - 1) / kBlockT : 0;
+    r.block = K;
+    // algorithmic bytes of one launch: per face its three zeta, S copies
     // and twin slots and its sign byte read, its three zeta written (the
-    // twins' zeta are the same array, read by their own faces)
-    r.bytes_per_iter = (uint64_t)49 * nf;
+    // twins' zeta are the same array, read by their own faces); blocked:
+    // per face its record, three zeta and S copies read and three zeta
+    // written once (halo re-reads and the occasional extra write of the
+    // state one iteration back are overhead)
+    r.bytes_per_iter = (uint64_t)(tiles ? 44 : 49) * nf;
     // path kernels: chunk sums read per slot its edge, slot pair, S', zeta
     // pair, sign and copy (28 B) and write 8 B per chunk; the fix reads per
     // slot its index, path, sign and copy and writes the copy (20 B), per
@@ -569,35 +660,75 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                                P.z.p, w.sumz.p, zi, zo, P.gzslot.p, mu, inv1mu, mu_relax, P.seff.p, w.sumd.p);
         }
     };
-    // runs of `check` iterations between two checks; with an even count the
-    // two buffers are back in their roles after a run, so one captured graph
-    // serves every full run
-    GraphChunk graph;
-    const bool graphs = !fixed && o.use_graphs && (check % 2) == 0;
+    // K iterations from zi into zo in one launch; with zp, zp also receives
+    // the state one iteration before zo's
+    auto iterate_block = [&](float* zi, float* zo, float* zp) {
+        const size_t lds = (size_t)6 * tiles->max_region * sizeof(float);
+        const int stride = 3 * tiles->max_region;
+        switch (per) {
+#define HG_TILED(P)                                                                                              \
+    case P:                                                                                                      \
+        hipLaunchKernelGGL(k_admm_edge_tiled<P>, dim3(tiles->n), dim3(kBlockT), lds, s, tiles->f0.p,             \
+                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, stride, mu, inv1mu, \
+                           mu_relax);                                                                            \
+        break;
+            HG_TILED(1)
+            HG_TILED(2)
+            HG_TILED(3)
+            HG_TILED(4)
+#undef HG_TILED
+            default: throw Error{HG_E_DEVICE, "blocked ADMM: region too large"};
+        }
+    };
+    // a run of n iterations from za: blocked launches while K fit, the last
+    // of them also keeping the state one iteration back (in w.h, whose
+    // directions the edge form has already turned into targets), then single
+    // iterations; returns the launches and sets zprev to the state one
+    // iteration before za's
+    // (with enqueue = false only the buffer roles are followed, for a run
+    // replayed from a graph)
+    float* zback = w.h.p;
+    const float* zprev = zb;
+    auto run = [&](int n, float*& a, float*& b, const float*& prev, bool enqueue) {
+        const int nb = tiles ? n / K : 0;
+        const int rest = n - nb * K;
+        for (int k = 0; k < nb; ++k) {
+            if (enqueue) iterate_block(a, b, (k == nb - 1 && rest == 0) ? zback : nullptr);
+            std::swap(a, b);
+        }
+        for (int k = 0; k < rest; ++k) {
+            if (enqueue) iterate(a, b);
+            std::swap(a, b);   // a is now the current state, b the previous
+        }
+        prev = rest > 0 ? b : (nb > 0 ? zback : b);
+        return nb + rest;
+    };
+    // runs of `check` iterations between two checks, one captured graph per
+    // starting buffer (a run may swap the buffers' roles)
+    GraphChunk graph[2];
+    const bool graphs = !fixed && o.use_graphs;
     int it = 0;
     while (it < cap) {
         const int n = std::min(check - it % check, cap - it);
+        GraphChunk& gr = graph[za == w.z0.p ? 0 : 1];
         rt.start(s);
-        if (graphs && n == check && !graph.tried)
-            graph.capture(s, [&] {
-                float *a = za, *b = zb;
-                for (int k = 0; k < n; ++k) {
-                    iterate(a, b);
-                    std::swap(a, b);
-                }
-            });
-        if (graphs && n == check && graph.ready()) {
-            graph.launch(s);
+        int launches = 0;
+        if (graphs && n == check && !gr.tried) {
+            float *a = za, *b = zb;
+            const float* pv = nullptr;
+            gr.capture(s, [&] { (void)run(n, a, b, pv, true); });
+        }
+        if (graphs && n == check && gr.ready()) {
+            gr.launch(s);
+            launches = run(n, za, zb, zprev, false);
         } else {
-            for (int k = 0; k < n; ++k) {
-                iterate(za, zb);
-                std::swap(za, zb);   // za is now the current state, zb the previous
-            }
+            launches = run(n, za, zb, zprev, true);
         }
         HG_CHECK_HIP(hipGetLastError());
         it += n;
         r.iters = it;
-        run_len = n;
+        r.launches += launches;
+        run_len = launches;
         r.kernel_ms += rt.stop(s);
         r.timed_launches += run_len;
         const bool want = it >= next_check || it == cap;
@@ -621,7 +752,7 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                     stop.restart();
                 }
             } else {
-                residuals(zb, za);
+                residuals(zprev, za);
                 done = r.rp <= o.tol_admm && r.rd <= o.tol_admm;
             }
             next_check = it + interval;
@@ -636,7 +767,7 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         r.timed_launches += run_len;
     }
     if (fixed) r.converged = true;
-    if (r.iters > 0) residuals(zb, za);
+    if (r.iters > 0) residuals(zprev, za);
     hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu, w.xe.p);
     HG_CHECK_HIP(hipGetLastError());
     // the seam of the final state (its d is the last check's), once
@@ -951,6 +1082,7 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     if (monitor && !stop.first && o.tol_seam <= 0.0) r.seam = seam_now(m, w, HG_FORM_FACE, nullptr, ga, s) / m.hbar;
     if (r.iters > 0) face_residuals(m, w, gf, gb, ga, zb, za, mu, o.relax, normM, s, r);
     HG_CHECK_HIP(hipMemcpyAsync(w.gf.p, ga, (size_t)3 * nf * sizeof(float), hipMemcpyDeviceToDevice, s));
+    r.launches = r.iters;
     return r;
 }
 
