@@ -131,7 +131,9 @@ typedef struct {
                                iteration; a mesh whose tiles do not fit in
                                LDS, and every solve with source paths or
                                generator loops, runs one iteration per
-                               launch.  0 = auto (default, 2) */
+                               launch.  In hg_geodesic_solve the distance
+                               checks then fall on multiples of k (the
+                               interval rounded up).  0 = auto (default, 3) */
     int32_t reserved[1];
 } hg_opts;
 

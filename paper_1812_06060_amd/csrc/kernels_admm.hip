@@ -213,40 +213,45 @@ __device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1m
 }
 
 // One folded iteration of a face from its three copies zo, the twins'
-// copies tz (0 on boundary slots, flagged in bnd) and the target sums S.
-__device__ inline void edge_face_update(const float zo[3], const float tz[3], const float S[3], const int bnd[3],
-                                        uint32_t sg, float mu, float inv1mu, float mu_relax, float zn[3]) {
-    float x[3];
-    for (int k = 0; k < 3; ++k) x[k] = edge_x(S[k], zo[k], tz[k], bnd[k], inv1mu);
-    float q[3], v[3];
+// copies tz (0 on boundary slots) and per slot the target sum S, the X-update
+// scale cS = 1 / (|H_e| (1 + mu)) and the sign q (Eq. 20); rmu = 1 / mu.
+// x = (S + zo + tz) cS equals edge_x exactly (the factor 1/2 is a power of
+// two).  Contraction is off and the fused operations are written out, so
+// every kernel that inlines this rounds the same way.
+__device__ inline void edge_face_update(const float zo[3], const float tz[3], const float S[3], const float cS[3],
+                                        const float q[3], float rmu, float mu_relax, float zn[3]) {
+#pragma clang fp contract(off)
+    float x[3], v[3];
     float qv = 0.f;
     for (int k = 0; k < 3; ++k) {
-        q[k] = (sg >> k) & 1 ? 1.f : -1.f;
-        v[k] = 2.f * x[k] - zo[k] / mu;
-        qv += q[k] * v[k];
+        x[k] = (S[k] + zo[k] + tz[k]) * cS[k];
+        v[k] = fmaf(-zo[k], rmu, x[k] + x[k]);
+        qv += q[k] * v[k];   // q = +-1: exact
     }
     qv *= (1.f / 3.f);
     for (int k = 0; k < 3; ++k) {
-        float w = v[k] - qv * q[k];
-        zn[k] = zo[k] + mu_relax * (w - x[k]);
+        const float w = fmaf(-qv, q[k], v[k]);
+        zn[k] = fmaf(mu_relax, w - x[k], zo[k]);
     }
 }
 
 __device__ inline void admm_edge_face(int f, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
                                       const float* __restrict__ sumd, const float* __restrict__ zin,
-                                      float* __restrict__ zout, float mu, float inv1mu, float mu_relax) {
-    float zo[3], tz[3], S[3], zn[3];
-    int tw[3], bnd[3];
+                                      float* __restrict__ zout, float rmu, float inv1mu, float mu_relax) {
+    float zo[3], tz[3], S[3], cS[3], q[3], zn[3];
+    int tw[3];
     for (int k = 0; k < 3; ++k) {
         tw[k] = twin[3 * f + k];
         zo[k] = zin[3 * f + k];
     }
+    const uint32_t sg = fsign[f];
     for (int k = 0; k < 3; ++k) {
         tz[k] = tw[k] >= 0 ? zin[tw[k]] : 0.f;
-        bnd[k] = tw[k] < 0;
+        cS[k] = tw[k] >= 0 ? 0.5f * inv1mu : inv1mu;
+        q[k] = (sg >> k) & 1 ? 1.f : -1.f;
         S[k] = sumd[3 * f + k];
     }
-    edge_face_update(zo, tz, S, bnd, fsign[f], mu, inv1mu, mu_relax, zn);
+    edge_face_update(zo, tz, S, cS, q, rmu, mu_relax, zn);
     for (int k = 0; k < 3; ++k) zout[3 * f + k] = zn[k];
 }
 
@@ -254,10 +259,10 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const int32_t* __
                                                        const uint8_t* __restrict__ fsign,
                                                        const float* __restrict__ sumd,
                                                        const float* __restrict__ zin, float* __restrict__ zout,
-                                                       float mu, float inv1mu, float mu_relax) {
+                                                       float rmu, float inv1mu, float mu_relax) {
     int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
-    admm_edge_face(f, twin, fsign, sumd, zin, zout, mu, inv1mu, mu_relax);
+    admm_edge_face(f, twin, fsign, sumd, zin, zout, rmu, inv1mu, mu_relax);
 }
 
 // `iters` iterations per launch over LDS-resident regions (face tiles with
@@ -275,32 +280,62 @@ template <int PER>
 __global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
     const int32_t* __restrict__ f0, const int32_t* __restrict__ rptr, const int32_t* __restrict__ halo,
     const uint64_t* __restrict__ rec, const float* __restrict__ sumd, const float* __restrict__ zin,
-    float* __restrict__ zout, float* __restrict__ zprev, int iters, int stride, float mu, float inv1mu,
+    float* __restrict__ zout, float* __restrict__ zprev, int iters, int stride, float rmu, float inv1mu,
     float mu_relax) {
-    extern __shared__ float zl[];
+    extern __shared__ float zl[];   // two buffers of `stride` floats; the last of each is a zero
     const int p = xcd_block(blockIdx.x, gridDim.x);
     const int a = f0[p], nint = f0[p + 1] - a;
     const int rb = rptr[p], nreg = rptr[p + 1] - rb;
     if (nint == 0) return;   // the same for the whole workgroup
     const int hb = rb - a;
     const int tid = threadIdx.x;
+    const int zero = stride - 1;
     float* cur = zl;
     float* nxt = zl + stride;
+    // per region face: LDS index of each twin copy (the zero slot on the
+    // boundary, the face's own copy for a twin outside the region), the
+    // X-update scales, signs and target sums, kept in registers for the launch
+    // (all of a thread's loads are issued before any is used, in two
+    // rounds: the halo faces' ids, then the faces' data; threads past the
+    // region load the region's last face and discard it)
+    int ta[PER][3], g[PER];
+    float S[PER][3], cS[PER][3], q[PER][3], z[PER][3];
     uint64_t R[PER];
-    float S[PER][3];
+    const int nh = nreg - nint;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int r = min(tid + j * kBlockT, nreg - 1);
+        g[j] = a + r;
+        if (nh > 0) {   // the same for the whole workgroup
+            const int hg = halo[hb + min(max(r - nint, 0), nh - 1)];
+            if (r >= nint) g[j] = hg;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int r = min(tid + j * kBlockT, nreg - 1);
+        R[j] = rec[rb + r];
+        for (int k = 0; k < 3; ++k) {
+            S[j][k] = sumd[3 * g[j] + k];
+            z[j][k] = zin[3 * g[j] + k];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int r = tid + j * kBlockT;
-        R[j] = 0;
-        S[j][0] = S[j][1] = S[j][2] = 0.f;
-        if (r < nreg) {
-            const int g = r < nint ? a + r : halo[hb + r - nint];
-            R[j] = rec[rb + r];
-            for (int k = 0; k < 3; ++k) {
-                S[j][k] = sumd[3 * g + k];
-                cur[3 * r + k] = zin[3 * g + k];
-            }
+        const uint32_t sg = (uint32_t)(R[j] >> 48);
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t c = (uint32_t)(R[j] >> (16 * k)) & 0xFFFFu;
+            ta[j][k] = c == kTwinNone ? zero : (c == kTwinOut ? 3 * r + k : (int)c);
+            cS[j][k] = c == kTwinNone ? inv1mu : 0.5f * inv1mu;
+            q[j][k] = (sg >> k) & 1 ? 1.f : -1.f;
         }
+        if (r < nreg)
+            for (int k = 0; k < 3; ++k) cur[3 * r + k] = z[j][k];
+    }
+    if (tid == 0) {
+        cur[zero] = 0.f;
+        nxt[zero] = 0.f;
     }
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
@@ -309,14 +344,9 @@ __global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
             const int r = tid + j * kBlockT;
             if (r >= nreg) continue;
             float zo[3], tz[3], zn[3];
-            int bnd[3];
             for (int k = 0; k < 3; ++k) zo[k] = cur[3 * r + k];
-            for (int k = 0; k < 3; ++k) {
-                const uint32_t c = (uint32_t)(R[j] >> (16 * k)) & 0xFFFFu;
-                bnd[k] = c == kTwinNone;
-                tz[k] = c == kTwinNone ? 0.f : (c == kTwinOut ? zo[k] : cur[c]);
-            }
-            edge_face_update(zo, tz, S[j], bnd, (uint32_t)(R[j] >> 48), mu, inv1mu, mu_relax, zn);
+            for (int k = 0; k < 3; ++k) tz[k] = cur[ta[j][k]];
+            edge_face_update(zo, tz, S[j], cS[j], q[j], rmu, mu_relax, zn);
             for (int k = 0; k < 3; ++k) nxt[3 * r + k] = zn[k];
         }
         __syncthreads();
@@ -458,8 +488,8 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge_paths(
     const float* __restrict__ sumd, const float* __restrict__ zin, float* __restrict__ zout,
     const int32_t* __restrict__ chunk_path, const int32_t* __restrict__ cptr, const int32_t* __restrict__ ptr,
     const int32_t* __restrict__ edge, const float* __restrict__ sign, const int2* __restrict__ zslot,
-    const float* __restrict__ seff, const float* __restrict__ zp, double* __restrict__ pc, float mu, float inv1mu,
-    float mu_relax) {
+    const float* __restrict__ seff, const float* __restrict__ zp, double* __restrict__ pc, float mu, float rmu,
+    float inv1mu, float mu_relax) {
     __shared__ double sh[kBlockA / 64];
     if ((int)blockIdx.x < nch) {
         path_edge_chunk_block((int)blockIdx.x, chunk_path, cptr, ptr, edge, sign, zslot, seff, zin, zp, pc, mu,
@@ -467,7 +497,7 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge_paths(
         return;
     }
     const int f = xcd_block((int)blockIdx.x - nch, nfb) * blockDim.x + threadIdx.x;
-    if (f < nf) admm_edge_face(f, twin, fsign, sumd, zin, zout, mu, inv1mu, mu_relax);
+    if (f < nf) admm_edge_face(f, twin, fsign, sumd, zin, zout, rmu, inv1mu, mu_relax);
 }
 
 // Second half, one thread per edge carrying path slots: each slot's copy is
@@ -581,6 +611,7 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     w.sumd.alloc((size_t)3 * nf);
     w.xe.alloc(ne);
     const float mu = (float)o.mu, inv1mu = 1.0f / (1.0f + mu), mu_relax = (float)(o.mu * o.relax);
+    const float rmu = 1.0f / mu;
     const int gf = grid_for(nf, kBlockA), ge = grid_for(ne, kBlockA);
     if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
     if (m.intrinsic)
@@ -607,18 +638,21 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const bool fixed = iters > 0;
     const bool monitor = !fixed && depth >= 0;
     const int cap = fixed ? iters : o.max_admm;
-    const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
-    // iterations between two checks: one chunk, or kCoarseChecks chunks far
-    // from convergence (DistStop)
-    int interval = check, next_check = check;
-    float* za = w.z0.p;
-    float* zb = w.z1.p;
     // blocked launches (several iterations each) without constraint groups
     const Mesh::EdgeTileSet* tiles = nullptr;
     if (!use_paths && o.admm_block > 1) tiles = m.ensure_edge_tiles(o.admm_block, s);
     const int K = tiles ? o.admm_block : 1;
     const int per = tiles ? (tiles->max_region + kBlockT - 1) / kBlockT : 0;
     r.block = K;
+    // distance checks at least 64 iterations apart, at a multiple of the
+    // iterations per launch
+    const int check =
+        monitor ? (std::max(64, o.check_every) + K - 1) / K * K : std::max(1, o.check_every);
+    // iterations between two checks: one chunk, or kCoarseChecks chunks far
+    // from convergence (DistStop)
+    int interval = check, next_check = check;
+    float* za = w.z0.p;
+    float* zb = w.z1.p;
     // algorithmic bytes of one launch: per face its three zeta, S copies
     // and twin slots and its sign byte read, its three zeta written (the
     // twins' zeta are the same array, read by their own faces); blocked:
@@ -650,11 +684,11 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     auto iterate = [&](float* zi, float* zo) {
         if (!use_paths) {
             hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.twin.p, m.fsign.p, w.sumd.p, zi, zo,
-                               mu, inv1mu, mu_relax);
+                               rmu, inv1mu, mu_relax);
         } else {
             hipLaunchKernelGGL(k_admm_edge_paths, dim3(gf + P.nch), dim3(kBlockA), 0, s, nf, gf, P.nch, m.twin.p,
                                m.fsign.p, w.sumd.p, zi, zo, P.chunk_path.p, P.cptr.p, P.ptr.p, P.edge.p, P.sign.p,
-                               P.zslot.p, S, P.z.p, P.pc.p, mu, inv1mu, mu_relax);
+                               P.zslot.p, S, P.z.p, P.pc.p, mu, rmu, inv1mu, mu_relax);
             hipLaunchKernelGGL(k_path_edge_fix, dim3(grid_for(P.ng_edge, kBlockA)), dim3(kBlockA), 0, s, P.ng_edge,
                                P.eg_ptr.p, P.eg_id.p, P.eg_slot.p, P.spath.p, P.ptr.p, P.cptr.p, P.pc.p, P.sign.p,
                                P.z.p, w.sumz.p, zi, zo, P.gzslot.p, mu, inv1mu, mu_relax, P.seff.p, w.sumd.p);
@@ -663,13 +697,13 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     // K iterations from zi into zo in one launch; with zp, zp also receives
     // the state one iteration before zo's
     auto iterate_block = [&](float* zi, float* zo, float* zp) {
-        const size_t lds = (size_t)6 * tiles->max_region * sizeof(float);
-        const int stride = 3 * tiles->max_region;
+        const int stride = 3 * tiles->max_region + 1;   // + the zero slot
+        const size_t lds = (size_t)2 * stride * sizeof(float);
         switch (per) {
 #define HG_TILED(P)                                                                                              \
     case P:                                                                                                      \
         hipLaunchKernelGGL(k_admm_edge_tiled<P>, dim3(tiles->n), dim3(kBlockT), lds, s, tiles->f0.p,             \
-                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, stride, mu, inv1mu, \
+                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, stride, rmu, inv1mu, \
                            mu_relax);                                                                            \
         break;
             HG_TILED(1)

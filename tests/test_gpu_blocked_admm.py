@@ -100,19 +100,28 @@ def test_blocked_to_residual_tolerance(case, hg):
 
 
 @pytest.mark.parametrize("graphs", [0, 1])
-@pytest.mark.parametrize("check", [64, 65])
-def test_blocked_solve_identical(case, hg, graphs, check):
+@pytest.mark.parametrize("K, check", [(4, 64), (3, 66), (3, 69)])
+def test_blocked_solve_identical(case, hg, graphs, K, check):
+    """Check intervals that are multiples of K give the single-iteration
+    schedule's checks; 69 / 3 = 23 launches per run swaps the buffers'
+    roles, so graphs are captured from both buffers."""
     name, v, f, src, mesh = case
     base = dict(use_graphs=graphs, check_every=check, cycle_constraints=0)
     d1, i1 = mesh.solve(src, 0.0, hg.default_opts(admm_block=1, **base))
-    d4, i4 = mesh.solve(src, 0.0, hg.default_opts(admm_block=4, **base))
-    _say(name, "solve graphs", graphs, "check", check, "iters", i1.admm_iters, i4.admm_iters,
-         "launches", i4.admm_launches)
-    assert i4.admm_block == 4 and i1.admm_block == 1
-    assert i1.admm_iters == i4.admm_iters
-    assert i4.admm_launches < i1.admm_launches
-    a, b = d1.cpu().numpy(), d4.cpu().numpy()
+    dK, iK = mesh.solve(src, 0.0, hg.default_opts(admm_block=K, **base))
+    _say(name, "solve graphs", graphs, "K", K, "check", check, "iters", i1.admm_iters, iK.admm_iters,
+         "launches", iK.admm_launches)
+    assert iK.admm_block == K and i1.admm_block == 1
+    assert i1.admm_iters == iK.admm_iters
+    assert iK.admm_launches * K == iK.admm_iters
+    a, b = d1.cpu().numpy(), dK.cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_check_interval_rounded_to_block(case, hg):
+    name, v, f, src, mesh = case
+    _, i = mesh.solve(src, 0.0, hg.default_opts(admm_block=3, cycle_constraints=0))
+    assert i.admm_block == 3 and i.admm_iters % 66 == 0 and i.admm_launches * 3 == i.admm_iters
 
 
 def test_default_is_blocked_and_paths_fall_back(hg):
@@ -121,7 +130,7 @@ def test_default_is_blocked_and_paths_fall_back(hg):
     mesh = hg.Mesh(v, f)
     try:
         _, i = mesh.solve(src[:1], 0.0, hg.default_opts())
-        assert i.admm_block == 2
+        assert i.admm_block == 3
         _, i = mesh.solve(src, 0.0, hg.default_opts())         # source paths: single iterations
         assert i.admm_block == 1 and i.n_paths == 2 and i.admm_launches == i.admm_iters
         _, i = mesh.solve(src[:1], 0.0, hg.default_opts(formulation="face"))
