@@ -133,7 +133,7 @@ typedef struct {
                                generator loops, runs one iteration per
                                launch.  In hg_geodesic_solve the distance
                                checks then fall on multiples of k (the
-                               interval rounded up).  0 = auto (default, 3) */
+                               interval rounded up).  0 = auto (default, 4) */
     int32_t reserved[1];
 } hg_opts;
 

@@ -212,19 +212,20 @@ __device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1m
     return bnd ? (S + z0) * inv1mu : 0.5f * (S + z0 + z1) * inv1mu;
 }
 
-// One folded iteration of a face from its three copies zo, the twins'
-// copies tz (0 on boundary slots) and per slot the target sum S, the X-update
-// scale cS = 1 / (|H_e| (1 + mu)) and the sign q (Eq. 20); rmu = 1 / mu.
-// x = (S + zo + tz) cS equals edge_x exactly (the factor 1/2 is a power of
-// two).  Contraction is off and the fused operations are written out, so
-// every kernel that inlines this rounds the same way.
-__device__ inline void edge_face_update(const float zo[3], const float tz[3], const float S[3], const float cS[3],
-                                        const float q[3], float rmu, float mu_relax, float zn[3]) {
+// One folded iteration of a face from its three copies zo and per slot the
+// twin's copy tz and target sum S, with c = 1 / (2 (1 + mu)) and the sign q
+// (Eq. 20); rmu = 1 / mu.  The X-update x = (S + zo + tz) c covers both
+// kinds of edge: an interior edge has |H_e| = 2; a boundary slot passes its
+// own copy as tz and 2 S, which gives (S + zo) / (1 + mu) up to rounding.
+// Contraction is off and the fused operations are written out, so every
+// kernel that inlines this rounds the same way.
+__device__ inline void edge_face_update(const float zo[3], const float tz[3], const float S[3], const float q[3],
+                                        float c, float rmu, float mu_relax, float zn[3]) {
 #pragma clang fp contract(off)
     float x[3], v[3];
     float qv = 0.f;
     for (int k = 0; k < 3; ++k) {
-        x[k] = (S[k] + zo[k] + tz[k]) * cS[k];
+        x[k] = (S[k] + zo[k] + tz[k]) * c;
         v[k] = fmaf(-zo[k], rmu, x[k] + x[k]);
         qv += q[k] * v[k];   // q = +-1: exact
     }
@@ -237,8 +238,8 @@ __device__ inline void edge_face_update(const float zo[3], const float tz[3], co
 
 __device__ inline void admm_edge_face(int f, const int32_t* __restrict__ twin, const uint8_t* __restrict__ fsign,
                                       const float* __restrict__ sumd, const float* __restrict__ zin,
-                                      float* __restrict__ zout, float rmu, float inv1mu, float mu_relax) {
-    float zo[3], tz[3], S[3], cS[3], q[3], zn[3];
+                                      float* __restrict__ zout, float rmu, float c, float mu_relax) {
+    float zo[3], tz[3], S[3], q[3], zn[3];
     int tw[3];
     for (int k = 0; k < 3; ++k) {
         tw[k] = twin[3 * f + k];
@@ -246,12 +247,12 @@ __device__ inline void admm_edge_face(int f, const int32_t* __restrict__ twin, c
     }
     const uint32_t sg = fsign[f];
     for (int k = 0; k < 3; ++k) {
-        tz[k] = tw[k] >= 0 ? zin[tw[k]] : 0.f;
-        cS[k] = tw[k] >= 0 ? 0.5f * inv1mu : inv1mu;
+        const float sd = sumd[3 * f + k];
+        tz[k] = tw[k] >= 0 ? zin[tw[k]] : zo[k];
+        S[k] = tw[k] >= 0 ? sd : 2.f * sd;
         q[k] = (sg >> k) & 1 ? 1.f : -1.f;
-        S[k] = sumd[3 * f + k];
     }
-    edge_face_update(zo, tz, S, cS, q, rmu, mu_relax, zn);
+    edge_face_update(zo, tz, S, q, c, rmu, mu_relax, zn);
     for (int k = 0; k < 3; ++k) zout[3 * f + k] = zn[k];
 }
 
@@ -259,10 +260,10 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const int32_t* __
                                                        const uint8_t* __restrict__ fsign,
                                                        const float* __restrict__ sumd,
                                                        const float* __restrict__ zin, float* __restrict__ zout,
-                                                       float rmu, float inv1mu, float mu_relax) {
+                                                       float rmu, float c, float mu_relax) {
     int f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= nf) return;
-    admm_edge_face(f, twin, fsign, sumd, zin, zout, rmu, inv1mu, mu_relax);
+    admm_edge_face(f, twin, fsign, sumd, zin, zout, rmu, c, mu_relax);
 }
 
 // `iters` iterations per launch over LDS-resident regions (face tiles with
@@ -280,26 +281,25 @@ template <int PER>
 __global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
     const int32_t* __restrict__ f0, const int32_t* __restrict__ rptr, const int32_t* __restrict__ halo,
     const uint64_t* __restrict__ rec, const float* __restrict__ sumd, const float* __restrict__ zin,
-    float* __restrict__ zout, float* __restrict__ zprev, int iters, int stride, float rmu, float inv1mu,
+    float* __restrict__ zout, float* __restrict__ zprev, int iters, int stride, float rmu, float c,
     float mu_relax) {
-    extern __shared__ float zl[];   // two buffers of `stride` floats; the last of each is a zero
+    extern __shared__ float zl[];   // two buffers of `stride` floats
     const int p = xcd_block(blockIdx.x, gridDim.x);
     const int a = f0[p], nint = f0[p + 1] - a;
     const int rb = rptr[p], nreg = rptr[p + 1] - rb;
     if (nint == 0) return;   // the same for the whole workgroup
     const int hb = rb - a;
     const int tid = threadIdx.x;
-    const int zero = stride - 1;
     float* cur = zl;
     float* nxt = zl + stride;
-    // per region face: LDS index of each twin copy (the zero slot on the
-    // boundary, the face's own copy for a twin outside the region), the
-    // X-update scales, signs and target sums, kept in registers for the launch
+    // per region face: LDS index of each twin copy (the face's own copy on
+    // the boundary and for a twin outside the region), target sums (doubled
+    // on the boundary) and signs, kept in registers for the launch
     // (all of a thread's loads are issued before any is used, in two
     // rounds: the halo faces' ids, then the faces' data; threads past the
     // region load the region's last face and discard it)
     int ta[PER][3], g[PER];
-    float S[PER][3], cS[PER][3], q[PER][3], z[PER][3];
+    float S[PER][3], q[PER][3], z[PER][3];
     uint64_t R[PER];
     const int nh = nreg - nint;
 #pragma unroll
@@ -325,17 +325,13 @@ __global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
         const int r = tid + j * kBlockT;
         const uint32_t sg = (uint32_t)(R[j] >> 48);
         for (int k = 0; k < 3; ++k) {
-            const uint32_t c = (uint32_t)(R[j] >> (16 * k)) & 0xFFFFu;
-            ta[j][k] = c == kTwinNone ? zero : (c == kTwinOut ? 3 * r + k : (int)c);
-            cS[j][k] = c == kTwinNone ? inv1mu : 0.5f * inv1mu;
+            const uint32_t code = (uint32_t)(R[j] >> (16 * k)) & 0xFFFFu;
+            ta[j][k] = code >= kTwinOut ? 3 * r + k : (int)code;
+            if (code == kTwinNone) S[j][k] = 2.f * S[j][k];
             q[j][k] = (sg >> k) & 1 ? 1.f : -1.f;
         }
         if (r < nreg)
             for (int k = 0; k < 3; ++k) cur[3 * r + k] = z[j][k];
-    }
-    if (tid == 0) {
-        cur[zero] = 0.f;
-        nxt[zero] = 0.f;
     }
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
@@ -346,7 +342,7 @@ __global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
             float zo[3], tz[3], zn[3];
             for (int k = 0; k < 3; ++k) zo[k] = cur[3 * r + k];
             for (int k = 0; k < 3; ++k) tz[k] = cur[ta[j][k]];
-            edge_face_update(zo, tz, S[j], cS[j], q[j], rmu, mu_relax, zn);
+            edge_face_update(zo, tz, S[j], q[j], c, rmu, mu_relax, zn);
             for (int k = 0; k < 3; ++k) nxt[3 * r + k] = zn[k];
         }
         __syncthreads();
@@ -497,7 +493,7 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge_paths(
         return;
     }
     const int f = xcd_block((int)blockIdx.x - nch, nfb) * blockDim.x + threadIdx.x;
-    if (f < nf) admm_edge_face(f, twin, fsign, sumd, zin, zout, rmu, inv1mu, mu_relax);
+    if (f < nf) admm_edge_face(f, twin, fsign, sumd, zin, zout, rmu, 0.5f * inv1mu, mu_relax);
 }
 
 // Second half, one thread per edge carrying path slots: each slot's copy is
@@ -611,7 +607,7 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     w.sumd.alloc((size_t)3 * nf);
     w.xe.alloc(ne);
     const float mu = (float)o.mu, inv1mu = 1.0f / (1.0f + mu), mu_relax = (float)(o.mu * o.relax);
-    const float rmu = 1.0f / mu;
+    const float rmu = 1.0f / mu, chalf = 0.5f * inv1mu;
     const int gf = grid_for(nf, kBlockA), ge = grid_for(ne, kBlockA);
     if ((int)w.partial.n < 2 * gf + 8) w.partial.alloc((size_t)2 * gf + 8);
     if (m.intrinsic)
@@ -684,7 +680,7 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     auto iterate = [&](float* zi, float* zo) {
         if (!use_paths) {
             hipLaunchKernelGGL(k_admm_edge, dim3(gf), dim3(kBlockA), 0, s, nf, m.twin.p, m.fsign.p, w.sumd.p, zi, zo,
-                               rmu, inv1mu, mu_relax);
+                               rmu, chalf, mu_relax);
         } else {
             hipLaunchKernelGGL(k_admm_edge_paths, dim3(gf + P.nch), dim3(kBlockA), 0, s, nf, gf, P.nch, m.twin.p,
                                m.fsign.p, w.sumd.p, zi, zo, P.chunk_path.p, P.cptr.p, P.ptr.p, P.edge.p, P.sign.p,
@@ -697,13 +693,13 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     // K iterations from zi into zo in one launch; with zp, zp also receives
     // the state one iteration before zo's
     auto iterate_block = [&](float* zi, float* zo, float* zp) {
-        const int stride = 3 * tiles->max_region + 1;   // + the zero slot
+        const int stride = 3 * tiles->max_region;
         const size_t lds = (size_t)2 * stride * sizeof(float);
         switch (per) {
 #define HG_TILED(P)                                                                                              \
     case P:                                                                                                      \
         hipLaunchKernelGGL(k_admm_edge_tiled<P>, dim3(tiles->n), dim3(kBlockT), lds, s, tiles->f0.p,             \
-                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, stride, rmu, inv1mu, \
+                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, stride, rmu, chalf,  \
                            mu_relax);                                                                            \
         break;
             HG_TILED(1)
