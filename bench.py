@@ -221,6 +221,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_kernel_ms": kms, "alg_bytes_per_launch": int(kbytes)},
+        # the blocked edge ADMM runs several iterations per launch: its time per
+        # iteration against the HBM time of one iteration per launch (49 B per
+        # face read and written once at 8 TB/s)
+        "admm_per_iteration": (None if args.form != "edge" else {
+            "iterations_per_launch": block, "us": 1e3 * float(np.mean([i.ms_admm_kernel for i in infos])) / block,
+            "single_iteration_hbm_bound_us": 49.0 * mesh.nf / (HBM_PEAK_GBS * 1e9) * 1e6}),
         "alg_hbm_gbs_whole_solve": last.bytes_alg / (last.ms_total * 1e-3) / 1e9,
     }
     mesh.close()

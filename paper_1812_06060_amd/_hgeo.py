@@ -237,7 +237,14 @@ class Mesh:
         self.nv, self.nf, self.ne = st.nv, st.nf, st.ne
         self.hbar = st.hbar
         self.total_area = st.total_area
-        self.stats = {k: getattr(st, k) for k, _ in st._fields_ if k != "reserved"}
+
+    @property
+    def stats(self) -> dict:
+        """hg_mesh_get_stats, read now (mesh_bytes grows when a query first
+        builds the face form's slot records or the blocked ADMM's tiles)."""
+        st = MeshStats()
+        _check(_lib.hg_mesh_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_ if k != "reserved"}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -12,7 +12,8 @@ sweeps, automatic penalty), t = hbar^2 of each mesh.
 
 Reported: mesh build time, one solve after a warm solve (stage times, BFS
 depth, diffusion passes, ADMM iterations), the ADMM kernel's average time
-and algorithmic HBM rate, device bytes per vertex (mesh + query
+per launch (hg_info.admm_block iterations each) and algorithmic HBM rate,
+device bytes per vertex (mesh, with the blocked ADMM's face tiles, + query
 workspace), and the properties that hold at any size:
   * d = 0 at the source, finite and >= 0 everywhere;
   * |d_i - d_j| <= (1 + 0.05) l_ij over every edge with d < 0.9 max d (the
@@ -97,7 +98,9 @@ def _solve(level, v, f, src, log, seam_variant=None):
                                              "integrate": info.ms_integrate},
         "bfs_depth": info.bfs_depth, "diffusion_passes": info.passes, "sweeps": info.sweeps,
         "admm_iters": info.admm_iters, "converged": bool(info.converged_u and info.converged_admm),
+        "admm_block": info.admm_block, "admm_launches": info.admm_launches,
         "admm_kernel_us": 1e3 * info.ms_admm_kernel,
+        "admm_us_per_iteration": 1e3 * info.ms_admm_kernel / max(1, info.admm_block),
         "admm_kernel_gbs": info.bytes_admm_kernel / (info.ms_admm_kernel * 1e6) if info.ms_admm_kernel else None,
         "mesh_bytes": int(m.stats["mesh_bytes"]), "workspace_bytes": int(info.workspace_bytes),
         "bytes_per_vertex": (m.stats["mesh_bytes"] + info.workspace_bytes) / v.shape[0],
@@ -105,7 +108,8 @@ def _solve(level, v, f, src, log, seam_variant=None):
     row["seam_over_hbar"] = info.seam
     log(f"[scale] L{level} solve {row['solve_ms']:.0f} ms: diffusion {info.ms_diffusion:.0f} ms "
         f"({info.passes} passes), ADMM {info.ms_admm:.0f} ms ({info.admm_iters} iterations, "
-        f"{row['admm_kernel_us']:.0f} us, {row['admm_kernel_gbs']:.0f} GB/s), depth {info.bfs_depth}, "
+        f"{row['admm_kernel_us']:.0f} us per launch of {info.admm_block}, {row['admm_kernel_gbs']:.0f} GB/s), "
+        f"depth {info.bfs_depth}, "
         f"seam {info.seam:.2f} hbar")
     edges = m.edges().cpu().numpy()
     out = d.cpu().numpy()
