@@ -128,12 +128,15 @@ typedef struct {
                                halo of k rings of faces, with the result of k
                                single-iteration launches (the same
                                arithmetic) for fewer HBM bytes per
-                               iteration; a mesh whose tiles do not fit in
-                               LDS, and every solve with source paths or
-                               generator loops, runs one iteration per
-                               launch.  In hg_geodesic_solve the distance
-                               checks then fall on multiples of k (the
-                               interval rounded up).  0 = auto (default, 4) */
+                               iteration.  A mesh whose regions do not fit
+                               (at most 4096 faces each) uses the largest
+                               smaller k that fits; every solve with source
+                               paths or generator loops, and the face form,
+                               run one iteration per launch
+                               (hg_info.admm_block reports what was used).
+                               In hg_geodesic_solve the distance checks fall
+                               on multiples of k (the interval rounded up).
+                               0 = auto (default, 6) */
     int32_t reserved[1];
 } hg_opts;
 

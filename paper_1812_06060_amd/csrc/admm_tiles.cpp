@@ -172,11 +172,11 @@ const Mesh::EdgeTileSet* Mesh::ensure_edge_tiles(int rings, hipStream_t s) {
         if (t->rings == rings) return t->ok ? t.get() : nullptr;
     auto set = std::make_unique<EdgeTileSet>();
     set->rings = rings;
-    // region capacity: two copies of 3 floats per region face in LDS, at
-    // most 4 faces per thread of a 1024-thread workgroup
+    // region capacity: 3 floats per region face in LDS, at most 4 faces per
+    // thread of a 1024-thread workgroup
     int lds = 0;
     HG_CHECK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
-    const int cap = std::min(4096, lds / (int)(6 * sizeof(float)));
+    const int cap = std::min(4096, lds / (int)(3 * sizeof(float)));
     std::vector<int32_t> tri_h((size_t)3 * nf), twin_h((size_t)3 * nf), tptr((size_t)n_patches + 1);
     std::vector<uint8_t> sign_h((size_t)nf);
     HG_CHECK_HIP(hipMemcpyAsync(tri_h.data(), tri.p, tri.bytes(), hipMemcpyDeviceToHost, s));

@@ -154,7 +154,7 @@ void build_intrinsic(const double* xyz, int64_t nv, const int32_t* tri, int64_t 
 // the halo faces halo[rptr[p] - f0[p] ..] up to `rings` edge-adjacency steps
 // away; rec[rptr[p] + r] is region face r's record (twin copies, signs).
 constexpr int kMaxAdmmBlock = 8;    // iterations per blocked launch at most
-constexpr int kAutoAdmmBlock = 4;   // hg_opts.admm_block = 0
+constexpr int kAutoAdmmBlock = 6;   // hg_opts.admm_block = 0
 constexpr uint32_t kTwinNone = 0xFFFF;   // boundary slot: no twin
 constexpr uint32_t kTwinOut = 0xFFFE;    // twin outside the region
 struct EdgeTiles {

@@ -268,22 +268,24 @@ __global__ void __launch_bounds__(kBlockA) k_admm_edge(int nf, const int32_t* __
 
 // `iters` iterations per launch over LDS-resident regions (face tiles with
 // halos of `iters` rings, see admm_tiles.cpp): one workgroup per tile loads
-// its region's copies, target sums and records, runs the iterations with two
-// LDS buffers, and writes back its own faces (and, with zprev, their state
-// one iteration before the last).  Every face update is the one of
+// its region's copies, target sums and records into LDS and registers, runs
+// the iterations (each computes every face's new copies from LDS into
+// registers, then after a barrier stores them back: one LDS buffer), and
+// writes back its own faces (and, with zprev, their state one iteration
+// before the last).  Every face update is the one of
 // k_admm_edge, so the result is that of `iters` plain launches.  A halo face
 // whose twin lies outside the region uses its own copy in its place; such
 // faces are at the region's edge and, like every face d rings out, are
 // exact only for iters - d iterations, which the tile's faces never read
 // beyond.
+// (8 waves per SIMD: two 1024-thread workgroups per CU, so at most 64 VGPRs)
 constexpr int kBlockT = 1024;
 template <int PER>
-__global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
+__global__ void __launch_bounds__(kBlockT, 8) k_admm_edge_tiled(
     const int32_t* __restrict__ f0, const int32_t* __restrict__ rptr, const int32_t* __restrict__ halo,
     const uint64_t* __restrict__ rec, const float* __restrict__ sumd, const float* __restrict__ zin,
-    float* __restrict__ zout, float* __restrict__ zprev, int iters, int stride, float rmu, float c,
-    float mu_relax) {
-    extern __shared__ float zl[];   // two buffers of `stride` floats
+    float* __restrict__ zout, float* __restrict__ zprev, int iters, float rmu, float c, float mu_relax) {
+    extern __shared__ float zl[];   // 3 copies per region face
     const int p = xcd_block(blockIdx.x, gridDim.x);
     const int a = f0[p], nint = f0[p + 1] - a;
     const int rb = rptr[p], nreg = rptr[p + 1] - rb;
@@ -291,7 +293,6 @@ __global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
     const int hb = rb - a;
     const int tid = threadIdx.x;
     float* cur = zl;
-    float* nxt = zl + stride;
     // per region face: LDS index of each twin copy (the face's own copy on
     // the boundary and for a twin outside the region), target sums (doubled
     // on the boundary) and signs, kept in registers for the launch
@@ -335,20 +336,24 @@ __global__ void __launch_bounds__(kBlockT) k_admm_edge_tiled(
     }
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
+        float zn[PER][3];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int r = tid + j * kBlockT;
             if (r >= nreg) continue;
-            float zo[3], tz[3], zn[3];
+            float zo[3], tz[3];
             for (int k = 0; k < 3; ++k) zo[k] = cur[3 * r + k];
             for (int k = 0; k < 3; ++k) tz[k] = cur[ta[j][k]];
-            edge_face_update(zo, tz, S[j], q[j], c, rmu, mu_relax, zn);
-            for (int k = 0; k < 3; ++k) nxt[3 * r + k] = zn[k];
+            edge_face_update(zo, tz, S[j], q[j], c, rmu, mu_relax, zn[j]);
         }
         __syncthreads();
-        float* t = cur;
-        cur = nxt;
-        nxt = t;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int r = tid + j * kBlockT;
+            if (r >= nreg) continue;
+            for (int k = 0; k < 3; ++k) cur[3 * r + k] = zn[j][k];
+        }
+        __syncthreads();
         if (zprev && it == iters - 2) {
             for (int r = tid; r < nint; r += kBlockT)
                 for (int k = 0; k < 3; ++k) zprev[3 * (a + r) + k] = cur[3 * r + k];
@@ -634,10 +639,12 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const bool fixed = iters > 0;
     const bool monitor = !fixed && depth >= 0;
     const int cap = fixed ? iters : o.max_admm;
-    // blocked launches (several iterations each) without constraint groups
+    // blocked launches (several iterations each) without constraint groups:
+    // the largest block size up to the requested one whose regions fit
     const Mesh::EdgeTileSet* tiles = nullptr;
-    if (!use_paths && o.admm_block > 1) tiles = m.ensure_edge_tiles(o.admm_block, s);
-    const int K = tiles ? o.admm_block : 1;
+    int K = 1;
+    for (int k = use_paths ? 1 : o.admm_block; k > 1 && !tiles; --k)
+        if ((tiles = m.ensure_edge_tiles(k, s))) K = k;
     const int per = tiles ? (tiles->max_region + kBlockT - 1) / kBlockT : 0;
     r.block = K;
     // distance checks at least 64 iterations apart, at a multiple of the
@@ -693,13 +700,12 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     // K iterations from zi into zo in one launch; with zp, zp also receives
     // the state one iteration before zo's
     auto iterate_block = [&](float* zi, float* zo, float* zp) {
-        const int stride = 3 * tiles->max_region;
-        const size_t lds = (size_t)2 * stride * sizeof(float);
+        const size_t lds = (size_t)3 * tiles->max_region * sizeof(float);
         switch (per) {
 #define HG_TILED(P)                                                                                              \
     case P:                                                                                                      \
         hipLaunchKernelGGL(k_admm_edge_tiled<P>, dim3(tiles->n), dim3(kBlockT), lds, s, tiles->f0.p,             \
-                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, stride, rmu, chalf,  \
+                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, rmu, chalf,        \
                            mu_relax);                                                                            \
         break;
             HG_TILED(1)

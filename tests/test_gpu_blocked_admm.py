@@ -130,7 +130,7 @@ def test_default_is_blocked_and_paths_fall_back(hg):
     mesh = hg.Mesh(v, f)
     try:
         _, i = mesh.solve(src[:1], 0.0, hg.default_opts())
-        assert i.admm_block == 4
+        assert i.admm_block == 6
         _, i = mesh.solve(src, 0.0, hg.default_opts())         # source paths: single iterations
         assert i.admm_block == 1 and i.n_paths == 2 and i.admm_launches == i.admm_iters
         _, i = mesh.solve(src[:1], 0.0, hg.default_opts(formulation="face"))
