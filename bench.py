@@ -225,7 +225,8 @@ def main():
         # iteration against the HBM time of one iteration per launch (49 B per
         # face read and written once at 8 TB/s)
         "admm_per_iteration": (None if args.form != "edge" else {
-            "iterations_per_launch": block, "us": 1e3 * float(np.mean([i.ms_admm_kernel for i in infos])) / block,
+            "iterations_per_launch": block,
+            "us": 1e3 * float(np.mean([i.ms_admm_kernel * i.admm_launches / i.admm_iters for i in infos])),
             "single_iteration_hbm_bound_us": 49.0 * mesh.nf / (HBM_PEAK_GBS * 1e9) * 1e6}),
         "alg_hbm_gbs_whole_solve": last.bytes_alg / (last.ms_total * 1e-3) / 1e9,
     }

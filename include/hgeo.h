@@ -134,9 +134,10 @@ typedef struct {
                                paths or generator loops, and the face form,
                                run one iteration per launch
                                (hg_info.admm_block reports what was used).
-                               In hg_geodesic_solve the distance checks fall
-                               on multiples of k (the interval rounded up).
-                               0 = auto (default, 6) */
+                               Between two checks the iterations run in
+                               launches of k and one launch of the rest, so
+                               the result, the iteration count included, is
+                               the same for every k.  0 = auto (default, 6) */
     int32_t reserved[1];
 } hg_opts;
 

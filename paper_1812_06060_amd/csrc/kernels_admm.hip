@@ -647,10 +647,7 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         if ((tiles = m.ensure_edge_tiles(k, s))) K = k;
     const int per = tiles ? (tiles->max_region + kBlockT - 1) / kBlockT : 0;
     r.block = K;
-    // distance checks at least 64 iterations apart, at a multiple of the
-    // iterations per launch
-    const int check =
-        monitor ? (std::max(64, o.check_every) + K - 1) / K * K : std::max(1, o.check_every);
+    const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
     // iterations between two checks: one chunk, or kCoarseChecks chunks far
     // from convergence (DistStop)
     int interval = check, next_check = check;
@@ -697,15 +694,16 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                                P.z.p, w.sumz.p, zi, zo, P.gzslot.p, mu, inv1mu, mu_relax, P.seff.p, w.sumd.p);
         }
     };
-    // K iterations from zi into zo in one launch; with zp, zp also receives
-    // the state one iteration before zo's
-    auto iterate_block = [&](float* zi, float* zo, float* zp) {
+    // n <= K iterations from zi into zo in one launch (the regions' K-ring
+    // halos cover any n up to K); with zp, zp also receives the state one
+    // iteration before zo's
+    auto iterate_block = [&](float* zi, float* zo, float* zp, int n) {
         const size_t lds = (size_t)3 * tiles->max_region * sizeof(float);
         switch (per) {
 #define HG_TILED(P)                                                                                              \
     case P:                                                                                                      \
         hipLaunchKernelGGL(k_admm_edge_tiled<P>, dim3(tiles->n), dim3(kBlockT), lds, s, tiles->f0.p,             \
-                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, K, rmu, chalf,        \
+                           tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, n, rmu, chalf,        \
                            mu_relax);                                                                            \
         break;
             HG_TILED(1)
@@ -716,28 +714,32 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
             default: throw Error{HG_E_DEVICE, "blocked ADMM: region too large"};
         }
     };
-    // a run of n iterations from za: blocked launches while K fit, the last
-    // of them also keeping the state one iteration back (in w.h, whose
-    // directions the edge form has already turned into targets), then single
-    // iterations; returns the launches and sets zprev to the state one
-    // iteration before za's
-    // (with enqueue = false only the buffer roles are followed, for a run
-    // replayed from a graph)
+    // a run of n iterations from za: blocked launches of K, then one of the
+    // remaining iterations (a single iteration runs the plain kernel); the
+    // last blocked launch also keeps the state one iteration back (in w.h,
+    // whose directions the edge form has already turned into targets).
+    // Returns the launches and sets prev to the state one iteration before
+    // a's.  (With enqueue = false only the buffer roles are followed, for a
+    // run replayed from a graph.)
     float* zback = w.h.p;
     const float* zprev = zb;
     auto run = [&](int n, float*& a, float*& b, const float*& prev, bool enqueue) {
         const int nb = tiles ? n / K : 0;
         const int rest = n - nb * K;
-        for (int k = 0; k < nb; ++k) {
-            if (enqueue) iterate_block(a, b, (k == nb - 1 && rest == 0) ? zback : nullptr);
+        const bool tail = tiles && rest >= 2;   // the remainder as one blocked launch
+        const int nl = nb + (tail ? 1 : 0);
+        const int single = tail ? 0 : rest;
+        for (int k = 0; k < nl; ++k) {
+            const int it_k = k < nb ? K : rest;
+            if (enqueue) iterate_block(a, b, (k == nl - 1 && single == 0) ? zback : nullptr, it_k);
             std::swap(a, b);
         }
-        for (int k = 0; k < rest; ++k) {
+        for (int k = 0; k < single; ++k) {
             if (enqueue) iterate(a, b);
             std::swap(a, b);   // a is now the current state, b the previous
         }
-        prev = rest > 0 ? b : (nb > 0 ? zback : b);
-        return nb + rest;
+        prev = single > 0 || nl == 0 ? b : zback;
+        return nl + single;
     };
     // runs of `check` iterations between two checks, one captured graph per
     // starting buffer (a run may swap the buffers' roles)

@@ -100,7 +100,7 @@ def _solve(level, v, f, src, log, seam_variant=None):
         "admm_iters": info.admm_iters, "converged": bool(info.converged_u and info.converged_admm),
         "admm_block": info.admm_block, "admm_launches": info.admm_launches,
         "admm_kernel_us": 1e3 * info.ms_admm_kernel,
-        "admm_us_per_iteration": 1e3 * info.ms_admm_kernel / max(1, info.admm_block),
+        "admm_us_per_iteration": 1e3 * info.ms_admm_kernel * info.admm_launches / max(1, info.admm_iters),
         "admm_kernel_gbs": info.bytes_admm_kernel / (info.ms_admm_kernel * 1e6) if info.ms_admm_kernel else None,
         "mesh_bytes": int(m.stats["mesh_bytes"]), "workspace_bytes": int(info.workspace_bytes),
         "bytes_per_vertex": (m.stats["mesh_bytes"] + info.workspace_bytes) / v.shape[0],
