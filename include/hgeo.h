@@ -156,10 +156,10 @@ typedef struct {
     uint64_t bytes_alg;     /* algorithmic HBM bytes of the solve's kernels */
     uint64_t workspace_bytes; /* device bytes held for this mesh's queries */
     int32_t converged_u, converged_admm;
-    /* average device time of one diffusion-pass kernel and of one launch
-       of the main ADMM kernel (admm_block iterations), from HIP events
-       around back-to-back launches on the solve's stream, and the
-       algorithmic HBM bytes one such launch moves */
+    /* average device time of one diffusion pass and of one launch of the
+       main ADMM kernel (up to admm_block iterations: see admm_launches),
+       from HIP events around back-to-back launches on the solve's stream,
+       and the algorithmic HBM bytes one such launch moves */
     float ms_pass_kernel, ms_admm_kernel;
     uint64_t bytes_pass_kernel, bytes_admm_kernel;
     int32_t n_paths;        /* source paths constrained (Eqs. 24-25) */
@@ -169,10 +169,14 @@ typedef struct {
                                over those loops */
     float seam;             /* hg_geodesic_solve: the last check's largest
                                seam / hbar (see hg_opts.tol_seam) */
-    int32_t admm_launches;  /* launches of the main ADMM kernel, each of
-                               admm_block iterations (ms_admm_kernel and
-                               bytes_admm_kernel are per such launch) */
-    int32_t admm_block;     /* iterations per launch actually used */
+    int32_t admm_launches;  /* launches of the main ADMM kernel: between
+                               two checks, launches of admm_block
+                               iterations and one of the rest
+                               (ms_admm_kernel and bytes_admm_kernel are
+                               per launch; admm_iters / admm_launches
+                               iterations per launch on average) */
+    int32_t admm_block;     /* iterations per launch actually used (1: one
+                               iteration per launch) */
     int32_t reserved[1];
 } hg_info;
 
