@@ -96,6 +96,10 @@ bool build_edge_tiles(int64_t nf, const std::vector<int32_t>& tri, const std::ve
         for (int p = id; p < nt; p += nth) {
             region.clear();
             map.clear();
+            if (out.f0[p + 1] - out.f0[p] > max_region) {   // the map holds at most max_region faces
+                too_big[id] = 1;
+                return;
+            }
             for (int32_t f = out.f0[p]; f < out.f0[p + 1]; ++f) {
                 map.insert(f, (int32_t)region.size());
                 region.push_back(f);
