@@ -34,6 +34,16 @@ Gauss-Seidel of Eqs. 6-7 -- the vertex sets D_i are swept in order, all
 vertices of one set updated simultaneously from the latest neighbour values.
 It is the paper's algorithm, kept for convergence studies; the exact solve is
 the oracle's answer.
+
+Second exact route (:func:`solve_log_gauge`): one sparse LU of the whole
+system after a diagonal similarity.  With E = diag(e^psi) for a potential psi
+that grows at least as fast as log u falls, v = E u solves
+(E M E^-1) v = E u_0 and stays inside the FP64 range.  A similarity by a
+positive diagonal keeps an M-matrix an M-matrix and leaves the diagonal of
+the inverse (hence every pivot of a diagonal-pivot LU) unchanged, so the
+factorisation and both triangular solves add terms of one sign only and the
+result is accurate componentwise.  It shares nothing with the banded solve
+but the matrix, so the two pin each other at sizes where both run.
 """
 from __future__ import annotations
 
@@ -176,6 +186,59 @@ def solve_log(M: sp.csr_matrix, sources, band_rings: int | None = None,
         if ok:
             return out
     raise RuntimeError("value-band refinement did not confirm its windows")
+
+
+def gauge_potential(M: sp.csr_matrix, verts, edges, t: float, sources) -> np.ndarray:
+    """psi for :func:`solve_log_gauge`: shortest-path distance from the
+    sources with edge weight min(ln(1/c), l/sqrt(t)), where l is the edge's
+    length and c = t theta / M_jj the smaller of its two coupling ratios.
+
+    ln(1/c) bounds the fall of log u across the edge (u_j >= c_jk u_k for an
+    M-matrix), so psi >= -log u + log u_s wherever that term is the minimum;
+    l/sqrt(t) is the continuum decay rate of the 1-D heat kernel
+    e^(-|x|/sqrt(t)), which the discrete solution does not exceed on
+    reasonable meshes (the caller checks the range of the scaled solution,
+    so a potential that falls short fails loudly instead of underflowing)."""
+    from scipy.sparse.csgraph import dijkstra
+    M = M.tocsr()
+    a, b = np.asarray(edges[:, 0]), np.asarray(edges[:, 1])
+    mab = -np.asarray(M[a, b]).ravel()          # t theta_ab (> 0 off the diagonal)
+    diag = M.diagonal()
+    with np.errstate(divide="ignore", invalid="ignore"):
+        c = np.minimum(mab / diag[a], mab / diag[b])
+        w_c = np.where(c > 0, -np.log(np.where(c > 0, c, 1.0)), np.inf)
+    length = np.linalg.norm(np.asarray(verts)[a] - np.asarray(verts)[b], axis=1)
+    w = np.minimum(w_c, length / np.sqrt(t))
+    nv = M.shape[0]
+    G = sp.csr_matrix((np.concatenate([w, w]), (np.concatenate([a, b]), np.concatenate([b, a]))),
+                      shape=(nv, nv))
+    return dijkstra(G, indices=np.unique(np.asarray(sources)), min_only=True)
+
+
+def solve_log_gauge(M: sp.csr_matrix, sources, psi: np.ndarray) -> np.ndarray:
+    """log u for M u = u_0 by one sparse LU of E M E^-1 (E = diag(e^psi)),
+    diagonal pivots, then log u = log v - psi.  Vertices with psi = inf (not
+    connected to a source) get -inf.  Raises if the scaled solution leaves
+    [1e-280, 1e280], i.e. if psi does not keep it inside the FP64 range."""
+    sources = np.unique(np.asarray(sources, dtype=np.int64))
+    M = M.tocsr()
+    nv = M.shape[0]
+    out = np.full(nv, -np.inf)
+    reach = np.flatnonzero(np.isfinite(psi))
+    if reach.size == 0:
+        return out
+    pr = psi[reach]
+    C = M[reach][:, reach].tocoo()
+    S = sp.csc_matrix((C.data * np.exp(pr[C.row] - pr[C.col]), (C.row, C.col)), shape=(reach.size,) * 2)
+    rhs = np.zeros(reach.size)
+    pos = np.searchsorted(reach, sources)
+    rhs[pos] = np.exp(pr[pos])
+    lu = spla.splu(S, permc_spec="COLAMD", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    v = lu.solve(rhs)
+    if not (np.all(np.isfinite(v)) and v.min() > 1e-280 and v.max() < 1e280):
+        raise RuntimeError(f"gauge-scaled diffusion left the FP64 range: v in [{v.min():.3e}, {v.max():.3e}]")
+    out[reach] = np.log(v) - pr
+    return out
 
 
 def gauss_seidel_bfs(K: sp.csr_matrix, A: np.ndarray, t: float, sources,

@@ -89,9 +89,14 @@ class VCycle:
         return self._cycle(0, b)
 
 
+class NotConverged(RuntimeError):
+    pass
+
+
 def pcg(A, b, M, rtol: float = 1e-10, maxiter: int = 500):
     """Plain preconditioned conjugate gradients; returns (x, iterations,
-    final relative residual)."""
+    final relative residual).  Raises NotConverged if the relative residual
+    is still above rtol after maxiter iterations."""
     x = np.zeros_like(b)
     r = b.copy()
     z = M(r)
@@ -110,12 +115,14 @@ def pcg(A, b, M, rtol: float = 1e-10, maxiter: int = 500):
         rz_new = r @ z
         p = z + (rz_new / rz) * p
         rz = rz_new
-    return x, maxiter, res
+    raise NotConverged(f"pcg: relative residual {res:.3e} > {rtol:.1e} after {maxiter} iterations")
 
 
 def dirichlet_solve_mg(L: sp.spmatrix, rhs: np.ndarray, sources, Ps, rtol: float = 1e-10):
     """Solve L d = rhs with d = 0 at the sources by multigrid-preconditioned
-    CG; the prolongations are restricted to the free vertices."""
+    CG; the prolongations are restricted to the free vertices.  Returns
+    (d, iterations, relative residual |rhs_F - L_FF d_F| / |rhs_F| recomputed
+    from d), and raises NotConverged if that residual exceeds 10 rtol."""
     nv = L.shape[0]
     fixed = np.zeros(nv, dtype=bool)
     fixed[np.asarray(sources)] = True
@@ -124,7 +131,11 @@ def dirichlet_solve_mg(L: sp.spmatrix, rhs: np.ndarray, sources, Ps, rtol: float
     Aff = Lc[free][:, free].tocsr()
     Ps_f = [Ps[0][free]] + list(Ps[1:]) if Ps else []
     M = VCycle(Aff, Ps_f) if Ps_f else (lambda b: b / Aff.diagonal())
-    x, it, res = pcg(Aff, rhs[free], M, rtol=rtol)
+    x, it, _ = pcg(Aff, rhs[free], M, rtol=rtol)
+    bf = rhs[free]
+    res = float(np.linalg.norm(bf - Aff @ x) / np.linalg.norm(bf))
+    if res > 10.0 * rtol:
+        raise NotConverged(f"dirichlet_solve_mg: true relative residual {res:.3e}")
     d = np.zeros(nv)
     d[free] = x
     return d, it, res

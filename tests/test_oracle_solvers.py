@@ -511,3 +511,154 @@ def test_unreachable_component_is_infinite():
     r = pipeline.heat_method(v, f, [0])
     assert np.all(np.isfinite(r.d[:v1.shape[0]])) and np.all(np.isinf(r.d[v1.shape[0]:]))
     assert np.all(r.level[v1.shape[0]:] == -1)
+
+
+# ------------------------------------------ gauge-scaled whole-mesh diffusion
+def test_gauge_route_matches_dense_and_banded(bumpy3):
+    """The gauge-scaled whole-mesh LU equals a dense solve where FP64 holds
+    u, and the banded solve (a different exact route) on a larger mesh."""
+    v, f = bumpy3
+    topo, K, A, t = _setup(v, f)
+    M = diffusion.heat_matrix(K, A, t)
+    dense = np.linalg.solve(M.toarray(), np.eye(v.shape[0])[17])
+    psi = diffusion.gauge_potential(M, v, topo.edges, t, [17])
+    lg = diffusion.solve_log_gauge(M, [17], psi)
+    assert np.abs(lg - np.log(dense)).max() < 1e-11
+    v6, f6 = meshgen.icosphere(6)
+    v6 = meshgen.harmonic_displacement(v6, seed=3)
+    topo6, K6, A6, t6 = _setup(v6, f6)
+    M6 = diffusion.heat_matrix(K6, A6, t6)
+    src = [5, 30001]
+    lb = diffusion.solve_log(M6, src)
+    lg6 = diffusion.solve_log_gauge(M6, src, diffusion.gauge_potential(M6, v6, topo6.edges, t6, src))
+    assert np.abs(lg6 - lb).max() < 1e-9 * np.abs(lb).max()
+
+
+@pytest.mark.parametrize("m", [1e-4, 0.01])
+def test_gauge_route_beyond_fp64_range_vs_80bit_jacobi(m):
+    """Where u itself leaves the FP64 range, the gauge-scaled solve matches an
+    80-bit Jacobi iteration run to its fixed point."""
+    v, f = meshgen.icosphere(5)
+    v = meshgen.harmonic_displacement(v, seed=3)
+    topo, K, A, t = _setup(v, f, m=m)
+    M = diffusion.heat_matrix(K, A, t)
+    lg = diffusion.solve_log_gauge(M, [0], diffusion.gauge_potential(M, v, topo.edges, t, [0]))
+    lj = _jacobi_longdouble(K, A, t, [0], 400 if m < 1e-3 else 1500)
+    if m < 1e-3:
+        assert lg.min() < -745
+    assert np.abs(lg - lj).max() < 1e-9 * np.abs(lj).max()
+
+
+def test_gauge_route_mass_conservation_and_symmetry():
+    """1^T K = 0 gives sum_j A_j u_j = number of sources; the Green's function
+    of the symmetric M is symmetric, u^(a)_b = u^(b)_a, although the two
+    solves use different potentials psi."""
+    v, f = meshgen.icosphere(4)
+    v = meshgen.harmonic_displacement(v, seed=9)
+    topo, K, A, t = _setup(v, f)
+    M = diffusion.heat_matrix(K, A, t)
+    a, b = 3, 1999
+    la = diffusion.solve_log_gauge(M, [a], diffusion.gauge_potential(M, v, topo.edges, t, [a]))
+    lb = diffusion.solve_log_gauge(M, [b], diffusion.gauge_potential(M, v, topo.edges, t, [b]))
+    lab = diffusion.solve_log_gauge(M, [a, b], diffusion.gauge_potential(M, v, topo.edges, t, [a, b]))
+    assert abs(np.sum(A * np.exp(la)) - 1.0) < 1e-12
+    assert abs(np.sum(A * np.exp(lab)) - 2.0) < 1e-12
+    assert abs(la[b] - lb[a]) < 1e-11
+    # linearity: u^(a,b) = u^(a) + u^(b)
+    assert np.abs(np.log(np.exp(la - lab) + np.exp(lb - lab))).max() < 1e-12
+
+
+def test_gauge_route_refuses_a_potential_that_underflows():
+    """psi = 0 leaves v = u, which underflows at m = 1e-4: the solve raises
+    instead of returning zeros."""
+    v, f = meshgen.icosphere(5)
+    topo, K, A, t = _setup(v, f, m=1e-4)
+    M = diffusion.heat_matrix(K, A, t)
+    with pytest.raises(RuntimeError):
+        diffusion.solve_log_gauge(M, [0], np.zeros(v.shape[0]))
+
+
+# ---------------------------------------------------- multigrid CG Poisson
+@pytest.fixture(scope="module")
+def bumpy6_field():
+    v, f = meshgen.icosphere(6)
+    v = meshgen.harmonic_displacement(v, seed=3)
+    src = meshgen.random_sources(v.shape[0], 8, seed=11)
+    r = pipeline.heat_method(v, f, src[:1], form="edge")
+    return v, f, src, r
+
+
+def test_subdivision_prolongations_rebuild_the_hierarchy():
+    """The prolongations recovered from the finest adjacency are those of the
+    generator's 1->4 subdivision: coarse vertices copy, every midpoint
+    averages the two ends of the coarse edge it splits, which are the edges
+    of the coarser icosphere."""
+    from oracle import multigrid
+    v5, f5 = meshgen.icosphere(5)
+    v4, f4 = meshgen.icosphere(4)
+    topo5 = mesh.build_topology(f5, v5.shape[0])
+    rp, col = mesh.vertex_adjacency(v5.shape[0], topo5.edges)
+    Ps = multigrid.subdivision_prolongations(v5.shape[0], rp, col)
+    assert [P.shape for P in Ps] == [(10242, 2562), (2562, 642)]
+    P = Ps[0]
+    assert np.allclose(P.sum(axis=1), 1.0)
+    # unnormalised midpoints of the level-4 positions point along the
+    # level-5 midpoints (the generator projects them to the sphere)
+    mid = P @ v4
+    cos = np.einsum("ij,ij->i", mid, v5) / np.linalg.norm(mid, axis=1)
+    assert np.all(cos > 1 - 1e-12)
+    # parent pairs are exactly the level-4 edges
+    topo4 = mesh.build_topology(f4, v4.shape[0])
+    C = P.tocoo()
+    keep = (C.row >= 2562)
+    pairs = np.sort(C.col[keep].reshape(-1, 2), axis=1)
+    got = np.unique(pairs[:, 0] * 2562 + pairs[:, 1])
+    ref = np.unique(topo4.edges[:, 0] * 2562 + topo4.edges[:, 1])
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("form", ["edge", "face"])
+@pytest.mark.parametrize("nsrc", [1, 8])
+def test_multigrid_cg_matches_sparse_lu(bumpy6_field, form, nsrc):
+    """Both Poisson systems, Dirichlet at 1 and 8 sources: the multigrid-
+    preconditioned CG of the large meshes equals the sparse LU solve."""
+    from oracle import multigrid
+    v, f, src, r = bumpy6_field
+    s = src[:nsrc]
+    topo = r.topo
+    if form == "edge":
+        L, b = poisson.edge_system(v, f, topo, r.h)
+    else:
+        L, b = assembly.cotan_stiffness(v, f), poisson.face_rhs(v, f, r.h)
+    d_lu = poisson.dirichlet_solve(L, b, s)
+    rp, col = mesh.vertex_adjacency(v.shape[0], topo.edges)
+    Ps = multigrid.subdivision_prolongations(v.shape[0], rp, col)
+    assert len(Ps) == 3
+    d_mg, it, res = multigrid.dirichlet_solve_mg(L, b, s, Ps)
+    assert res <= 1e-9 and it < 60
+    assert np.abs(d_mg - d_lu).max() <= 1e-10 * d_lu.max()
+
+
+def test_pcg_raises_when_not_converged(bumpy6_field):
+    from oracle import multigrid
+    v, f, src, r = bumpy6_field
+    L, b = poisson.edge_system(v, f, r.topo, r.h)
+    with pytest.raises(multigrid.NotConverged):
+        multigrid.dirichlet_solve_mg(L, b, src[:1], [], rtol=1e-10)   # Jacobi-CG, 500 iterations
+
+
+def test_pipeline_large_mesh_path_equals_small_mesh_path(monkeypatch):
+    """The whole pipeline with its large-mesh routes (banded diffusion,
+    multigrid CG) forced on a level-5 mesh equals the small-mesh routes
+    (gauge-scaled LU, sparse LU)."""
+    v, f = meshgen.icosphere(5)
+    v = meshgen.harmonic_displacement(v, seed=3)
+    src = meshgen.random_sources(v.shape[0], 3, seed=5)
+    small = {form: pipeline.heat_method(v, f, src, form=form) for form in ("edge", "face")}
+    monkeypatch.setattr(pipeline, "MG_MIN_V", 0)
+    for form in ("edge", "face"):
+        big = pipeline.heat_method(v, f, src, form=form, diffusion_route="bands")
+        assert big.poisson_iters > 0 and small[form].poisson_iters == 0
+        assert big.diffusion_route == "bands" and small[form].diffusion_route == "gauge"
+        assert np.abs(big.logu - small[form].logu).max() < 1e-9 * np.abs(small[form].logu).max()
+        assert np.abs(big.d - small[form].d).max() <= 1e-10 * small[form].d.max()
