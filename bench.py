@@ -11,8 +11,8 @@ in HBM before timing starts.
 Prints one JSON line.  `value` = solves per second; the roofline object is
 for the dominant kernel, its average duration measured with HIP events on
 the solve's stream during the timed steps; `cpu_baseline` times the CPU
-oracle on a bounded sample (a smaller mesh of the same family) and scales
-it to the workload by vertex count.
+oracle on a bounded sample (two smaller meshes of the same family, levels 7
+and 8) and scales it to the workload with the growth measured between them.
 """
 from __future__ import annotations
 
@@ -68,21 +68,41 @@ def _measured_traffic(kernel: str, per: str = "launch"):
     return rec.get("bytes_per_" + per)
 
 
-def cpu_baseline(sample_level: int, full_nv: int):
-    """The oracle (FP64 heat method, edge-form Poisson) on a smaller mesh of
-    the same family; solves/s scaled to the full vertex count linearly (a
-    generous bound: the oracle's sparse LU grows faster than linearly)."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(levels, full_nv: int):
+    """The oracle as it stands (FP64 banded-LU diffusion, edge-form Poisson by
+    multigrid CG, single-threaded scipy) timed on this host on displaced
+    icospheres of two smaller levels.  The value is solves/s of the full
+    workload, from the larger level's measured time and the growth exponent
+    measured between the two levels, T ~ V^k (k >= 1)."""
     from oracle import pipeline
-    v, f, s = _mesh(sample_level, None)
-    t0 = time.perf_counter()
-    pipeline.heat_method(v, f, s, form="edge")
-    dt = time.perf_counter() - t0
-    scaled = dt * full_nv / v.shape[0]
-    return {"value": 1.0 / scaled, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full oracle solve (FP64 sparse LU diffusion + edge Poisson) on the "
-                      f"level-{sample_level} displaced icosphere ({v.shape[0]} vertices) took "
-                      f"{dt:.2f} s; scaled x{full_nv / v.shape[0]:.0f} by vertex count",
-            "sample_seconds": dt}
+    times, sizes = [], []
+    for lvl in levels:
+        v, f, s = _mesh(lvl, None)
+        t0 = time.perf_counter()
+        pipeline.heat_method(v, f, s, form="edge", diffusion_route="bands")
+        times.append(time.perf_counter() - t0)
+        sizes.append(v.shape[0])
+        print(f"[bench] oracle level {lvl} ({v.shape[0]} vertices): {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    k = max(1.0, float(np.log(times[-1] / times[0]) / np.log(sizes[-1] / sizes[0]))) if len(levels) > 1 else 1.0
+    full_s = times[-1] * (full_nv / sizes[-1]) ** k
+    return {"value": 1.0 / full_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus_available": len(os.sched_getaffinity(0)),
+            "sample": (f"one full oracle solve (banded-LU FP64 diffusion, edge Poisson by multigrid CG, one "
+                       f"thread) on displaced icospheres of levels {', '.join(map(str, levels))} "
+                       f"({', '.join(map(str, sizes))} vertices): "
+                       f"{', '.join(f'{x:.2f}' for x in times)} s; scaled to {full_nv} vertices as "
+                       f"T ~ V^{k:.2f} from the two measured points"),
+            "measured_s": dict(zip(map(str, levels), times)), "growth_exponent": k}
 
 
 def main():
@@ -93,7 +113,8 @@ def main():
     ap.add_argument("--level", type=int, default=10)
     ap.add_argument("--form", default="edge", choices=["edge", "face"])
     ap.add_argument("--cache", default=os.environ.get("HGEO_MESH_CACHE", "/tmp/hgeo_mesh_cache"))
-    ap.add_argument("--cpu-sample-level", type=int, default=7)
+    ap.add_argument("--cpu-sample-levels", default="7,8",
+                    help="icosphere levels the oracle is timed on for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default diffusion schedule instead of tuning it on the first query")
@@ -146,11 +167,12 @@ def main():
         t0 = time.perf_counter()
         tune = mesh.autotune(src, 0.0, opts)
         ch = tune["candidates"][tune["chosen"]]
+        def label(c):
+            return {1: "jacobi", 2: f"tiles/{c['inner_sweeps']}",
+                    3: f"overlap-tiles/{c['inner_sweeps']}"}.get(c["schedule"], "?")
         print(f"[bench] autotune ({time.perf_counter() - t0:.1f}s): " +
-              ", ".join(f"{'tiles/' + str(c['inner_sweeps']) if c['schedule'] == 2 else 'jacobi'}="
-                        f"{c['ms']:.0f}ms" for c in tune["candidates"]) +
-              f" -> {'tiles/' + str(ch['inner_sweeps']) if ch['schedule'] == 2 else 'jacobi'}",
-              file=sys.stderr, flush=True)
+              ", ".join(f"{label(c)}={c['ms']:.0f}ms ({c['passes']} passes)" for c in tune["candidates"]) +
+              f" -> {label(ch)}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         _, info = mesh.solve(src, 0.0, opts, out=out)
@@ -244,7 +266,7 @@ def main():
                                               log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(args.cpu_sample_level, v.shape[0])
+        result["cpu_baseline"] = cpu_baseline([int(x) for x in args.cpu_sample_levels.split(",")], v.shape[0])
     print(json.dumps(result), flush=True)
 
 

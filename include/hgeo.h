@@ -81,7 +81,11 @@ typedef struct {
                                in the ADMM step entry points */
     int32_t check_every;    /* iterations between convergence checks; 32 */
     int32_t diffusion_schedule; /* 0 = auto, 1 = global Jacobi sweeps,
-                                   2 = LDS-tiled patch sweeps */
+                                   2 = LDS-tiled patch sweeps, 3 = LDS
+                                   tiles that also sweep overlap_rings
+                                   rings of vertices around their own (an
+                                   overlapping Schwarz iteration: the same
+                                   fixed point in fewer passes) */
     int32_t inner_sweeps;   /* patch schedule: sweeps per global pass; 0 = auto */
     double relax;           /* ADMM over-relaxation alpha in (0, 2); default
                                1.9 (measured: 4-21% fewer edge-form
@@ -138,7 +142,8 @@ typedef struct {
                                launches of k and one launch of the rest, so
                                the result, the iteration count included, is
                                the same for every k.  0 = auto (default, 6) */
-    int32_t reserved[1];
+    int32_t overlap_rings;  /* schedule 3: rings of overlap around each tile,
+                               1..4; 0 = auto (2) */
 } hg_opts;
 
 /* Per-solve report. */
@@ -272,6 +277,42 @@ hg_status hg_geodesic_solve(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, do
                             const hg_opts* opts, float* d_dev, void* stream, hg_info* info);
 
 /*
+ * Queries on several resident meshes in one solve (Algorithm 1 once for all
+ * of them; a source list per mesh as in Sec. 5.2): query i runs on meshes[i]
+ * from the HOST int32 source ids src[i][0 .. nsrc[i]) (its own vertex ids)
+ * and writes DEVICE float32[nv of meshes[i]] d_dev[i].  The meshes are joined
+ * on the device as the connected components of one mesh (their arrays
+ * concatenated with shifted indices; nothing is rebuilt on the host), so
+ * every step of the path runs one launch sequence for the whole batch.  Each
+ * member diffuses with its own t = m hbar_i^2 when t <= 0 (t > 0 applies to
+ * all), its breadth-first sets, tiles and source paths stay inside it, and
+ * it gets the distance it has alone, to the solve's tolerances (the ADMM
+ * stopping rule and the automatic penalty see the whole batch).  opts as in
+ * hg_geodesic_solve (t_per_component is set by the call); info reports the
+ * batch solve.  The join is kept for the next batch over the same meshes in
+ * the same order (it holds a copy of their device arrays plus a workspace,
+ * about as much as the members' own), and is freed when a batch over other
+ * meshes is run or one of its members is destroyed.  A mesh may appear more
+ * than once.  All meshes must live on the current device and be all
+ * extrinsic or all intrinsic (HG_E_INVALID_ARG).  Batch calls are serialised
+ * by the library.  Returns HG_E_NOT_CONVERGED (results written) if a cap was
+ * hit.
+ */
+hg_status hg_geodesic_solve_batch(const hg_mesh_t* meshes, int32_t nq, const int32_t* const* src,
+                                  const int32_t* nsrc, double t, const hg_opts* opts, float* const* d_dev,
+                                  void* stream, hg_info* info);
+
+/* Device bytes held by a mesh (its arrays and the schedules built so far);
+ * 0 for NULL. */
+uint64_t hg_mesh_bytes(hg_mesh_t mesh);
+/* Upper estimate of the device bytes of one query's workspace on this mesh
+ * with nsrc sources in the form of opts (NULL: edge form): breadth-first
+ * sets, diffusion state, normalised field, ADMM state, integration and
+ * source-path buffers.  The serving runtime admits queries by this figure.
+ * 0 for NULL mesh, nsrc <= 0 or an unknown formulation. */
+uint64_t hg_query_bytes(hg_mesh_t mesh, int32_t nsrc, const hg_opts* opts);
+
+/*
  * The generator loops of the cycle constraints (Sec. 5.1), built with the
  * mesh by a tree-cotree decomposition on the caller's ids: primal tree =
  * breadth-first tree from the smallest vertex of each component (parent =
@@ -344,6 +385,49 @@ hg_status hg_integrate_face(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
 /* Canonical edge list: DEVICE int32[ne*2] (smaller id, larger id). */
 hg_status hg_mesh_edges(hg_mesh_t mesh, int32_t* edges_dev, void* stream);
 
+/* ---- the comparator of Sec. 6.4: the original heat method by CG ----
+ *
+ * The paper sets its Gauss-Seidel diffusion and ADMM gradient solver against
+ * the original heat method with its direct solves replaced by conjugate
+ * gradients with a diagonal preconditioner, measuring the heat residual
+ * E_1 = |(A - t L_c) u - u_0|_2 (Eq. 29) and the distance error
+ * E_2 = |d - d*|_2 / n (Eq. 30) against time.  These entry points run that
+ * CG in FP64 on the device (x0 = 0, Jacobi preconditioner, the CG scalars
+ * kept on the device; deterministic reductions).  tol > 0: stop at relative
+ * residual |r|/|b| <= tol, checked every 16 iterations, HG_E_NOT_CONVERGED
+ * (result written) if max_iters is reached first; tol = 0: exactly
+ * max_iters iterations. */
+typedef struct {
+    int32_t iters;          /* CG iterations run */
+    int32_t converged;      /* 1 if the relative residual reached tol */
+    double res_rel;         /* final |r|_2 / |b|_2 (recursive residual) */
+    double res_abs;         /* final |r|_2 */
+    double res_abs0;        /* |b|_2 */
+    float ms;               /* device time of the iterations (HIP events) */
+    int32_t reserved[3];
+} hg_cg_info;
+
+/* CG on Eq. 4, (A - t L_c) u = u_0 with u_0 = 1 at the sources (HOST int32
+ * ids), t <= 0 meaning hbar^2.  u_dev = DEVICE float64[nv], plain u (it
+ * underflows to 0 where u is below the FP64 range; E_1 is absolute, so the
+ * paper's comparison is unaffected). */
+hg_status hg_cg_diffuse(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, int32_t max_iters,
+                        double tol, double* u_dev, void* stream, hg_cg_info* info);
+/* CG on the Poisson step with d = 0 at every source (the paper fixes the
+ * source values to make the system definite) from the DEVICE float32[nf*3]
+ * normalised field h_dev (caller face order): form HG_FORM_FACE solves
+ * K d = r with r_i = sum_f A_f grad phi_i|_f . h_f (Sec. 3.2, the face
+ * ADMM's converged answer); HG_FORM_EDGE solves L_E d = b_E (edge weight
+ * |H_e|, b_E,i = sum_{f ni i} h_f . (2 p_i - p_j - p_k); the edge ADMM's).
+ * d_dev = DEVICE float64[nv]; +inf where no source reaches.  Extrinsic
+ * meshes only (HG_E_INVALID_ARG for an intrinsic one). */
+hg_status hg_cg_poisson(hg_mesh_t mesh, int32_t form, const float* h_dev, const int32_t* src, int32_t nsrc,
+                        int32_t max_iters, double tol, double* d_dev, void* stream, hg_cg_info* info);
+/* E_1 of Eq. 29 for the DEVICE float64[nv] field u_dev (is_log = 1: it holds
+ * log u, as hg_diffuse writes it), t <= 0 meaning hbar^2; *e1 on the host. */
+hg_status hg_heat_residual(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const double* u_dev,
+                           int32_t is_log, double* e1, void* stream);
+
 /* ---- serving: concurrent queries over resident meshes ----
  *
  * A server runs queries on n_slots worker threads, each with its own HIP
@@ -354,10 +438,13 @@ hg_status hg_mesh_edges(hg_mesh_t mesh, int32_t* edges_dev, void* stream);
  * that arrive while others run start as soon as a slot and memory allow and
  * overlap with them on the device.  Admission by device memory: query
  * workspaces are pooled per mesh and reused; a new one is created only while
- * the workspaces held stay within workspace_budget bytes (0 = half of the
- * free device memory at creation), releasing idle workspaces of other meshes
- * for the oldest waiting query; with nothing running the oldest query is
- * always admitted.  Meshes, source arrays' contents (copied at submit) and
+ * the bytes held stay within workspace_budget (0 = half of the free device
+ * memory at creation), releasing idle workspaces of other meshes for the
+ * oldest waiting query; with nothing running the oldest query is always
+ * admitted.  The bytes held count each workspace at the larger of its
+ * admission estimate (hg_query_bytes) and its size after its last query,
+ * plus the schedules served queries added to their meshes (face tiles of
+ * the blocked edge ADMM, the face form's slot geometry).  Meshes, source arrays' contents (copied at submit) and
  * the output buffers must stay valid until the query's result is taken. */
 typedef struct hg_server_s* hg_server_t;
 
@@ -396,7 +483,8 @@ void hg_server_destroy(hg_server_t server);
 typedef struct {
     int32_t n_candidates;
     int32_t chosen;              /* index into the arrays below */
-    int32_t schedule[8];         /* 1 = global Jacobi sweeps, 2 = LDS tiles */
+    int32_t schedule[8];         /* 1 = global Jacobi sweeps, 2 = LDS tiles,
+                                    3 = overlapping LDS tiles */
     int32_t inner_sweeps[8];     /* sweeps per tile pass (0 for Jacobi) */
     float ms[8];                 /* time of the diffusion stage (converged) */
     int32_t passes[8];
@@ -404,8 +492,9 @@ typedef struct {
 } hg_tune_report;
 
 /* Times the diffusion stage of a probe query (src/nsrc, t, opts as in
- * hg_geodesic_solve) once per candidate schedule -- LDS tiles with 8, 16, 32,
- * 48 and 64 in-tile sweeps per pass, and global Jacobi sweeps on meshes of at
+ * hg_geodesic_solve) once per candidate schedule -- LDS tiles with 16, 32
+ * and 64 in-tile sweeps per pass, overlapping LDS tiles (opts->overlap_rings,
+ * default 2) with 16, 32 and 64, and global Jacobi sweeps on meshes of at
  * most 16 tiles -- on the mesh's default workspace and stream, and stores
  * the fastest one that converges in the mesh: later queries whose
  * diffusion_schedule / inner_sweeps options are 0 (auto) use it.  The

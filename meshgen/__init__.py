@@ -39,6 +39,7 @@ __all__ = [
     "harmonic_displacement",
     "random_sources",
     "config_mesh",
+    "batch_meshes",
 ]
 
 
@@ -288,6 +289,24 @@ def disjoint_union(parts, shift=3.0):
         starts.append(n)
         n += v.shape[0]
     return np.vstack(vs), np.vstack(fs).astype(np.int32), starts
+
+
+def batch_meshes(n: int = 256, levels=(3, 6), seed: int = 4):
+    """The many-small-meshes workload: n displaced icospheres whose levels
+    are drawn uniformly from `levels` (seed), mesh i displaced with seed
+    1000 + i and given one source drawn with seed 2000 + i.  Returns
+    (list of (verts, tris), list of source arrays)."""
+    rng = np.random.default_rng(seed)
+    base = {}
+    out = []
+    for i in range(n):
+        L = int(rng.integers(levels[0], levels[1] + 1))
+        if L not in base:
+            base[L] = icosphere(L)
+        v, f = base[L]
+        out.append((harmonic_displacement(v, seed=1000 + i), f))
+    src = [random_sources(v.shape[0], 1, seed=2000 + i) for i, (v, _) in enumerate(out)]
+    return out, src
 
 
 # --------------------------------------------------------------------------

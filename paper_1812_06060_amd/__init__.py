@@ -15,4 +15,5 @@ from ._hgeo import (  # noqa: F401
     Server,
     default_opts,
     load_library,
+    solve_batch,
 )

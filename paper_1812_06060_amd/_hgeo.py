@@ -39,7 +39,7 @@ class Opts(C.Structure):
         ("mu", C.c_double), ("check_every", C.c_int32), ("diffusion_schedule", C.c_int32),
         ("inner_sweeps", C.c_int32), ("relax", C.c_double), ("source_paths", C.c_int32),
         ("t_per_component", C.c_int32), ("use_graphs", C.c_int32), ("cycle_constraints", C.c_int32),
-        ("tol_seam", C.c_double), ("admm_block", C.c_int32), ("reserved", C.c_int32 * 1),
+        ("tol_seam", C.c_double), ("admm_block", C.c_int32), ("overlap_rings", C.c_int32),
     ]
 
 
@@ -97,6 +97,14 @@ class TuneReport(C.Structure):
     ]
 
 
+class CgInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("res_rel", C.c_double), ("res_abs", C.c_double),
+                ("res_abs0", C.c_double), ("ms", C.c_float), ("reserved", C.c_int32 * 3)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 # (name, argtypes)
 _P = C.c_void_p
 _API = {
@@ -107,6 +115,12 @@ _API = {
     "hg_mesh_destroy": [_P],
     "hg_mesh_get_stats": [_P, C.POINTER(MeshStats)],
     "hg_geodesic_solve": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_geodesic_solve_batch": [_P, C.c_int32, _P, _P, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
+    "hg_mesh_bytes": [_P],
+    "hg_cg_diffuse": [_P, _P, C.c_int32, C.c_double, C.c_int32, C.c_double, _P, _P, C.POINTER(CgInfo)],
+    "hg_cg_poisson": [_P, C.c_int32, _P, _P, C.c_int32, C.c_int32, C.c_double, _P, _P, C.POINTER(CgInfo)],
+    "hg_heat_residual": [_P, _P, C.c_int32, C.c_double, _P, C.c_int32, C.POINTER(C.c_double), _P],
+    "hg_query_bytes": [_P, C.c_int32, C.POINTER(Opts)],
     "hg_bfs": [_P, _P, C.c_int32, _P, _P, _P, C.POINTER(C.c_int32)],
     "hg_diffuse": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
     "hg_normalize": [_P, _P, _P, _P],
@@ -147,6 +161,8 @@ def load_library(path: str = LIB_PATH):
             fn.restype = None
         elif name == "hg_server_clock":
             fn.restype = C.c_double
+        elif name in ("hg_mesh_bytes", "hg_query_bytes"):
+            fn.restype = C.c_uint64
         else:
             fn.restype = C.c_int
     if path == LIB_PATH:
@@ -271,6 +287,51 @@ class Mesh:
             _check(st)
         return out, SolveInfo(info.as_dict())
 
+    # ------------------------------------------- Sec. 6.4 comparator (CG)
+    def cg_diffuse(self, sources, t: float = 0.0, max_iters: int = 100000, tol: float = 1e-12, stream=None,
+                   raise_on_nonconvergence: bool = True):
+        """Jacobi-preconditioned CG on Eq. 4 (hg_cg_diffuse): (float64 u, info)."""
+        torch = _torch()
+        u = torch.empty(self.nv, dtype=torch.float64, device="cuda")
+        a, p, n = _src_array(sources)
+        info = CgInfo()
+        st = _lib.hg_cg_diffuse(self._h, p, n, float(t), int(max_iters), float(tol),
+                                _dptr(u, torch.float64, self.nv), _stream(stream), C.byref(info))
+        if st != HG_E_NOT_CONVERGED or raise_on_nonconvergence:
+            _check(st)
+        return u, info.as_dict()
+
+    def cg_poisson(self, h, sources, form: str = "face", max_iters: int = 100000, tol: float = 1e-12,
+                   stream=None, raise_on_nonconvergence: bool = True):
+        """Jacobi-preconditioned CG on the Poisson step with d = 0 at the
+        sources (hg_cg_poisson), from float32 h [nf*3]: (float64 d, info)."""
+        torch = _torch()
+        d = torch.empty(self.nv, dtype=torch.float64, device="cuda")
+        a, p, n = _src_array(sources)
+        fm = {"face": FORM_FACE, "edge": FORM_EDGE}[form]
+        info = CgInfo()
+        st = _lib.hg_cg_poisson(self._h, fm, _dptr(h, torch.float32, 3 * self.nf), p, n, int(max_iters),
+                                float(tol), _dptr(d, torch.float64, self.nv), _stream(stream), C.byref(info))
+        if st != HG_E_NOT_CONVERGED or raise_on_nonconvergence:
+            _check(st)
+        return d, info.as_dict()
+
+    def heat_residual(self, sources, u, t: float = 0.0, is_log: bool = False, stream=None) -> float:
+        """E_1 = |(A - t L_c) u - u_0|_2 of Eq. 29 (hg_heat_residual)."""
+        torch = _torch()
+        a, p, n = _src_array(sources)
+        e1 = C.c_double()
+        _check(_lib.hg_heat_residual(self._h, p, n, float(t), _dptr(u, torch.float64, self.nv),
+                                     1 if is_log else 0, C.byref(e1), _stream(stream)))
+        return e1.value
+
+    def mesh_bytes(self) -> int:
+        return int(_lib.hg_mesh_bytes(self._h))
+
+    def query_bytes(self, nsrc: int, opts: Opts | None = None) -> int:
+        """Upper estimate of one query's workspace bytes (hg_query_bytes)."""
+        return int(_lib.hg_query_bytes(self._h, int(nsrc), C.byref(opts) if opts else None))
+
     def autotune(self, sources, t: float = 0.0, opts: Opts | None = None, stream=None) -> dict:
         """Pick the fastest diffusion schedule for this mesh on a probe query
         (hg_mesh_autotune); later solves with automatic options use it."""
@@ -386,6 +447,30 @@ class Mesh:
         _check(_lib.hg_integrate_face(self._h, p, n, _dptr(g, torch.float32, 3 * self.nf),
                                       _dptr(d, torch.float32, self.nv), _stream(stream)))
         return d
+
+
+def solve_batch(meshes, sources, t: float = 0.0, opts: Opts | None = None, outs=None, stream=None,
+                raise_on_nonconvergence: bool = True):
+    """One solve over several resident meshes (hg_geodesic_solve_batch):
+    query i on meshes[i] from sources[i] (its own vertex ids).  Returns (list
+    of float32 device tensors, one per mesh, SolveInfo of the batch)."""
+    torch = _torch()
+    n = len(meshes)
+    if n == 0 or len(sources) != n:
+        raise ValueError("one source list per mesh expected")
+    if outs is None:
+        outs = [torch.empty(m.nv, dtype=torch.float32, device="cuda") for m in meshes]
+    arrs = [np.ascontiguousarray(np.atleast_1d(np.asarray(s, dtype=np.int32))) for s in sources]
+    hs = (C.c_void_p * n)(*[m._h for m in meshes])
+    sp = (C.c_void_p * n)(*[a.ctypes.data for a in arrs])
+    ns = (C.c_int32 * n)(*[a.size for a in arrs])
+    dp = (C.c_void_p * n)(*[_dptr(o, torch.float32, m.nv).value for o, m in zip(outs, meshes)])
+    info = Info()
+    st = _lib.hg_geodesic_solve_batch(hs, n, sp, ns, float(t), C.byref(opts) if opts else None, dp,
+                                      _stream(stream), C.byref(info))
+    if st != HG_E_NOT_CONVERGED or raise_on_nonconvergence:
+        _check(st)
+    return outs, SolveInfo(info.as_dict())
 
 
 class Server:

@@ -1,7 +1,7 @@
 """Batch benchmark: 256 independent small meshes (displaced icospheres of
 levels 3-6, sizes drawn uniformly, seed 4; mesh i displaced with seed
 1000 + i; one source each, seed 2000 + i), answered by one batched solve
-(all meshes as components of one resident mesh: one launch per step for
+over the resident meshes (hg_geodesic_solve_batch: one launch per step for
 all of them) against one solve per mesh.  Both are the same method; the
 largest difference between the two answers is reported relative to each
 mesh's diameter.
@@ -20,17 +20,7 @@ import numpy as np
 
 def make_meshes(n: int, levels=(3, 6), seed: int = 4):
     import meshgen
-    rng = np.random.default_rng(seed)
-    base = {}
-    out = []
-    for i in range(n):
-        L = int(rng.integers(levels[0], levels[1] + 1))
-        if L not in base:
-            base[L] = meshgen.icosphere(L)
-        v, f = base[L]
-        out.append((meshgen.harmonic_displacement(v, seed=1000 + i), f))
-    src = [meshgen.random_sources(v.shape[0], 1, seed=2000 + i) for i, (v, _) in enumerate(out)]
-    return out, src
+    return meshgen.batch_meshes(n, levels, seed)
 
 
 def run(n_meshes: int = 256, form: str = "edge", reps: int = 3, log=print):
@@ -54,7 +44,7 @@ def run(n_meshes: int = 256, form: str = "edge", reps: int = 3, log=print):
     batched = [d.cpu().numpy() for d in ds]
     log(f"[batch] {n_meshes} meshes ({nv} vertices) in one solve: {1e3 * min(tb):.1f} ms "
         f"(passes {info.passes}, admm {info.admm_iters})")
-    singles = [hg.Mesh(v, f) for v, f in meshes]
+    singles = b.meshes   # the same resident meshes, one solve each
     for m, s in zip(singles, src):
         m.solve(s, 0.0, opts)
     torch.cuda.synchronize()
@@ -70,8 +60,6 @@ def run(n_meshes: int = 256, form: str = "edge", reps: int = 3, log=print):
         a = a.cpu().numpy()
         worst = max(worst, float(np.abs(a - bb).max() / a.max()))
     log(f"[batch] one solve per mesh: {1e3 * ts:.1f} ms; largest batched-vs-alone difference {worst:.2e} of the diameter")
-    for m in singles:
-        m.close()
     b.close()
     return {"meshes": n_meshes, "vertices": nv, "form": form,
             "batched": {"ms": 1e3 * min(tb), "meshes_per_s": n_meshes / min(tb),
@@ -118,7 +106,6 @@ def run_fields(n_fields: int = 64, slots: int = 8, log=print, batched: bool = Fa
     same = all(np.array_equal(o.cpu().numpy(), r) for o, r in zip(outs, ref))
     log(f"[fields] {len(src)} single-source fields on L9: one at a time {t_seq:.2f} s, "
         f"{slots}-slot server {t_srv:.2f} s, identical {same}")
-    mesh.close()
     out = {"fields": len(src), "vertices": int(v.shape[0]), "slots": slots,
            "one_at_a_time": {"s": t_seq, "fields_per_s": len(src) / t_seq},
            "served": {"s": t_srv, "fields_per_s": len(src) / t_srv}, "results_identical": same}
@@ -129,9 +116,9 @@ def run_fields(n_fields: int = 64, slots: int = 8, log=print, batched: bool = Fa
         # mesh data is duplicated per field)
         from .batch import MeshBatch
         t0 = time.perf_counter()
-        b = MeshBatch([(v, f)] * len(src))
-        log(f"[fields] batch of {len(src)} mesh instances built in {time.perf_counter() - t0:.1f} s "
-            f"({b.mesh.stats['mesh_bytes'] / 1e9:.1f} GB)")
+        b = MeshBatch([mesh] * len(src))
+        log(f"[fields] batch of {len(src)} instances of the resident mesh "
+            f"({len(src) * mesh.mesh_bytes() / 1e9:.1f} GB joined)")
         srcs = [[int(x)] for x in src]
         ds, info = b.solve(srcs, opts=hg.default_opts())
         torch.cuda.synchronize()
@@ -143,9 +130,10 @@ def run_fields(n_fields: int = 64, slots: int = 8, log=print, batched: bool = Fa
         log(f"[fields] one batched solve: {t_b:.2f} s (passes {info.passes}, ADMM {info.admm_iters}); "
             f"largest difference from the fields alone {worst:.2e} of the diameter")
         out["batched"] = {"s": t_b, "fields_per_s": len(src) / t_b, "passes": info.passes,
-                          "admm_iters": info.admm_iters, "mesh_bytes": int(b.mesh.stats["mesh_bytes"]),
+                          "admm_iters": info.admm_iters, "mesh_bytes": int(len(src) * mesh.mesh_bytes()),
                           "max_diff_vs_alone_over_diam": worst}
         b.close()
+    mesh.close()
     return out
 
 

@@ -27,6 +27,9 @@ SOURCES = [
     "kernels_patch.hip",
     "kernels_paths.hip",
     "server.cpp",
+    "batch.cpp",
+    "kernels_cg.hip",
+    "overlap_tiles.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -13,13 +13,14 @@
 namespace hg {
 
 static thread_local std::string g_last_error;
+std::string& last_error_ref() { return g_last_error; }
 
 size_t Work::bytes() const {
     return level.bytes() + parent.bytes() + pslot.bytes() + frontier_a.bytes() + frontier_b.bytes() +
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
            h.bytes() + sumz.bytes() + sumd.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
-           src.bytes() + dprev.bytes() + paths.bytes() + tcomp.bytes() + tile_t.bytes();
+           src.bytes() + dprev.bytes() + paths.bytes() + tcomp.bytes() + tile_t.bytes() + cg.bytes();
 }
 
 size_t Work::Paths::bytes() const {
@@ -39,6 +40,10 @@ uint64_t Mesh::mesh_bytes() const {
         std::lock_guard<std::mutex> lock(et_mu);
         for (const auto& t : etiles) blocked += t->f0.bytes() + t->rptr.bytes() + t->halo.bytes() + t->rec.bytes();
     }
+    {
+        std::lock_guard<std::mutex> lock(ot_mu);
+        for (const auto& t : otiles) blocked += t->bytes();
+    }
     return face_form + blocked + floc.bytes() + px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() +
@@ -48,28 +53,8 @@ uint64_t Mesh::mesh_bytes() const {
 
 Mesh::~Mesh() = default;
 
-static hg_status fail(hg_status code, const std::string& msg) {
-    g_last_error = msg;
-    return code;
-}
 
-template <class F>
-static hg_status guarded(F&& fn) {
-    try {
-        g_last_error.clear();
-        return fn();
-    } catch (const Error& e) {
-        return fail(e.code, e.msg);
-    } catch (const std::bad_alloc&) {
-        return fail(HG_E_OOM, "host allocation failed");
-    } catch (const std::exception& e) {
-        return fail(HG_E_DEVICE, e.what());
-    } catch (...) {
-        return fail(HG_E_DEVICE, "unknown error");
-    }
-}
-
-static std::vector<int32_t> map_sources(const Mesh& m, const int32_t* src, int32_t nsrc) {
+std::vector<int32_t> map_sources(const Mesh& m, const int32_t* src, int32_t nsrc) {
     if (!src || nsrc <= 0) throw Error{HG_E_INVALID_ARG, "empty source list"};
     std::vector<int32_t> out;
     out.reserve(nsrc);
@@ -98,6 +83,10 @@ static hg_opts resolve_opts(const hg_opts* o) {
     if (r.admm_block < 0 || r.admm_block > kMaxAdmmBlock)
         throw Error{HG_E_INVALID_ARG, "admm_block must lie in 0..8 (0 = auto)"};
     if (r.admm_block == 0) r.admm_block = kAutoAdmmBlock;
+    if (r.overlap_rings < 0 || r.overlap_rings > 4) throw Error{HG_E_INVALID_ARG, "overlap_rings must lie in 0..4"};
+    if (r.overlap_rings == 0) r.overlap_rings = kAutoOverlapRings;
+    if (r.diffusion_schedule < 0 || r.diffusion_schedule > 3)
+        throw Error{HG_E_INVALID_ARG, "diffusion_schedule must lie in 0..3"};
     if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
         throw Error{HG_E_INVALID_ARG, "iteration caps must be positive"};
     return r;
@@ -387,7 +376,20 @@ hg_status hg_mesh_intrinsic(hg_mesh_t mesh, int32_t* tri_out, double* length_out
     });
 }
 
-void hg_mesh_destroy(hg_mesh_t mesh) { delete reinterpret_cast<Mesh*>(mesh); }
+void hg_mesh_destroy(hg_mesh_t mesh) {
+    if (!mesh) return;
+    forget_joins_with(reinterpret_cast<Mesh*>(mesh));
+    delete reinterpret_cast<Mesh*>(mesh);
+}
+
+uint64_t hg_mesh_bytes(hg_mesh_t mesh) { return mesh ? reinterpret_cast<Mesh*>(mesh)->mesh_bytes() : 0; }
+
+uint64_t hg_query_bytes(hg_mesh_t mesh, int32_t nsrc, const hg_opts* opts) {
+    if (!mesh || nsrc <= 0) return 0;
+    const int form = opts ? opts->formulation : HG_FORM_EDGE;
+    if (form != HG_FORM_EDGE && form != HG_FORM_FACE) return 0;
+    return work_estimate(*reinterpret_cast<Mesh*>(mesh), form, nsrc);
+}
 
 hg_status hg_mesh_get_stats(hg_mesh_t mesh, hg_mesh_stats* st) {
     return guarded([&]() -> hg_status {
@@ -603,8 +605,10 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
         // candidate only on meshes of a few tiles (or without tiles)
         std::vector<Cand> cands;
         if (!patch_supported(*m) || m->n_patches <= 16) cands.push_back({1, 0});
-        if (patch_supported(*m))
-            for (int inner : {8, 16, 32, 48, 64}) cands.push_back({2, inner});
+        if (patch_supported(*m)) {
+            for (int inner : {16, 32, 64}) cands.push_back({2, inner});
+            for (int inner : {16, 32, 64}) cands.push_back({3, inner});
+        }
         hg_tune_report rep;
         std::memset(&rep, 0, sizeof(rep));
         rep.n_candidates = (int)cands.size();
@@ -621,7 +625,14 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
                 oc.diffusion_schedule = cands[i].sched;
                 oc.inner_sweeps = cands[i].inner;
                 HG_CHECK_HIP(hipEventRecord(a, s));
-                DiffusionResult dr = run_diffusion(*m, w, si, tt, oc, s);
+                DiffusionResult dr;
+                try {
+                    dr = run_diffusion(*m, w, si, tt, oc, s);
+                } catch (const Error& e) {
+                    // overlapping tiles that do not fit this mesh: not a candidate
+                    if (e.code != HG_E_INVALID_ARG || cands[i].sched != 3) throw;
+                    dr = DiffusionResult();
+                }
                 HG_CHECK_HIP(hipEventRecord(b, s));
                 HG_CHECK_HIP(hipEventSynchronize(b));
                 float ms = 0.f;

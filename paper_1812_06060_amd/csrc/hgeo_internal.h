@@ -15,6 +15,8 @@
 #include <cstdint>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -35,6 +37,29 @@ struct Error {
             throw ::hg::Error{_e == hipErrorOutOfMemory ? HG_E_OOM : HG_E_DEVICE,           \
                               std::string(#expr) + ": " + hipGetErrorString(_e)};           \
     } while (0)
+
+// The thread-local message behind hg_last_error (api.cpp).
+std::string& last_error_ref();
+inline hg_status fail(hg_status code, const std::string& msg) {
+    last_error_ref() = msg;
+    return code;
+}
+// Runs an entry point's body, converting exceptions to status codes.
+template <class F>
+hg_status guarded(F&& fn) {
+    try {
+        last_error_ref().clear();
+        return fn();
+    } catch (const Error& e) {
+        return fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(HG_E_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(HG_E_DEVICE, e.what());
+    } catch (...) {
+        return fail(HG_E_DEVICE, "unknown error");
+    }
+}
 
 // A device buffer owned by the library.
 template <class T>
@@ -155,6 +180,7 @@ void build_intrinsic(const double* xyz, int64_t nv, const int32_t* tri, int64_t 
 // away; rec[rptr[p] + r] is region face r's record (twin copies, signs).
 constexpr int kMaxAdmmBlock = 8;    // iterations per blocked launch at most
 constexpr int kAutoAdmmBlock = 6;   // hg_opts.admm_block = 0
+constexpr int kAutoOverlapRings = 2; // hg_opts.overlap_rings = 0
 constexpr uint32_t kTwinNone = 0xFFFF;   // boundary slot: no twin
 constexpr uint32_t kTwinOut = 0xFFFE;    // twin outside the region
 struct EdgeTiles {
@@ -167,6 +193,26 @@ struct EdgeTiles {
 bool build_edge_tiles(int64_t nf, const std::vector<int32_t>& tri, const std::vector<int32_t>& twin,
                       const std::vector<uint8_t>& fsign, const std::vector<int32_t>& tile_ptr, int rings,
                       int max_region, EdgeTiles& out);
+
+// Overlapping diffusion tiles (overlap_tiles.cpp): per tile, halo_idx holds
+// its n_ov overlap vertices (updated by the in-tile sweeps, never written
+// back) followed by the fixed outer ring; ELL rows of the core (stride P)
+// then of the overlap vertices (stride n_ov); colours such that no tile
+// reads the core of a tile of its own colour.
+struct OverlapTiles {
+    int rings = 0, max_halo = 0, max_ov = 0, max_ell_width = 0;
+    std::vector<int32_t> halo_ptr, halo_idx, n_ov, ell_ptr, color_ptr, tile_order;
+    std::vector<uint8_t> ell_width;
+    std::vector<uint16_t> lnb;
+};
+// A tile whose region with `rings` rings would exceed lds_budget bytes
+// (values, exponents and, per overlap vertex, lds_width coefficients and
+// slots) or max_ov overlap vertices gets fewer rings.  false if even the
+// plain halo leaves too many overlap vertices or the region does not fit
+// 16-bit local slots.
+bool build_overlap_tiles(const std::vector<int32_t>& row_ptr, const std::vector<int32_t>& col,
+                         const std::vector<int32_t>& tile_ptr, int P, int rings, int max_ov, OverlapTiles& out,
+                         size_t lds_budget = ~(size_t)0, int lds_width = 16);
 
 // Per-query device workspace.  A query runs on one Work and one stream; the
 // mesh data it reads is never written after mesh_create, so queries on the
@@ -213,6 +259,15 @@ struct Work {
     DBuf<double> red_host_dummy;
     double* pinned = nullptr;           // host pinned reduction results
     DBuf<int32_t> src;
+    // conjugate gradients of the Sec. 6.4 comparator (kernels_cg.hip)
+    struct Cg {
+        DBuf<double> x, r, z, p, q, D, b, partial, scal;
+        DBuf<uint8_t> fixed;
+        size_t bytes() const {
+            return x.bytes() + r.bytes() + z.bytes() + p.bytes() + q.bytes() + D.bytes() + b.bytes() +
+                   partial.bytes() + scal.bytes() + fixed.bytes();
+        }
+    } cg;
     // source paths of the multi-source constraints (Eqs. 24-25), built by
     // build_source_paths: np paths over ns slots, slots grouped by edge
     // and by face (CSR over the distinct ids, slots in increasing order)
@@ -273,6 +328,23 @@ struct Mesh {
     };
     std::vector<std::unique_ptr<EdgeTileSet>> etiles;
     mutable std::mutex et_mu;
+    // diffusion tiles with `rings` rings of overlap (OverlapTiles on the
+    // device), one set per depth used, built on first use and kept
+    struct OverlapTileSet {
+        int rings = 0, max_halo = 0, max_ov = 0, max_ell_width = 0;
+        bool ok = false;
+        DBuf<int32_t> halo_ptr, halo_idx, n_ov, ell_ptr, tile_order;
+        DBuf<uint8_t> ell_width;
+        DBuf<uint16_t> lnb;
+        DBuf<double> theta_ell;
+        std::vector<int32_t> color_ptr_host;
+        size_t bytes() const {
+            return halo_ptr.bytes() + halo_idx.bytes() + n_ov.bytes() + ell_ptr.bytes() + tile_order.bytes() +
+                   ell_width.bytes() + lnb.bytes() + theta_ell.bytes();
+        }
+    };
+    std::vector<std::unique_ptr<OverlapTileSet>> otiles;
+    mutable std::mutex ot_mu;
 
     // patch tiles
     int patch_size = 0, n_patches = 0, max_halo = 0, max_ell_width = 0;
@@ -316,6 +388,10 @@ struct Mesh {
     // the blocked edge-ADMM tiles for `rings` (nullptr if the mesh's regions
     // do not fit in LDS)
     const EdgeTileSet* ensure_edge_tiles(int rings, hipStream_t s);
+    // the overlapping diffusion tiles for `rings` (nullptr if a tile has more
+    // than max_ov overlap vertices)
+    const OverlapTileSet* ensure_overlap_tiles(int rings, int max_ov, size_t lds_budget, int lds_width,
+                                               hipStream_t s);
     ~Mesh();
 };
 
@@ -323,6 +399,14 @@ struct Mesh {
 // elen: per internal edge length (intrinsic meshes; positions otherwise)
 void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen = nullptr);
 int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s);
+// The breadth-first search on caller-provided device buffers: level, parent,
+// pslot, frontier_a, frontier_b [nv] each, counters [8], src [nsrc].
+struct BfsBuffers {
+    int32_t *level, *parent, *pslot, *frontier_a, *frontier_b, *counters, *src;
+};
+int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src_internal, hipStream_t s);
+// caller id -> internal id of each source, checked (throws HG_E_INVALID_ARG)
+std::vector<int32_t> map_sources(const Mesh& m, const int32_t* src, int32_t nsrc);
 struct DiffusionResult {
     int sweeps = 0, passes = 0;
     double res = 0.0;
@@ -337,8 +421,10 @@ DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src_
                               const hg_opts& o, hipStream_t s);
 void diffusion_logu(Mesh& m, Work& w, hipStream_t s);                   // w.logu from (v, e)
 void build_theta_ell(Mesh& m, hipStream_t s);
+void build_theta_ell_overlap(Mesh& m, Mesh::OverlapTileSet& t, hipStream_t s);
 bool patch_supported(const Mesh& m);
-DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inner, hipStream_t s);
+// overlap > 0: the overlapping tiles with that many rings
+DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inner, hipStream_t s, int overlap = 0);
 void run_normalize(Mesh& m, Work& w, hipStream_t s);                    // w.h from (v, e)
 void normalize_from_logu(Mesh& m, Work& w, const double* logu_user, hipStream_t s);
 struct AdmmResult {
@@ -491,6 +577,29 @@ struct QueryOutcome {
 };
 QueryOutcome solve_query(Mesh& m, Work& w, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
                          float* d_dev, hipStream_t s, hg_info* info);
+
+// The join of several resident meshes as the components of one mesh (device
+// arrays concatenated with shifted indices; batch.cpp), and the release of a
+// cached join that holds a mesh about to be destroyed.
+std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s);
+void forget_joins_with(Mesh* m);
+// Upper estimate of the device bytes of one query's workspace (server.cpp).
+uint64_t work_estimate(const Mesh& m, int form, int nsrc);
+
+// Conjugate gradients with a diagonal preconditioner (Sec. 6.4) on the heat
+// system (op 0), the face-form Poisson system (1) or the edge-form one (2);
+// the result is in w.cg.x (internal order).  tol > 0: stop at relative
+// residual <= tol (checked every 16 iterations); tol = 0: max_iters exactly.
+struct CgResult {
+    int iters = 0;
+    bool converged = false;
+    double res_rel = 0.0, res_abs = 0.0, res_abs0 = 0.0, ms = 0.0;
+};
+CgResult run_cg(Mesh& m, Work& w, int op, const std::vector<int32_t>& src_internal, const std::vector<double>& tc,
+                const float* h_internal, int max_iters, double tol, hipStream_t s);
+// |(A - t L_c) u - u_0|_2 (Sec. 6.4's E_1) for u in internal order (log u if is_log)
+double heat_residual(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, const std::vector<double>& tc,
+                     const double* u_internal, bool is_log, hipStream_t s);
 
 // permutation helpers
 void gather_faces_to_internal(Mesh& m, const float* user3, float* internal3, hipStream_t s);

@@ -35,10 +35,13 @@ __global__ void k_bfs_sources(int nsrc, const int32_t* src, int32_t* level, int3
     }
 }
 
-__global__ void k_bfs_expand(int L, const int32_t* row_ptr, const int32_t* col, int32_t* level,
-                             const int32_t* fin, int32_t* fout, int32_t* counters) {
+// One level's expansion: the vertices of frontier L claim their unvisited
+// neighbours for level L + 1 (atomicCAS on the level array) and append them
+// to the next frontier, one atomic per wavefront.
+__global__ void k_bfs_expand(int L, int nv, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                             int32_t* level, const int32_t* fin, int32_t* fout, int32_t* counters) {
     const int cin = L % 3, cout = (L + 1) % 3, czero = (L + 2) % 3;
-    const int n = counters[cin];
+    const int n = min(counters[cin], nv);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         counters[czero] = 0;
         if (n > 0) counters[3] = L;   // deepest non-empty level so far
@@ -52,8 +55,8 @@ __global__ void k_bfs_expand(int L, const int32_t* row_ptr, const int32_t* col, 
         int i = base + lane;
         int claimed[kCap];
         int c = 0;
-        if (i < n) {
-            int v = fin[i];
+        const int v = i < n ? fin[i] : -1;
+        if (v >= 0 && v < nv) {
             for (int k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
                 int u = col[k];
                 if (level[u] < 0 && atomicCAS(&level[u], -1, L + 1) == -1) {
@@ -104,6 +107,36 @@ __global__ void k_bfs_parent(int nv, const int32_t* row_ptr, const int32_t* col,
     pslot[j] = bslot;
 }
 
+int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, hipStream_t s) {
+    const int nv = (int)m.nv;
+    HG_CHECK_HIP(hipMemcpyAsync(b.src, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, b.level, -1);
+    hipLaunchKernelGGL(k_bfs_sources, dim3(1), dim3(64), 0, s, (int)src.size(), b.src, b.level, b.frontier_a,
+                       b.counters);
+    HG_CHECK_HIP(hipGetLastError());
+    int32_t hc[4];
+    const int grid = std::max(1, std::min(grid_for(nv, kBlockB), 2048));
+    for (int L = 0;; ++L) {
+        int32_t* fin = (L % 2 == 0) ? b.frontier_a : b.frontier_b;
+        int32_t* fout = (L % 2 == 0) ? b.frontier_b : b.frontier_a;
+        hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(kBlockB), 0, s, L, nv, m.row_ptr.p, m.col.p, b.level,
+                           fin, fout, b.counters);
+        HG_CHECK_HIP(hipGetLastError());
+        if ((L & 31) == 31) {
+            HG_CHECK_HIP(hipMemcpyAsync(hc, b.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HG_CHECK_HIP(hipStreamSynchronize(s));
+            if (hc[(L + 1) % 3] == 0) break;
+        }
+        if (L > nv + 1) break;
+    }
+    hipLaunchKernelGGL(k_bfs_parent, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, m.row_ptr.p, m.col.p,
+                       b.level, m.perm_v.p, b.parent, b.pslot);
+    HG_CHECK_HIP(hipGetLastError());
+    HG_CHECK_HIP(hipMemcpyAsync(hc, b.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HG_CHECK_HIP(hipStreamSynchronize(s));
+    return hc[3];   // deepest level whose frontier was non-empty
+}
+
 int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src, hipStream_t s) {
     const int nv = (int)m.nv;
     w.level.alloc(nv);
@@ -113,32 +146,8 @@ int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src, hipStream_t s) {
     w.frontier_b.alloc(nv);
     w.counters.alloc(8);
     w.src.alloc(src.size());
-    HG_CHECK_HIP(hipMemcpyAsync(w.src.p, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, w.level.p, -1);
-    hipLaunchKernelGGL(k_bfs_sources, dim3(1), dim3(64), 0, s, (int)src.size(), w.src.p, w.level.p, w.frontier_a.p,
-                       w.counters.p);
-    HG_CHECK_HIP(hipGetLastError());
-    const int grid = std::max(1, std::min(grid_for(nv, kBlockB), 2048));
-    int32_t hc[4];
-    for (int L = 0;; ++L) {
-        int32_t* fin = (L % 2 == 0) ? w.frontier_a.p : w.frontier_b.p;
-        int32_t* fout = (L % 2 == 0) ? w.frontier_b.p : w.frontier_a.p;
-        hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(kBlockB), 0, s, L, m.row_ptr.p, m.col.p, w.level.p, fin,
-                           fout, w.counters.p);
-        HG_CHECK_HIP(hipGetLastError());
-        if ((L & 31) == 31) {
-            HG_CHECK_HIP(hipMemcpyAsync(hc, w.counters.p, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HG_CHECK_HIP(hipStreamSynchronize(s));
-            if (hc[(L + 1) % 3] == 0) break;
-        }
-        if (L > nv + 1) break;
-    }
-    hipLaunchKernelGGL(k_bfs_parent, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, m.row_ptr.p, m.col.p,
-                       w.level.p, m.perm_v.p, w.parent.p, w.pslot.p);
-    HG_CHECK_HIP(hipGetLastError());
-    HG_CHECK_HIP(hipMemcpyAsync(hc, w.counters.p, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HG_CHECK_HIP(hipStreamSynchronize(s));
-    return hc[3];   // deepest level whose frontier was non-empty
+    BfsBuffers b{w.level.p, w.parent.p, w.pslot.p, w.frontier_a.p, w.frontier_b.p, w.counters.p, w.src.p};
+    return run_bfs_into(m, b, src, s);
 }
 
 }  // namespace hg

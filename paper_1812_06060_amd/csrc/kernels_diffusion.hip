@@ -155,11 +155,12 @@ DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src,
                        m.sum_theta.p, w.level.p, w.invD.p, w.v0.p, w.e0.p);
     HG_CHECK_HIP(hipGetLastError());
     const int sched = o.diffusion_schedule != 0 ? o.diffusion_schedule : m.tuned_schedule;
-    const bool patch = sched == 2 || (sched == 0 && patch_supported(m));
+    const bool patch = sched == 2 || sched == 3 || (sched == 0 && patch_supported(m));
     if (patch) {
         if (!patch_supported(m)) throw Error{HG_E_INVALID_ARG, "tiled schedule needs valence <= 16"};
         const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : (m.tuned_inner > 0 ? m.tuned_inner : 32);
-        return run_diffusion_patch(m, w, o, inner, s);
+        const int rings = o.overlap_rings > 0 ? o.overlap_rings : kAutoOverlapRings;
+        return run_diffusion_patch(m, w, o, inner, s, sched == 3 ? rings : 0);
     }
     return run_diffusion_jacobi(m, w, o, s);
 }

@@ -52,15 +52,21 @@ __device__ inline double blk_max(double v, double* sh) {
 }
 constexpr int kNone = -(1 << 30);   // "no reference exponent yet"
 
-template <int MAXW>
-__global__ void __launch_bounds__(kThreads) k_patch_pass(
+// OV: overlapping tiles.  Then halo slots [0, n_ov) hold overlap vertices,
+// updated by the sweeps like the core (overlap vertex tid is a second row of
+// thread tid, with its coefficients and neighbour slots kept in LDS rather
+// than registers, so that two workgroups still fit per compute unit), and
+// only the slots from n_ov on are held fixed; the core alone is written
+// back.  Without OV every halo slot is fixed.
+__host__ __device__ constexpr size_t ov_lds_offset(int ntot) { return ((size_t)ntot * 20 + 7) & ~(size_t)7; }
+
+template <int MAXW, bool OV>
+__device__ __forceinline__ void patch_pass_body(
     const int32_t* __restrict__ tile_list, const double* __restrict__ tile_t, const int32_t* __restrict__ tile_ptr,
-    const int32_t* __restrict__ halo_ptr,
-    const int32_t* __restrict__ halo_idx, const int32_t* __restrict__ ell_ptr,
-    const uint8_t* __restrict__ ell_width, const uint16_t* __restrict__ lnb, const double* __restrict__ theta_ell,
-    const double* __restrict__ invD, const int32_t* __restrict__ level, const double* vin,
-    const int32_t* ein, double* vout, int32_t* eout, int inner,
-    double* __restrict__ partial) {
+    const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx, const int32_t* __restrict__ n_ov,
+    const int32_t* __restrict__ ell_ptr, const uint8_t* __restrict__ ell_width, const uint16_t* __restrict__ lnb,
+    const double* __restrict__ theta_ell, const double* __restrict__ invD, const int32_t* __restrict__ level,
+    const double* vin, const int32_t* ein, double* vout, int32_t* eout, int inner, double* __restrict__ partial) {
     extern __shared__ double lds[];
     __shared__ double shd[kThreads / 64];
     const int p = tile_list[xcd_block(blockIdx.x, gridDim.x)];
@@ -68,10 +74,14 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
     const int v0 = tile_ptr[p];
     const int np = tile_ptr[p + 1] - v0;
     const int h0 = halo_ptr[p], nh = halo_ptr[p + 1] - h0;
+    const int no = OV ? n_ov[p] : 0;
     const int ntot = kTile + nh;
     double* cur = lds;
     double* nxt = lds + ntot;
     int* R = reinterpret_cast<int*>(lds + 2 * ntot);
+    // overlap rows' coefficients and neighbour slots, slot-major (s * no + j)
+    double* oc = OV ? reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + ov_lds_offset(ntot)) : nullptr;
+    uint16_t* ol = OV ? reinterpret_cast<uint16_t*>(oc + MAXW * no) : nullptr;
     const int tid = threadIdx.x;
 
     // 1. coefficients c_jk = t theta_jk / (A_j + t sum theta) into registers,
@@ -98,9 +108,27 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
             c[q][s] = ok ? t * th * id : 0.0;
         }
     }
+    // the overlap row of this thread (OV): vertex halo_idx[h0 + tid], tid < no
+    const bool has1 = OV && tid < no;
+    const int g1 = has1 ? halo_idx[h0 + tid] : 0;
+    double b1 = 0.0;
+    int Rown1 = kNone;
+    if (has1) {
+        const double id = invD[g1];
+        b1 = id;
+        const int ob = eb + W * kTile;
+        for (int s = 0; s < MAXW; ++s) {
+            bool ok = s < W;
+            uint16_t li = ok ? lnb[ob + s * no + tid] : (uint16_t)0xFFFF;
+            ok = ok && li != 0xFFFF;
+            ol[s * no + tid] = ok ? li : (uint16_t)0;
+            oc[s * no + tid] = ok ? t * theta_ell[ob + s * no + tid] * id : 0.0;
+        }
+    }
 
     // 2. reference exponents: own exponent for non-zero values (and the
-    //    source term's for sources), "none" otherwise; halo keeps its own
+    //    source term's for sources), "none" otherwise; the fixed halo keeps
+    //    its own
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         int i = tid + q * kThreads;
@@ -113,17 +141,26 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
         Rown[q] = r;
         R[i] = r;
     }
-    for (int i = tid; i < nh; i += kThreads) {
+    if (has1) {
+        int r = kNone;
+        if (vin[g1] != 0.0) r = ein[g1];
+        if (level[g1] == 0) r = max(r, ilogb(b1));
+        Rown1 = r;
+        R[kTile + tid] = r;
+    }
+    for (int i = tid + no; i < nh; i += kThreads) {
         int g = halo_idx[h0 + i];
         R[kTile + i] = vin[g] != 0.0 ? ein[g] : kNone;
     }
     __syncthreads();
     // 3. max-plus relaxation R_j = max(R_j, R_k + floor(log2 |c_jk|) - 2) over
-    //    the tile (halo fixed).  Every weight c_jk 2^(R_k - R_j) is then <= 8,
-    //    so no value can overflow within the pass.  The least fixed point is
-    //    unique (all edge weights are negative), so the in-place, any-order
-    //    updates give the same R every time; it is reached within np rounds.
-    for (int round = 0; round < kTile; ++round) {
+    //    the updated slots (fixed halo held).  Every weight c_jk 2^(R_k - R_j)
+    //    is then <= 8, so no value can overflow within the pass.  The least
+    //    fixed point is unique (all edge weights are negative), so the
+    //    in-place, any-order updates give the same R every time; it is
+    //    reached within as many rounds as there are updated slots.
+    const int nrounds = kTile + no;
+    for (int round = 0; round < nrounds; ++round) {
         int changed = 0;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
@@ -140,6 +177,21 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
             if (r != Rown[q]) {
                 Rown[q] = r;
                 R[i] = r;
+                changed = 1;
+            }
+        }
+        if (has1) {
+            int r = Rown1;
+            for (int s = 0; s < W; ++s) {
+                const double cs = oc[s * no + tid];
+                if (cs == 0.0) continue;
+                int rk = R[ol[s * no + tid]];
+                if (rk == kNone) continue;
+                r = max(r, rk + ilogb(cs) - 2);
+            }
+            if (r != Rown1) {
+                Rown1 = r;
+                R[kTile + tid] = r;
                 changed = 1;
             }
         }
@@ -169,10 +221,28 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
         vstart[q] = x;
         cur[i] = x;   // slots np..kTile-1 of a short tile stay 0
     }
-    for (int i = tid; i < nh; i += kThreads) {
+    if (has1) {
+        const int rj = Rown1;
+        const bool live = rj != kNone;
+        double x = 0.0;
+        if (live) {
+            double v = vin[g1];
+            if (v != 0.0) x = ldexp(v, ein[g1] - rj);
+            b1 = level[g1] == 0 ? ldexp(b1, -rj) : 0.0;
+        } else {
+            b1 = 0.0;
+        }
+        for (int s = 0; s < W; ++s) {
+            const double cs = oc[s * no + tid];
+            const int rk = R[ol[s * no + tid]];
+            oc[s * no + tid] = (live && cs != 0.0 && rk != kNone) ? ldexp(cs, rk - rj) : 0.0;
+        }
+        cur[kTile + tid] = x;
+    }
+    for (int i = tid + no; i < nh; i += kThreads) {
         int g = halo_idx[h0 + i];
         double v = vin[g];
-        cur[kTile + i] = v;   // the halo's reference exponent is its own
+        cur[kTile + i] = v;   // the fixed halo's reference exponent is its own
         nxt[kTile + i] = v;
     }
     __syncthreads();
@@ -187,14 +257,19 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
             for (int s = 0; s < MAXW; ++s) acc = fma(c[q][s], cur[l[q][s]], acc);
             if (i < np) nxt[i] = acc;
         }
+        if (has1) {
+            double acc = b1;
+            for (int s = 0; s < W; ++s) acc = fma(oc[s * no + tid], cur[ol[s * no + tid]], acc);
+            nxt[kTile + tid] = acc;
+        }
         __syncthreads();
         double* tmp = cur;
         cur = nxt;
         nxt = tmp;
     }
 
-    // 6. write back renormalised; largest relative change over the pass
-    //    (a non-finite value would be a bug: report it as not converged)
+    // 6. write back the core renormalised; largest relative change over the
+    //    pass (a non-finite value would be a bug: report it as not converged)
     double res = 0.0;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -221,6 +296,30 @@ __global__ void __launch_bounds__(kThreads) k_patch_pass(
     if (tid == 0) partial[p] = res;
 }
 
+#define HG_PATCH_PARAMS                                                                                           \
+    const int32_t *__restrict__ tile_list, const double *__restrict__ tile_t, const int32_t *__restrict__ tile_ptr, \
+        const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo_idx,                                 \
+        const int32_t *__restrict__ n_ov, const int32_t *__restrict__ ell_ptr,                                      \
+        const uint8_t *__restrict__ ell_width, const uint16_t *__restrict__ lnb,                                    \
+        const double *__restrict__ theta_ell, const double *__restrict__ invD, const int32_t *__restrict__ level,   \
+        const double *vin, const int32_t *ein, double *vout, int32_t *eout, int inner, double *__restrict__ partial
+#define HG_PATCH_FWD                                                                                       \
+    tile_list, tile_t, tile_ptr, halo_ptr, halo_idx, n_ov, ell_ptr, ell_width, lnb, theta_ell, invD, level, vin, \
+        ein, vout, eout, inner, partial
+
+// plain tiles: registers as needed (52 at valence 6: two workgroups per CU)
+template <int MAXW>
+__global__ void __launch_bounds__(kThreads) k_patch_pass(HG_PATCH_PARAMS) {
+    patch_pass_body<MAXW, false>(HG_PATCH_FWD);
+}
+// overlapping tiles: held to 64 registers so that two workgroups fit per CU
+template <int MAXW>
+__global__ void __launch_bounds__(kThreads, 8) k_patch_pass_ov(HG_PATCH_PARAMS) {
+    patch_pass_body<MAXW, true>(HG_PATCH_FWD);
+}
+#undef HG_PATCH_PARAMS
+#undef HG_PATCH_FWD
+
 // theta in the tiles' ELL layout, gathered from the CSR rows (same order);
 // one workgroup per tile.
 __global__ void k_theta_ell(const int32_t* tile_ptr, const int32_t* row_ptr, const double* theta,
@@ -243,24 +342,82 @@ void build_theta_ell(Mesh& m, hipStream_t s) {
     HG_CHECK_HIP(hipGetLastError());
 }
 
-static size_t patch_lds_bytes(const Mesh& m) { return (size_t)(kTile + m.max_halo) * (8 + 8 + 4); }
+// theta of the overlapping tiles' ELL rows: core rows (stride kTile), then
+// the overlap vertices' rows (stride n_ov)
+__global__ void k_theta_ell_overlap(const int32_t* tile_ptr, const int32_t* row_ptr, const double* theta,
+                                    const int32_t* halo_ptr, const int32_t* halo_idx, const int32_t* n_ov,
+                                    const int32_t* ell_ptr, const uint8_t* ell_width, double* theta_ell) {
+    const int p = blockIdx.x;
+    const int v0 = tile_ptr[p], np = tile_ptr[p + 1] - v0;
+    const int W = ell_width[p], eb = ell_ptr[p], no = n_ov[p], h0 = halo_ptr[p];
+    for (int i = threadIdx.x; i < np + no; i += blockDim.x) {
+        const bool core = i < np;
+        const int j = core ? i : i - np;
+        const int v = core ? v0 + i : halo_idx[h0 + j];
+        const int base = core ? eb : eb + W * kTile;
+        const int stride = core ? kTile : no;
+        const int k0 = row_ptr[v], deg = row_ptr[v + 1] - k0;
+        for (int s = 0; s < W; ++s) theta_ell[base + s * stride + j] = s < deg ? theta[k0 + s] : 0.0;
+    }
+}
+
+void build_theta_ell_overlap(Mesh& m, Mesh::OverlapTileSet& t, hipStream_t s) {
+    if (m.patch_size != kTile) throw Error{HG_E_DEVICE, "tile size mismatch"};
+    t.theta_ell.alloc(t.lnb.n);
+    hipLaunchKernelGGL(k_theta_ell_overlap, dim3(m.n_patches), dim3(256), 0, s, m.tile_ptr.p, m.row_ptr.p,
+                       m.theta.p, t.halo_ptr.p, t.halo_idx.p, t.n_ov.p, t.ell_ptr.p, t.ell_width.p, t.theta_ell.p);
+    HG_CHECK_HIP(hipGetLastError());
+}
+
+static size_t patch_lds_bytes(int max_halo) { return (size_t)(kTile + max_halo) * (8 + 8 + 4); }
+// overlapping tiles: the above (aligned), plus per overlap row maxw
+// coefficients (FP64) and neighbour slots (uint16)
+static size_t patch_lds_bytes_ov(int max_halo, int max_ov, int maxw) {
+    return ov_lds_offset(kTile + max_halo) + (size_t)max_ov * maxw * (8 + 2);
+}
+static int template_width(int w) { return w <= 6 ? 6 : (w <= 8 ? 8 : 16); }
 
 // valence within the register tables, LDS within 64 KiB
 bool patch_supported(const Mesh& m) {
-    return m.max_ell_width <= 16 && m.patch_size == kTile && patch_lds_bytes(m) <= 65536;
+    return m.max_ell_width <= 16 && m.patch_size == kTile && patch_lds_bytes(m.max_halo) <= 65536;
 }
 
-// Runs patch passes until the largest relative change over a pass is <= tol.
-DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inner, hipStream_t s) {
+// Runs patch passes until the largest relative change over a pass is <= tol;
+// overlap > 0: on the overlapping tiles with that many rings (one overlap
+// vertex per thread at most).
+DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inner, hipStream_t s, int overlap) {
     const int nv = (int)m.nv;
     const int nt = m.n_patches;
     if ((int)w.partial.n < nt + 8) w.partial.alloc((size_t)nt + 8);
-    const size_t lds = patch_lds_bytes(m);
+    const Mesh::OverlapTileSet* ot = nullptr;
+    if (overlap > 0) {
+        ot = m.ensure_overlap_tiles(overlap, kThreads, 65536, template_width(m.max_ell_width), s);
+        if (!ot) throw Error{HG_E_INVALID_ARG, "overlapping tiles do not fit this mesh (more overlap vertices than "
+                                               "threads); use fewer overlap rings"};
+        if (ot->max_ell_width > 16 ||
+            patch_lds_bytes_ov(ot->max_halo, ot->max_ov, template_width(ot->max_ell_width)) > 65536)
+            throw Error{HG_E_INVALID_ARG, "overlapping tiles exceed the valence or LDS limits"};
+    }
+    const size_t lds = ot ? patch_lds_bytes_ov(ot->max_halo, ot->max_ov, template_width(ot->max_ell_width))
+                          : patch_lds_bytes(m.max_halo);
+    const int maxw = ot ? ot->max_ell_width : m.max_ell_width;
+    const std::vector<int32_t>& color_ptr = ot ? ot->color_ptr_host : m.color_ptr_host;
+    const int32_t* order = ot ? ot->tile_order.p : m.tile_order.p;
+    const int32_t* halo_ptr = ot ? ot->halo_ptr.p : m.halo_ptr.p;
+    const int32_t* halo_idx = ot ? ot->halo_idx.p : m.halo_idx.p;
+    const int32_t* n_ov = ot ? ot->n_ov.p : nullptr;
+    const int32_t* ell_ptr = ot ? ot->ell_ptr.p : m.ell_ptr.p;
+    const uint8_t* ell_width = ot ? ot->ell_width.p : m.ell_width.p;
+    const uint16_t* lnb = ot ? ot->lnb.p : m.lnb.p;
+    const double* theta_ell = ot ? ot->theta_ell.p : m.theta_ell.p;
     DiffusionResult r;
     // algorithmic bytes of one pass: tile tables (ELL slots + theta), halo
-    // list, 1/D and level, (v, e) read for tile and halo, (v, e) written
-    r.bytes_per_pass = (uint64_t)m.lnb.n * (2 + 8) + (uint64_t)m.halo_idx.n * (4 + 16) +
-                       (uint64_t)nv * (8 + 4 + 12 + 12) + (uint64_t)nt * 17;
+    // list, 1/D and level, (v, e) read for tile and halo, (v, e) written;
+    // overlap vertices also read their 1/D and level
+    const uint64_t ell_n = ot ? ot->lnb.n : m.lnb.n;
+    const uint64_t halo_n = ot ? ot->halo_idx.n : m.halo_idx.n;
+    r.bytes_per_pass = ell_n * (2 + 8) + halo_n * (4 + 16) + (uint64_t)nv * (8 + 4 + 12 + 12) +
+                       (uint64_t)nt * (ot ? 21 : 17) + (ot ? (uint64_t)halo_n * 12 : 0);
     double* va = w.v0.p;   // updated in place
     int32_t* ea = w.e0.p;
     const int check = std::max(1, o.check_every / std::max(1, inner / 4));
@@ -269,18 +426,27 @@ DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inne
     // the latest values of the others (block Gauss-Seidel between tiles,
     // Jacobi within a colour: tiles of one colour are independent)
     auto pass = [&] {
-        for (size_t c = 0; c + 1 < m.color_ptr_host.size(); ++c) {
-            const int c0 = m.color_ptr_host[c], nc = m.color_ptr_host[c + 1] - c0;
-#define HG_PATCH_ARGS                                                                                             \
-    dim3(nc), dim3(kThreads), lds, s, m.tile_order.p + c0, w.tile_t.p, m.tile_ptr.p, m.halo_ptr.p,         \
-        m.halo_idx.p, m.ell_ptr.p, m.ell_width.p, m.lnb.p, m.theta_ell.p, w.invD.p, w.level.p, va, ea, va, ea, \
-        inner, w.partial.p
-            if (m.max_ell_width <= 6)
-                hipLaunchKernelGGL(k_patch_pass<6>, HG_PATCH_ARGS);
-            else if (m.max_ell_width <= 8)
-                hipLaunchKernelGGL(k_patch_pass<8>, HG_PATCH_ARGS);
-            else
-                hipLaunchKernelGGL(k_patch_pass<16>, HG_PATCH_ARGS);
+        for (size_t c = 0; c + 1 < color_ptr.size(); ++c) {
+            const int c0 = color_ptr[c], nc = color_ptr[c + 1] - c0;
+            if (nc == 0) continue;
+#define HG_PATCH_ARGS                                                                                           \
+    dim3(nc), dim3(kThreads), lds, s, order + c0, w.tile_t.p, m.tile_ptr.p, halo_ptr, halo_idx, n_ov, ell_ptr, \
+        ell_width, lnb, theta_ell, w.invD.p, w.level.p, va, ea, va, ea, inner, w.partial.p
+            if (ot) {
+                if (maxw <= 6)
+                    hipLaunchKernelGGL(k_patch_pass_ov<6>, HG_PATCH_ARGS);
+                else if (maxw <= 8)
+                    hipLaunchKernelGGL(k_patch_pass_ov<8>, HG_PATCH_ARGS);
+                else
+                    hipLaunchKernelGGL(k_patch_pass_ov<16>, HG_PATCH_ARGS);
+            } else {
+                if (maxw <= 6)
+                    hipLaunchKernelGGL(k_patch_pass<6>, HG_PATCH_ARGS);
+                else if (maxw <= 8)
+                    hipLaunchKernelGGL(k_patch_pass<8>, HG_PATCH_ARGS);
+                else
+                    hipLaunchKernelGGL(k_patch_pass<16>, HG_PATCH_ARGS);
+            }
 #undef HG_PATCH_ARGS
         }
     };

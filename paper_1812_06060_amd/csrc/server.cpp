@@ -42,7 +42,7 @@ static double now_s() {
 // allocate: breadth-first sets and pairing, two (v, e) copies, 1/D, log u,
 // h, the form's double-buffered ADMM state, outputs, integration pairs and
 // pointer-jumping parents, plus the source paths (bounded by nsrc * depth).
-static uint64_t work_estimate(const Mesh& m, int form, int nsrc) {
+uint64_t work_estimate(const Mesh& m, int form, int nsrc) {
     const uint64_t nv = m.nv, nf = m.nf, ne = m.ne;
     uint64_t b = 24 * nv          // level, parent, pslot, two frontiers, counters
                  + 24 * nv + 8 * nv + 8 * nv   // v0, v1, invD; e0, e1; logu
@@ -79,7 +79,10 @@ struct Server {
         uint64_t last_use;
     };
     std::map<Mesh*, std::vector<Pooled>> free_ws;   // idle workspaces per mesh
-    uint64_t held_bytes = 0;    // estimates of all workspaces alive (idle or in use)
+    uint64_t held_bytes = 0;    // workspaces alive (idle or in use: the larger of their
+                                // admission estimate and their size after their last query),
+                                // plus mesh_growth
+    uint64_t mesh_growth = 0;   // schedules that served queries added to their meshes
     uint64_t use_clock = 0;
     uint64_t budget = 0;
     int running = 0;
@@ -178,6 +181,7 @@ struct Server {
             res.ticket = r.ticket;
             res.t_submit = r.t_submit;
             res.t_start = now_s();
+            const uint64_t mesh_before = r.mesh->mesh_bytes();
             try {
                 (void)hipSetDevice(r.mesh->device);
                 QueryOutcome q = solve_query(*r.mesh, *w.w, r.src.data(), (int32_t)r.src.size(), r.t,
@@ -192,7 +196,20 @@ struct Server {
             }
             res.t_end = now_s();
 
+            // what the query really holds: a pooled workspace grows past the
+            // estimate it was admitted with when a larger query (more
+            // sources, the other form) reuses it, and a query may build
+            // schedules the mesh keeps (the blocked-ADMM face tiles, the
+            // face form's slot geometry); both count against the budget
+            const uint64_t actual = std::max<uint64_t>(w.bytes, w.w->bytes());
+            const uint64_t mesh_after = r.mesh->mesh_bytes();
             lk.lock();
+            held_bytes += actual - w.bytes;
+            w.bytes = actual;
+            if (mesh_after > mesh_before) {
+                held_bytes += mesh_after - mesh_before;
+                mesh_growth += mesh_after - mesh_before;
+            }
             --running;
             w.last_use = ++use_clock;
             free_ws[r.mesh].push_back(std::move(w));

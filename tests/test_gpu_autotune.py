@@ -26,10 +26,11 @@ def test_autotune_then_solve(name):
         assert 0 <= rep["chosen"] < len(c)
         best = c[rep["chosen"]]["ms"]
         assert all(best <= x["ms"] + 1e-6 for x in c if x["passes"] > 0)
-        if mesh.stats["n_patches"] > 16:
-            assert all(x["schedule"] == 2 for x in c)
+        if mesh.stats["n_patches"] > 16:   # global Jacobi only on meshes of a few tiles
+            assert all(x["schedule"] in (2, 3) for x in c)
+        assert {x["schedule"] for x in c} >= {2, 3}
         d, info = mesh.solve(src, 0.0, hg.default_opts())
-        if c[rep["chosen"]]["schedule"] == 2:
+        if c[rep["chosen"]]["schedule"] in (2, 3):
             assert info.sweeps == info.passes * c[rep["chosen"]]["inner_sweeps"]
         ref = pipeline.heat_method(v, f, src, form="edge")
         mean, mx = metrics.parity(d.cpu().numpy(), ref.d)

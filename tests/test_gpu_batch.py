@@ -1,7 +1,10 @@
-"""Many meshes in one solve (components of one resident mesh, per-component
+"""Many resident meshes in one solve (hg_geodesic_solve_batch: the meshes
+joined on the device as the components of one mesh, each with its own
 diffusion time): every mesh's distance matches the oracle run on that mesh
-alone, in both forms, including a mesh with several sources; the stats see
-one component per mesh."""
+alone, in both forms, including a mesh with several sources; a batch over
+other meshes, or a destroyed member, replaces the cached join; and the
+256-mesh workload of levels 3-6 matches its stored oracle samples."""
+import os
 import numpy as np
 import pytest
 
@@ -43,10 +46,17 @@ def batch():
     b.close()
 
 
-def test_batch_stats(batch):
+def test_batch_sizes(batch):
+    import paper_1812_06060_amd as hg
     meshes, b = batch
-    assert b.mesh.stats["n_components"] == len(meshes)
-    assert b.mesh.nv == sum(v.shape[0] for v, _ in meshes)
+    assert [m.nv for m in b.meshes] == [v.shape[0] for v, _ in meshes]
+    for m in b.meshes:
+        assert m.mesh_bytes() == m.stats["mesh_bytes"] > 0
+        q1 = m.query_bytes(1)
+        assert q1 > 36 * m.nf
+        assert m.query_bytes(8) > q1
+        assert m.query_bytes(1, hg.default_opts(formulation="face")) > q1
+        assert m.query_bytes(0) == 0
 
 
 @pytest.mark.parametrize("form", ["edge", "face"])
@@ -64,17 +74,100 @@ def test_each_mesh_matches_its_oracle(batch, form):
         assert mean <= 1e-4 and mx <= 1e-3, i
 
 
-def test_shared_t_differs_from_per_mesh_t(batch):
-    """Without t_per_component the whole batch diffuses with one t (the
-    mean edge length of all meshes), which is not each mesh's own problem:
-    the distances of some mesh differ measurably."""
+def test_one_mesh_of_a_batch_equals_its_solve_alone(batch):
+    """A member's batched distance equals its own hg_geodesic_solve to well
+    within the parity bar (same t, same schedules; only the stopping rules
+    see the whole batch)."""
     import paper_1812_06060_amd as hg
     meshes, b = batch
     src = _sources(meshes)
     ds, _ = b.solve(src, opts=hg.default_opts())
-    o = hg.default_opts()
-    allsrc = np.concatenate([np.asarray(s) + b.starts[i] for i, s in enumerate(src)]).astype(np.int32)
-    d2, _ = b.mesh.solve(allsrc, 0.0, o)
-    d2 = d2.cpu().numpy()
-    diff = max(np.abs(ds[i].cpu().numpy() - d2[b.starts[i]:b.starts[i + 1]]).max() for i in range(len(b)))
+    for i in (0, 3, 8):
+        d1, _ = b.meshes[i].solve(src[i], 0.0, hg.default_opts())
+        a = d1.cpu().numpy()
+        assert np.abs(ds[i].cpu().numpy() - a).max() <= 1e-4 * a.max(), i
+
+
+def test_shared_t_differs_from_per_mesh_t(batch):
+    """The same meshes as one host-built mesh with one t (the mean edge
+    length of all of them) is not each mesh's own problem: the distances of
+    some mesh differ measurably from the batch's."""
+    import paper_1812_06060_amd as hg
+    meshes, b = batch
+    src = _sources(meshes)
+    ds, _ = b.solve(src, opts=hg.default_opts())
+    v, f, starts = meshgen.disjoint_union(meshes)
+    starts = list(starts) + [v.shape[0]]
+    u = hg.Mesh(v, f)
+    try:
+        allsrc = np.concatenate([np.asarray(s) + starts[i] for i, s in enumerate(src)]).astype(np.int32)
+        d2, _ = u.solve(allsrc, 0.0, hg.default_opts())
+        d2 = d2.cpu().numpy()
+    finally:
+        u.close()
+    diff = max(np.abs(ds[i].cpu().numpy() - d2[starts[i]:starts[i + 1]]).max() for i in range(len(b)))
     assert diff > 1e-4
+
+
+def test_join_is_replaced_by_other_meshes_and_dropped_with_a_member():
+    """Two batches in a row over different meshes (the second a subset in
+    another order), then a batch after one member was destroyed and
+    recreated: every answer equals the member's solve alone."""
+    import paper_1812_06060_amd as hg
+    ms = []
+    for i, lvl in enumerate([3, 4, 3]):
+        v, f = meshgen.icosphere(lvl)
+        ms.append(hg.Mesh(meshgen.harmonic_displacement(v, seed=50 + i), f))
+    try:
+        alone = [m.solve([5], 0.0, hg.default_opts())[0].cpu().numpy() for m in ms]
+
+        def check(members):
+            ds, _ = hg.solve_batch([ms[i] for i in members], [[5]] * len(members))
+            for i, d in zip(members, ds):
+                assert np.abs(d.cpu().numpy() - alone[i]).max() <= 1e-4 * alone[i].max(), (members, i)
+        _say("batch over meshes 0,1,2 then 2,0")
+        check([0, 1, 2])
+        check([2, 0])
+        check([2, 0])
+        ms[0].close()
+        v, f = meshgen.icosphere(3)
+        ms[0] = hg.Mesh(meshgen.harmonic_displacement(v, seed=50), f)
+        _say("batch after a member was destroyed")
+        check([2, 0])
+    finally:
+        for m in ms:
+            m.close()
+
+
+GOLD256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch256_edge.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD256), reason="batch256 goldens not generated")
+def test_256_small_meshes_match_stored_oracle_samples():
+    """The 256-mesh workload (levels 3-6 drawn uniformly, seed 4; mesh i
+    displaced with seed 1000 + i, source seed 2000 + i) in one batched
+    solve over resident meshes: every mesh within the parity bar at its
+    stored oracle sample (nearest, farthest and uniform vertices)."""
+    import paper_1812_06060_amd as hg
+    g = np.load(GOLD256)
+    meshes, src = meshgen.batch_meshes(256)
+    b = MeshBatchLocal(meshes)
+    try:
+        _say("256-mesh batch")
+        ds, info = b.solve(src, opts=hg.default_opts())
+        assert info.converged_u and info.converged_admm
+        worst = 0.0
+        for i, d in enumerate(ds):
+            idx = g["idx"][g["ptr"][i]:g["ptr"][i + 1]]
+            ref = g["d"][g["ptr"][i]:g["ptr"][i + 1]].astype(np.float64)
+            err = np.abs(d.cpu().numpy()[idx] - ref) / float(g["diam"][i])
+            worst = max(worst, float(err.max()))
+            assert err.mean() <= 1e-4 and err.max() <= 1e-3, i
+        _say("256-mesh batch: worst max error", worst)
+    finally:
+        b.close()
+
+
+def MeshBatchLocal(meshes):
+    from paper_1812_06060_amd.batch import MeshBatch
+    return MeshBatch(meshes)

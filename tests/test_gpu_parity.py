@@ -74,7 +74,7 @@ def test_bfs_bit_exact(case):
     assert depth == rf.level.max()
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 def test_diffusion_logu(case, hg, schedule):
     name, v, f, src, mesh, rf, _ = case
     _say(name, "diffuse schedule", schedule)
@@ -85,7 +85,7 @@ def test_diffusion_logu(case, hg, schedule):
     assert np.abs(lu - rf.logu).max() < 1e-8
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 def test_diffusion_beyond_fp64_range(hg, schedule):
     """t = 1e-4 hbar^2 on a displaced level-5 sphere: u reaches ~e^-800,
     far outside FP64; compared with the oracle's banded solve (pinned to an 80-bit Jacobi)."""
@@ -104,6 +104,42 @@ def test_diffusion_beyond_fp64_range(hg, schedule):
     assert info.converged_u and np.all(np.isfinite(lu))
     assert np.abs(lu - ref).max() < 1e-7 * np.abs(ref).max()
     mesh.close()
+
+
+def test_overlapping_tiles_beyond_lds_refused(hg):
+    """Four rings of overlap on 1024-vertex tiles exceed the 64 KiB of LDS
+    a tile's workgroup may take: refused with HG_E_INVALID_ARG, nothing run."""
+    v, f = meshgen.icosphere(6)
+    mesh = hg.Mesh(v, f)
+    try:
+        with pytest.raises(hg.HgeoError) as e:
+            mesh.diffuse([0], 0.0, hg.default_opts(diffusion_schedule=3, overlap_rings=4))
+        assert e.value.status == 1
+    finally:
+        mesh.close()
+
+
+@pytest.mark.parametrize("rings", [1, 2])
+def test_overlapping_tiles_same_fixed_point_fewer_passes(hg, rings):
+    """Schedule 3 (tiles that also sweep `rings` rings around themselves)
+    reaches the oracle's log u on a displaced level-6 sphere, with more
+    than one source, in fewer passes than the plain tiles."""
+    v, f = meshgen.icosphere(6)
+    v = meshgen.harmonic_displacement(v, seed=3)
+    src = meshgen.random_sources(v.shape[0], 3, seed=21)
+    ref = pipeline.heat_method(v, f, src, form="edge")
+    mesh = hg.Mesh(v, f)
+    try:
+        _say("bumpy6 overlap rings", rings)
+        l2, i2 = mesh.diffuse(src, 0.0, hg.default_opts(tol_u=1e-12, diffusion_schedule=2, inner_sweeps=32))
+        l3, i3 = mesh.diffuse(src, 0.0, hg.default_opts(tol_u=1e-12, diffusion_schedule=3, inner_sweeps=32,
+                                                        overlap_rings=rings))
+        _say("passes plain", i2.passes, "overlap", i3.passes, "mesh bytes", mesh.mesh_bytes())
+        assert i3.converged_u
+        assert np.abs(l3.cpu().numpy() - ref.logu).max() < 1e-8
+        assert i3.passes < i2.passes
+    finally:
+        mesh.close()
 
 
 def test_normalize(case):

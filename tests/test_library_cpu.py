@@ -131,3 +131,17 @@ def test_server_rejects_null_arguments(lib):
 
 def test_autotune_rejects_null_mesh(lib):
     assert lib.hg_mesh_autotune(None, None, 0, 0.0, None, None, None) == _hgeo.HG_E_INVALID_ARG
+
+
+def test_batch_and_size_calls_reject_null_arguments(lib):
+    """hg_geodesic_solve_batch, hg_mesh_bytes and hg_query_bytes refuse NULL or empty arguments before any device work."""
+    one = (C.c_int32 * 1)(1)
+    meshes = (C.c_void_p * 1)(None)
+    srcs = (C.c_void_p * 1)(None)
+    outs = (C.c_void_p * 1)(None)
+    assert lib.hg_geodesic_solve_batch(None, 1, srcs, one, 0.0, None, outs, None, None) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_geodesic_solve_batch(meshes, 0, srcs, one, 0.0, None, outs, None, None) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_geodesic_solve_batch(meshes, 1, srcs, one, 0.0, None, outs, None, None) == _hgeo.HG_E_INVALID_ARG
+    assert "batch query 0" in lib.hg_last_error().decode()
+    assert lib.hg_mesh_bytes(None) == 0
+    assert lib.hg_query_bytes(None, 1, None) == 0
