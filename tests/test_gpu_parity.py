@@ -106,24 +106,13 @@ def test_diffusion_beyond_fp64_range(hg, schedule):
     mesh.close()
 
 
-def test_overlapping_tiles_beyond_lds_refused(hg):
-    """Four rings of overlap on 1024-vertex tiles exceed the 64 KiB of LDS
-    a tile's workgroup may take: refused with HG_E_INVALID_ARG, nothing run."""
-    v, f = meshgen.icosphere(6)
-    mesh = hg.Mesh(v, f)
-    try:
-        with pytest.raises(hg.HgeoError) as e:
-            mesh.diffuse([0], 0.0, hg.default_opts(diffusion_schedule=3, overlap_rings=4))
-        assert e.value.status == 1
-    finally:
-        mesh.close()
-
-
-@pytest.mark.parametrize("rings", [1, 2])
+@pytest.mark.parametrize("rings", [1, 2, 4])
 def test_overlapping_tiles_same_fixed_point_fewer_passes(hg, rings):
     """Schedule 3 (tiles that also sweep `rings` rings around themselves)
     reaches the oracle's log u on a displaced level-6 sphere, with more
-    than one source, in fewer passes than the plain tiles."""
+    than one source, in fewer passes than the plain tiles.  At four rings
+    some tiles' regions would exceed the LDS a workgroup may take: those
+    tiles get fewer rings, with the same fixed point."""
     v, f = meshgen.icosphere(6)
     v = meshgen.harmonic_displacement(v, seed=3)
     src = meshgen.random_sources(v.shape[0], 3, seed=21)
