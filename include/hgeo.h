@@ -347,6 +347,19 @@ hg_status hg_mesh_cycles(hg_mesh_t mesh, int32_t form, int32_t* ptr, int32_t* id
 hg_status hg_bfs(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
                  int32_t* level_dev, int32_t* parent_dev, void* stream, int32_t* depth_out);
 
+/* The same search without allocating device memory, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, outputs and results are
+ * those of hg_bfs.  Its working arrays live in a fixed 64 MiB device array
+ * of the library, one per GPU, held from the first call on that GPU until
+ * the process ends; it takes meshes of at most 3,000,000 vertices and at
+ * most 65,536 sources (HG_E_INVALID_ARG beyond, nothing run).  Calls on
+ * one GPU share that array: calls that overlap in time on one GPU (from
+ * several threads or on several streams) race and must be serialised by
+ * the caller.  The stream is synchronised before returning. */
+hg_status hg_bfs_noalloc(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
+                         int32_t* level_dev, int32_t* parent_dev, void* stream, int32_t* depth_out);
+
 /* Diffusion (Eq. 4 by sweeps of Eq. 7): logu_dev = DEVICE float64[nv], the
  * natural log of u (-inf where u = 0).  Uses opts->tol_u / max_sweeps /
  * diffusion_schedule; info receives sweeps, passes, res_u, t. */

@@ -122,6 +122,7 @@ _API = {
     "hg_heat_residual": [_P, _P, C.c_int32, C.c_double, _P, C.c_int32, C.POINTER(C.c_double), _P],
     "hg_query_bytes": [_P, C.c_int32, C.POINTER(Opts)],
     "hg_bfs": [_P, _P, C.c_int32, _P, _P, _P, C.POINTER(C.c_int32)],
+    "hg_bfs_noalloc": [_P, _P, C.c_int32, _P, _P, _P, C.POINTER(C.c_int32)],
     "hg_diffuse": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
     "hg_normalize": [_P, _P, _P, _P],
     "hg_admm_edge": [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(Opts), _P, _P, C.POINTER(Info)],
@@ -385,6 +386,18 @@ class Mesh:
         depth = C.c_int32()
         _check(_lib.hg_bfs(self._h, p, n, _dptr(lev, torch.int32, self.nv), _dptr(par, torch.int32, self.nv),
                            _stream(stream), C.byref(depth)))
+        return lev, par, depth.value
+
+    def bfs_noalloc(self, sources, level=None, parent=None, stream=None):
+        """hg_bfs on the library's fixed device array (no device allocation
+        inside the call); level/parent: optional caller-owned int32[nv]."""
+        torch = _torch()
+        lev = torch.empty(self.nv, dtype=torch.int32, device="cuda") if level is None else level
+        par = torch.empty(self.nv, dtype=torch.int32, device="cuda") if parent is None else parent
+        a, p, n = _src_array(sources)
+        depth = C.c_int32()
+        _check(_lib.hg_bfs_noalloc(self._h, p, n, _dptr(lev, torch.int32, self.nv),
+                                   _dptr(par, torch.int32, self.nv), _stream(stream), C.byref(depth)))
         return lev, par, depth.value
 
     def diffuse(self, sources, t: float = 0.0, opts: Opts | None = None, stream=None,

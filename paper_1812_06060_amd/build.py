@@ -27,6 +27,7 @@ SOURCES = [
     "kernels_patch.hip",
     "kernels_paths.hip",
     "server.cpp",
+    "noalloc.hip",
     "batch.cpp",
     "kernels_cg.hip",
     "overlap_tiles.cpp",

@@ -134,7 +134,8 @@ def test_autotune_rejects_null_mesh(lib):
 
 
 def test_batch_and_size_calls_reject_null_arguments(lib):
-    """hg_geodesic_solve_batch, hg_mesh_bytes and hg_query_bytes refuse NULL or empty arguments before any device work."""
+    """hg_geodesic_solve_batch, hg_mesh_bytes, hg_query_bytes and
+    hg_bfs_noalloc refuse NULL or empty arguments before any device work."""
     one = (C.c_int32 * 1)(1)
     meshes = (C.c_void_p * 1)(None)
     srcs = (C.c_void_p * 1)(None)
@@ -145,3 +146,4 @@ def test_batch_and_size_calls_reject_null_arguments(lib):
     assert "batch query 0" in lib.hg_last_error().decode()
     assert lib.hg_mesh_bytes(None) == 0
     assert lib.hg_query_bytes(None, 1, None) == 0
+    assert lib.hg_bfs_noalloc(None, one, 1, None, None, None, None) == _hgeo.HG_E_INVALID_ARG
