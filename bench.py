@@ -169,7 +169,7 @@ def main():
         ch = tune["candidates"][tune["chosen"]]
         def label(c):
             return {1: "jacobi", 2: f"tiles/{c['inner_sweeps']}",
-                    3: f"overlap-tiles/{c['inner_sweeps']}"}.get(c["schedule"], "?")
+                    3: f"overlap{c.get('overlap_rings', 0)}-tiles/{c['inner_sweeps']}"}.get(c["schedule"], "?")
         print(f"[bench] autotune ({time.perf_counter() - t0:.1f}s): " +
               ", ".join(f"{label(c)}={c['ms']:.0f}ms ({c['passes']} passes)" for c in tune["candidates"]) +
               f" -> {label(ch)}", file=sys.stderr, flush=True)

@@ -143,7 +143,9 @@ typedef struct {
                                the result, the iteration count included, is
                                the same for every k.  0 = auto (default, 6) */
     int32_t overlap_rings;  /* schedule 3: rings of overlap around each tile,
-                               1..4; 0 = auto (2) */
+                               1..4 (a tile whose region would not fit the
+                               LDS gets fewer); 0 = auto: the autotuned
+                               count, else 2 */
 } hg_opts;
 
 /* Per-solve report. */
@@ -501,17 +503,20 @@ typedef struct {
     int32_t inner_sweeps[8];     /* sweeps per tile pass (0 for Jacobi) */
     float ms[8];                 /* time of the diffusion stage (converged) */
     int32_t passes[8];
-    int32_t reserved[8];
+    int32_t overlap_rings[8];    /* rings of overlap (schedule 3), else 0 */
 } hg_tune_report;
 
 /* Times the diffusion stage of a probe query (src/nsrc, t, opts as in
  * hg_geodesic_solve) once per candidate schedule -- LDS tiles with 16, 32
- * and 64 in-tile sweeps per pass, overlapping LDS tiles (opts->overlap_rings,
- * default 2) with 16, 32 and 64, and global Jacobi sweeps on meshes of at
- * most 16 tiles -- on the mesh's default workspace and stream, and stores
+ * and 64 in-tile sweeps per pass, overlapping LDS tiles with r and r + 1
+ * rings (r = opts->overlap_rings, 1 if 0) and 32 or 64 sweeps, and global
+ * Jacobi sweeps on meshes of at most 16 tiles -- on the mesh's default
+ * workspace and stream, and stores
  * the fastest one that converges in the mesh: later queries whose
  * diffusion_schedule / inner_sweeps options are 0 (auto) use it.  The
- * arithmetic of every candidate has the same fixed point.  report
+ * arithmetic of every candidate has the same fixed point.  Overlapping tiles
+ * built for the trial are kept only if they are chosen.  The call changes
+ * the mesh: it must not run while other calls use the same mesh.  report
  * (optional) receives the timings. */
 hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
                            void* stream, hg_tune_report* report);

@@ -93,7 +93,7 @@ class TuneReport(C.Structure):
     _fields_ = [
         ("n_candidates", C.c_int32), ("chosen", C.c_int32), ("schedule", C.c_int32 * 8),
         ("inner_sweeps", C.c_int32 * 8), ("ms", C.c_float * 8), ("passes", C.c_int32 * 8),
-        ("reserved", C.c_int32 * 8),
+        ("overlap_rings", C.c_int32 * 8),
     ]
 
 
@@ -343,7 +343,8 @@ class Mesh:
         k = rep.n_candidates
         return {"chosen": rep.chosen,
                 "candidates": [{"schedule": rep.schedule[i], "inner_sweeps": rep.inner_sweeps[i],
-                                "ms": rep.ms[i], "passes": rep.passes[i]} for i in range(k)]}
+                                "overlap_rings": rep.overlap_rings[i], "ms": rep.ms[i], "passes": rep.passes[i]}
+                               for i in range(k)]}
 
     def intrinsic_triangulation(self):
         """(flipped triangles int32[F, 3], edge lengths float64[E] in

@@ -47,8 +47,8 @@ uint64_t Mesh::mesh_bytes() const {
     return face_form + blocked + floc.bytes() + px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() +
-           tile_ptr.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
-           theta_ell.bytes() + tile_order.bytes() + twin.bytes() + h01.bytes() + comp_v.bytes() + tile_comp.bytes();
+           tile_ptr.bytes() + tile_k0.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
+           tile_order.bytes() + twin.bytes() + h01.bytes() + comp_v.bytes() + tile_comp.bytes();
 }
 
 Mesh::~Mesh() = default;
@@ -84,7 +84,6 @@ static hg_opts resolve_opts(const hg_opts* o) {
         throw Error{HG_E_INVALID_ARG, "admm_block must lie in 0..8 (0 = auto)"};
     if (r.admm_block == 0) r.admm_block = kAutoAdmmBlock;
     if (r.overlap_rings < 0 || r.overlap_rings > 4) throw Error{HG_E_INVALID_ARG, "overlap_rings must lie in 0..4"};
-    if (r.overlap_rings == 0) r.overlap_rings = kAutoOverlapRings;
     if (r.diffusion_schedule < 0 || r.diffusion_schedule > 3)
         throw Error{HG_E_INVALID_ARG, "diffusion_schedule must lie in 0..3"};
     if (r.max_sweeps <= 0 || r.max_admm <= 0 || r.check_every <= 0)
@@ -255,6 +254,7 @@ static hg_status create_mesh(const double* xyz, int64_t nv, const int32_t* tri, 
         build_topology(xyz, nv, intrinsic ? idt.tri.data() : tri, nf, 1024, T);
         build_cycles(T);
         std::vector<double> elen, floc;
+        std::vector<int32_t> tile_k0;   // uploaded asynchronously: lives until geometry_init has synchronised
         if (intrinsic) {
             // per internal edge length; per internal face its corners in its
             // own plane, (0,0), (l01,0), (x2,y2) by the law of cosines
@@ -322,6 +322,9 @@ static hg_status create_mesh(const double* xyz, int64_t nv, const int32_t* tri, 
             m->max_halo = T.max_halo;
             m->max_ell_width = T.max_ell_width;
             m->tile_ptr.upload(T.tile_ptr, s);
+            tile_k0.resize(T.tile_ptr.size());
+            for (size_t p = 0; p < tile_k0.size(); ++p) tile_k0[p] = T.row_ptr[T.tile_ptr[p]];
+            m->tile_k0.upload(tile_k0, s);
             m->halo_ptr.upload(T.halo_ptr, s);
             m->halo_idx.upload(T.halo_idx, s);
             m->ell_ptr.upload(T.ell_ptr, s);
@@ -599,15 +602,18 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
         w.ensure_pinned();
         run_bfs(*m, w, si, s);
         struct Cand {
-            int sched, inner;
+            int sched, inner, rings;
         };
         // global Jacobi needs more sweeps than the breadth-first depth: it is a
         // candidate only on meshes of a few tiles (or without tiles)
         std::vector<Cand> cands;
-        if (!patch_supported(*m) || m->n_patches <= 16) cands.push_back({1, 0});
+        if (!patch_supported(*m) || m->n_patches <= 16) cands.push_back({1, 0, 0});
         if (patch_supported(*m)) {
-            for (int inner : {16, 32, 64}) cands.push_back({2, inner});
-            for (int inner : {16, 32, 64}) cands.push_back({3, inner});
+            for (int inner : {16, 32, 64}) cands.push_back({2, inner, 0});
+            const int r0 = o.overlap_rings > 0 ? o.overlap_rings : 1;
+            for (int rings : {r0, r0 + 1})
+                if (rings <= 4)
+                    for (int inner : {32, 64}) cands.push_back({3, inner, rings});
         }
         hg_tune_report rep;
         std::memset(&rep, 0, sizeof(rep));
@@ -617,13 +623,19 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
         HG_CHECK_HIP(hipEventCreate(&a));
         HG_CHECK_HIP(hipEventCreate(&b));
         float best = 0.f;
-        const int saved_sched = m->tuned_schedule, saved_inner = m->tuned_inner;
+        const int saved_sched = m->tuned_schedule, saved_inner = m->tuned_inner, saved_rings = m->tuned_rings;
+        size_t overlap_sets_before;
+        {
+            std::lock_guard<std::mutex> lock(m->ot_mu);
+            overlap_sets_before = m->otiles.size();
+        }
         try {
-            m->tuned_schedule = m->tuned_inner = 0;
+            m->tuned_schedule = m->tuned_inner = m->tuned_rings = 0;
             for (size_t i = 0; i < cands.size(); ++i) {
                 hg_opts oc = o;
                 oc.diffusion_schedule = cands[i].sched;
                 oc.inner_sweeps = cands[i].inner;
+                oc.overlap_rings = cands[i].rings;
                 HG_CHECK_HIP(hipEventRecord(a, s));
                 DiffusionResult dr;
                 try {
@@ -639,6 +651,7 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
                 HG_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
                 rep.schedule[i] = cands[i].sched;
                 rep.inner_sweeps[i] = cands[i].inner;
+                rep.overlap_rings[i] = cands[i].rings;
                 rep.ms[i] = ms;
                 rep.passes[i] = dr.passes;
                 if (dr.converged && (rep.chosen < 0 || ms < best)) {
@@ -649,6 +662,7 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
         } catch (...) {
             m->tuned_schedule = saved_sched;
             m->tuned_inner = saved_inner;
+            m->tuned_rings = saved_rings;
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
             throw;
@@ -658,9 +672,19 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
         if (rep.chosen >= 0) {
             m->tuned_schedule = cands[rep.chosen].sched;
             m->tuned_inner = cands[rep.chosen].inner;
+            m->tuned_rings = cands[rep.chosen].rings;
         } else {
             m->tuned_schedule = saved_sched;
             m->tuned_inner = saved_inner;
+            m->tuned_rings = saved_rings;
+        }
+        // overlapping tiles built only for this trial are not kept unless chosen
+        {
+            HG_CHECK_HIP(hipStreamSynchronize(s));
+            std::lock_guard<std::mutex> lock(m->ot_mu);
+            auto& ot = m->otiles;
+            for (size_t i = ot.size(); i-- > overlap_sets_before;)
+                if (m->tuned_schedule != 3 || ot[i]->rings != m->tuned_rings) ot.erase(ot.begin() + i);
         }
         if (report) *report = rep;
         return rep.chosen >= 0 ? HG_OK : fail(HG_E_NOT_CONVERGED, "no candidate schedule converged");

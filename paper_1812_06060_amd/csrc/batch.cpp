@@ -129,12 +129,12 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
     m.twin.alloc(3 * NF);
     m.h01.alloc(2 * NE);
     m.tile_ptr.alloc(NT + 1);
+    m.tile_k0.alloc(NT + 1);
     m.halo_ptr.alloc(NT + 1);
     m.halo_idx.alloc(ho[n]);
     m.ell_ptr.alloc(NT + 1);
     m.lnb.alloc(lo[n]);
     m.ell_width.alloc(NT);
-    m.theta_ell.alloc(lo[n]);
     m.tile_order.alloc(NT);
     m.comp_v.alloc(NV);
     m.tile_comp.alloc(NT);
@@ -152,7 +152,6 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
         copy_into(m.fsign, fo[i], p.fsign, nf, s);
         copy_into(m.farea, fo[i], p.farea, nf, s);
         copy_into(m.lnb, lo[i], p.lnb, p.lnb.n, s);
-        copy_into(m.theta_ell, lo[i], p.theta_ell, p.lnb.n, s);
         copy_into(m.ell_width, to[i], p.ell_width, nt, s);
         if (m.intrinsic) copy_into(m.floc, 3 * fo[i], p.floc, 3 * nf, s);
         shift_into(m.perm_v.p, vo[i], p.perm_v.p, nv, vo[i], false, s);
@@ -170,6 +169,7 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
         shift_into(m.twin.p, 3 * fo[i], p.twin.p, 3 * nf, 3 * fo[i], true, s);
         shift_into(m.h01.p, 2 * eo[i], p.h01.p, 2 * ne, 3 * fo[i], true, s);
         shift_into(m.tile_ptr.p, to[i], p.tile_ptr.p, nt, vo[i], false, s);
+        shift_into(m.tile_k0.p, to[i], p.tile_k0.p, nt, ko[i], false, s);
         shift_into(m.halo_ptr.p, to[i], p.halo_ptr.p, nt, ho[i], false, s);
         shift_into(m.halo_idx.p, ho[i], p.halo_idx.p, p.halo_idx.n, vo[i], false, s);
         shift_into(m.ell_ptr.p, to[i], p.ell_ptr.p, nt, lo[i], false, s);
@@ -181,6 +181,7 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
         const int32_t tail[4] = {(int32_t)ko[n], (int32_t)NV, (int32_t)ho[n], (int32_t)lo[n]};
         HG_CHECK_HIP(hipMemcpyAsync(m.row_ptr.p + NV, &tail[0], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipMemcpyAsync(m.tile_ptr.p + NT, &tail[1], 4, hipMemcpyHostToDevice, s));
+        HG_CHECK_HIP(hipMemcpyAsync(m.tile_k0.p + NT, &tail[0], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipMemcpyAsync(m.halo_ptr.p + NT, &tail[2], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipMemcpyAsync(m.ell_ptr.p + NT, &tail[3], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipStreamSynchronize(s));   // tail lives on this stack frame

@@ -336,11 +336,10 @@ struct Mesh {
         DBuf<int32_t> halo_ptr, halo_idx, n_ov, ell_ptr, tile_order;
         DBuf<uint8_t> ell_width;
         DBuf<uint16_t> lnb;
-        DBuf<double> theta_ell;
         std::vector<int32_t> color_ptr_host;
         size_t bytes() const {
             return halo_ptr.bytes() + halo_idx.bytes() + n_ov.bytes() + ell_ptr.bytes() + tile_order.bytes() +
-                   ell_width.bytes() + lnb.bytes() + theta_ell.bytes();
+                   ell_width.bytes() + lnb.bytes();
         }
     };
     std::vector<std::unique_ptr<OverlapTileSet>> otiles;
@@ -349,9 +348,9 @@ struct Mesh {
     // patch tiles
     int patch_size = 0, n_patches = 0, max_halo = 0, max_ell_width = 0;
     DBuf<int32_t> tile_ptr, halo_ptr, halo_idx, ell_ptr;
+    DBuf<int32_t> tile_k0;                  // [n_tiles+1] first CSR entry of each tile's rows
     DBuf<uint16_t> lnb;
     DBuf<uint8_t> ell_width;
-    DBuf<double> theta_ell;                 // theta in the tiles' ELL layout
     std::vector<int32_t> color_ptr_host;    // tile colours (see HostTopo)
     DBuf<int32_t> tile_order;
     // connected components (see HostTopo)
@@ -378,7 +377,7 @@ struct Mesh {
 
     // diffusion schedule picked by hg_mesh_autotune for options left at 0
     // (auto): 0 = not tuned
-    int tuned_schedule = 0, tuned_inner = 0;
+    int tuned_schedule = 0, tuned_inner = 0, tuned_rings = 0;
     // default per-query workspace of the synchronous entry points (also
     // used for the mesh's own reductions)
     Work w;
@@ -420,8 +419,6 @@ DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src_
                               const std::vector<double>& t,
                               const hg_opts& o, hipStream_t s);
 void diffusion_logu(Mesh& m, Work& w, hipStream_t s);                   // w.logu from (v, e)
-void build_theta_ell(Mesh& m, hipStream_t s);
-void build_theta_ell_overlap(Mesh& m, Mesh::OverlapTileSet& t, hipStream_t s);
 bool patch_supported(const Mesh& m);
 // overlap > 0: the overlapping tiles with that many rings
 DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inner, hipStream_t s, int overlap = 0);

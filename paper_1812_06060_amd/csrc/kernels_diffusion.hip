@@ -159,7 +159,8 @@ DiffusionResult run_diffusion(Mesh& m, Work& w, const std::vector<int32_t>& src,
     if (patch) {
         if (!patch_supported(m)) throw Error{HG_E_INVALID_ARG, "tiled schedule needs valence <= 16"};
         const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : (m.tuned_inner > 0 ? m.tuned_inner : 32);
-        const int rings = o.overlap_rings > 0 ? o.overlap_rings : kAutoOverlapRings;
+        const int rings =
+            o.overlap_rings > 0 ? o.overlap_rings : (m.tuned_rings > 0 ? m.tuned_rings : kAutoOverlapRings);
         return run_diffusion_patch(m, w, o, inner, s, sched == 3 ? rings : 0);
     }
     return run_diffusion_jacobi(m, w, o, s);

@@ -225,7 +225,6 @@ void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen_host)
     hipLaunchKernelGGL(k_vertex_fill, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, nv, m.row_ptr.p,
                        m.csr_edge.p, m.ef.p, theta_e.p, m.farea.p, m.theta.p, m.sum_theta.p, m.Av.p);
     HG_CHECK_HIP(hipGetLastError());
-    build_theta_ell(m, s);
     HG_CHECK_HIP(hipStreamSynchronize(s));
 }
 

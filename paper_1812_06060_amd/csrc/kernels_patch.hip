@@ -60,13 +60,18 @@ constexpr int kNone = -(1 << 30);   // "no reference exponent yet"
 // back.  Without OV every halo slot is fixed.
 __host__ __device__ constexpr size_t ov_lds_offset(int ntot) { return ((size_t)ntot * 20 + 7) & ~(size_t)7; }
 
+// theta is staged through LDS in chunks of this many rows of kTile doubles
+// (48 KB at valence 6, 64 KB at 8 and above)
+__host__ __device__ constexpr int theta_stage_width(int maxw) { return maxw < 8 ? maxw : 8; }
+
 template <int MAXW, bool OV>
 __device__ __forceinline__ void patch_pass_body(
     const int32_t* __restrict__ tile_list, const double* __restrict__ tile_t, const int32_t* __restrict__ tile_ptr,
     const int32_t* __restrict__ halo_ptr, const int32_t* __restrict__ halo_idx, const int32_t* __restrict__ n_ov,
     const int32_t* __restrict__ ell_ptr, const uint8_t* __restrict__ ell_width, const uint16_t* __restrict__ lnb,
-    const double* __restrict__ theta_ell, const double* __restrict__ invD, const int32_t* __restrict__ level,
-    const double* vin, const int32_t* ein, double* vout, int32_t* eout, int inner, double* __restrict__ partial) {
+    const int32_t* __restrict__ tile_k0, const int32_t* __restrict__ row_ptr, const double* __restrict__ theta,
+    const double* __restrict__ invD, const int32_t* __restrict__ level, const double* vin, const int32_t* ein,
+    double* vout, int32_t* eout, int inner, double* __restrict__ partial) {
     extern __shared__ double lds[];
     __shared__ double shd[kThreads / 64];
     const int p = tile_list[xcd_block(blockIdx.x, gridDim.x)];
@@ -92,22 +97,57 @@ __device__ __forceinline__ void patch_pass_body(
     uint16_t l[kPer][MAXW];
     double b[kPer];
     int Rown[kPer];
+    // The ELL row lists the CSR row in order, and the tile's CSR rows are
+    // one contiguous range of theta: it is read coalesced into LDS (which
+    // holds no state yet), at once for valence <= 8, and each thread picks
+    // its row from there.
+    const int K0 = tile_k0[p];
+    const int nk = tile_k0[p + 1] - K0;
+    int k0[kPer];
+    uint32_t okm[kPer];   // bit s: slot s is a neighbour
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         int i = tid + q * kThreads;
         const bool in = i < np;
-        double id = in ? invD[v0 + i] : 0.0;
-        b[q] = id;
+        b[q] = in ? invD[v0 + i] : 0.0;
+        k0[q] = in ? row_ptr[v0 + i] - K0 : 0;
+        okm[q] = 0;
 #pragma unroll
         for (int s = 0; s < MAXW; ++s) {
             bool ok = in && (s < W);
             uint16_t li = ok ? lnb[eb + s * kTile + i] : (uint16_t)0xFFFF;
             ok = ok && li != 0xFFFF;
             l[q][s] = ok ? li : (uint16_t)0;   // padding reads slot 0 with weight 0
-            const double th = ok ? theta_ell[eb + s * kTile + i] : 0.0;
-            c[q][s] = ok ? t * th * id : 0.0;
+            okm[q] |= ok ? (1u << s) : 0u;
+            c[q][s] = 0.0;
         }
     }
+    constexpr int kChunk = theta_stage_width(MAXW) * kTile;   // doubles
+    for (int cb = 0; cb < nk; cb += kChunk) {
+        const int nc = min(kChunk, nk - cb);
+        if (cb > 0) __syncthreads();
+        double th[kChunk / kThreads];
+#pragma unroll
+        for (int j = 0; j < kChunk / kThreads; ++j) {
+            const int k = tid + j * kThreads;
+            th[j] = k < nc ? theta[K0 + cb + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kChunk / kThreads; ++j) {
+            const int k = tid + j * kThreads;
+            if (k < nc) lds[k] = th[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+#pragma unroll
+            for (int s = 0; s < MAXW; ++s) {
+                const int kk = k0[q] + s - cb;
+                if (((okm[q] >> s) & 1u) && kk >= 0 && kk < nc) c[q][s] = t * lds[kk] * b[q];
+            }
+        }
+    }
+    __syncthreads();   // the chunks' LDS is reused below
     // the overlap row of this thread (OV): vertex halo_idx[h0 + tid], tid < no
     const bool has1 = OV && tid < no;
     const int g1 = has1 ? halo_idx[h0 + tid] : 0;
@@ -115,6 +155,7 @@ __device__ __forceinline__ void patch_pass_body(
     int Rown1 = kNone;
     if (has1) {
         const double id = invD[g1];
+        const int k0 = row_ptr[g1];
         b1 = id;
         const int ob = eb + W * kTile;
         for (int s = 0; s < MAXW; ++s) {
@@ -122,7 +163,7 @@ __device__ __forceinline__ void patch_pass_body(
             uint16_t li = ok ? lnb[ob + s * no + tid] : (uint16_t)0xFFFF;
             ok = ok && li != 0xFFFF;
             ol[s * no + tid] = ok ? li : (uint16_t)0;
-            oc[s * no + tid] = ok ? t * theta_ell[ob + s * no + tid] * id : 0.0;
+            oc[s * no + tid] = ok ? t * theta[k0 + s] * id : 0.0;
         }
     }
 
@@ -301,11 +342,12 @@ __device__ __forceinline__ void patch_pass_body(
         const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo_idx,                                 \
         const int32_t *__restrict__ n_ov, const int32_t *__restrict__ ell_ptr,                                      \
         const uint8_t *__restrict__ ell_width, const uint16_t *__restrict__ lnb,                                    \
-        const double *__restrict__ theta_ell, const double *__restrict__ invD, const int32_t *__restrict__ level,   \
-        const double *vin, const int32_t *ein, double *vout, int32_t *eout, int inner, double *__restrict__ partial
+        const int32_t *__restrict__ tile_k0, const int32_t *__restrict__ row_ptr, const double *__restrict__ theta,  \
+        const double *__restrict__ invD, const int32_t *__restrict__ level, const double *vin, const int32_t *ein,   \
+        double *vout, int32_t *eout, int inner, double *__restrict__ partial
 #define HG_PATCH_FWD                                                                                       \
-    tile_list, tile_t, tile_ptr, halo_ptr, halo_idx, n_ov, ell_ptr, ell_width, lnb, theta_ell, invD, level, vin, \
-        ein, vout, eout, inner, partial
+    tile_list, tile_t, tile_ptr, halo_ptr, halo_idx, n_ov, ell_ptr, ell_width, lnb, tile_k0, row_ptr, theta, invD, \
+        level, vin, ein, vout, eout, inner, partial
 
 // plain tiles: registers as needed (52 at valence 6: two workgroups per CU)
 template <int MAXW>
@@ -319,55 +361,6 @@ __global__ void __launch_bounds__(kThreads, 8) k_patch_pass_ov(HG_PATCH_PARAMS) 
 }
 #undef HG_PATCH_PARAMS
 #undef HG_PATCH_FWD
-
-// theta in the tiles' ELL layout, gathered from the CSR rows (same order);
-// one workgroup per tile.
-__global__ void k_theta_ell(const int32_t* tile_ptr, const int32_t* row_ptr, const double* theta,
-                            const int32_t* ell_ptr, const uint8_t* ell_width, double* theta_ell) {
-    const int p = blockIdx.x;
-    const int v0 = tile_ptr[p], np = tile_ptr[p + 1] - v0;
-    const int W = ell_width[p], eb = ell_ptr[p];
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        int v = v0 + i;
-        int k0 = row_ptr[v], deg = row_ptr[v + 1] - k0;
-        for (int s = 0; s < W; ++s) theta_ell[eb + s * kTile + i] = s < deg ? theta[k0 + s] : 0.0;
-    }
-}
-
-void build_theta_ell(Mesh& m, hipStream_t s) {
-    if (m.patch_size != kTile) throw Error{HG_E_DEVICE, "tile size mismatch"};
-    m.theta_ell.alloc(m.lnb.n);
-    hipLaunchKernelGGL(k_theta_ell, dim3(m.n_patches), dim3(256), 0, s, m.tile_ptr.p, m.row_ptr.p, m.theta.p,
-                       m.ell_ptr.p, m.ell_width.p, m.theta_ell.p);
-    HG_CHECK_HIP(hipGetLastError());
-}
-
-// theta of the overlapping tiles' ELL rows: core rows (stride kTile), then
-// the overlap vertices' rows (stride n_ov)
-__global__ void k_theta_ell_overlap(const int32_t* tile_ptr, const int32_t* row_ptr, const double* theta,
-                                    const int32_t* halo_ptr, const int32_t* halo_idx, const int32_t* n_ov,
-                                    const int32_t* ell_ptr, const uint8_t* ell_width, double* theta_ell) {
-    const int p = blockIdx.x;
-    const int v0 = tile_ptr[p], np = tile_ptr[p + 1] - v0;
-    const int W = ell_width[p], eb = ell_ptr[p], no = n_ov[p], h0 = halo_ptr[p];
-    for (int i = threadIdx.x; i < np + no; i += blockDim.x) {
-        const bool core = i < np;
-        const int j = core ? i : i - np;
-        const int v = core ? v0 + i : halo_idx[h0 + j];
-        const int base = core ? eb : eb + W * kTile;
-        const int stride = core ? kTile : no;
-        const int k0 = row_ptr[v], deg = row_ptr[v + 1] - k0;
-        for (int s = 0; s < W; ++s) theta_ell[base + s * stride + j] = s < deg ? theta[k0 + s] : 0.0;
-    }
-}
-
-void build_theta_ell_overlap(Mesh& m, Mesh::OverlapTileSet& t, hipStream_t s) {
-    if (m.patch_size != kTile) throw Error{HG_E_DEVICE, "tile size mismatch"};
-    t.theta_ell.alloc(t.lnb.n);
-    hipLaunchKernelGGL(k_theta_ell_overlap, dim3(m.n_patches), dim3(256), 0, s, m.tile_ptr.p, m.row_ptr.p,
-                       m.theta.p, t.halo_ptr.p, t.halo_idx.p, t.n_ov.p, t.ell_ptr.p, t.ell_width.p, t.theta_ell.p);
-    HG_CHECK_HIP(hipGetLastError());
-}
 
 static size_t patch_lds_bytes(int max_halo) { return (size_t)(kTile + max_halo) * (8 + 8 + 4); }
 // overlapping tiles: the above (aligned), plus per overlap row maxw
@@ -398,9 +391,11 @@ DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inne
             patch_lds_bytes_ov(ot->max_halo, ot->max_ov, template_width(ot->max_ell_width)) > 65536)
             throw Error{HG_E_INVALID_ARG, "overlapping tiles exceed the valence or LDS limits"};
     }
-    const size_t lds = ot ? patch_lds_bytes_ov(ot->max_halo, ot->max_ov, template_width(ot->max_ell_width))
-                          : patch_lds_bytes(m.max_halo);
     const int maxw = ot ? ot->max_ell_width : m.max_ell_width;
+    // the region, or theta's staging before it, whichever is larger (<= 64 KiB)
+    const size_t lds = std::max(ot ? patch_lds_bytes_ov(ot->max_halo, ot->max_ov, template_width(maxw))
+                                   : patch_lds_bytes(m.max_halo),
+                                (size_t)theta_stage_width(template_width(maxw)) * kTile * sizeof(double));
     const std::vector<int32_t>& color_ptr = ot ? ot->color_ptr_host : m.color_ptr_host;
     const int32_t* order = ot ? ot->tile_order.p : m.tile_order.p;
     const int32_t* halo_ptr = ot ? ot->halo_ptr.p : m.halo_ptr.p;
@@ -409,15 +404,18 @@ DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inne
     const int32_t* ell_ptr = ot ? ot->ell_ptr.p : m.ell_ptr.p;
     const uint8_t* ell_width = ot ? ot->ell_width.p : m.ell_width.p;
     const uint16_t* lnb = ot ? ot->lnb.p : m.lnb.p;
-    const double* theta_ell = ot ? ot->theta_ell.p : m.theta_ell.p;
     DiffusionResult r;
-    // algorithmic bytes of one pass: tile tables (ELL slots + theta), halo
-    // list, 1/D and level, (v, e) read for tile and halo, (v, e) written;
-    // overlap vertices also read their 1/D and level
+    // algorithmic bytes of one pass: tile tables (ELL slots), theta and
+    // row offsets of the CSR rows, halo list, 1/D and level, (v, e) read for
+    // tile and halo, (v, e) written; overlap vertices also read their 1/D,
+    // level, row offset and theta
     const uint64_t ell_n = ot ? ot->lnb.n : m.lnb.n;
     const uint64_t halo_n = ot ? ot->halo_idx.n : m.halo_idx.n;
-    r.bytes_per_pass = ell_n * (2 + 8) + halo_n * (4 + 16) + (uint64_t)nv * (8 + 4 + 12 + 12) +
-                       (uint64_t)nt * (ot ? 21 : 17) + (ot ? (uint64_t)halo_n * 12 : 0);
+    r.bytes_per_pass = ell_n * 2 + (uint64_t)m.col.n * 8 + halo_n * (4 + 16) + (uint64_t)nv * (4 + 8 + 4 + 12 + 12) +
+                       (uint64_t)nt * (ot ? 21 : 17);
+    // overlap rows: their 1/D, level and row offset, and theta for the ELL
+    // entries beyond the plain tiles' (the overlap rows' slots)
+    if (ot) r.bytes_per_pass += halo_n * 12 + (ell_n > m.lnb.n ? (ell_n - m.lnb.n) * 8 : 0);
     double* va = w.v0.p;   // updated in place
     int32_t* ea = w.e0.p;
     const int check = std::max(1, o.check_every / std::max(1, inner / 4));
@@ -431,7 +429,7 @@ DiffusionResult run_diffusion_patch(Mesh& m, Work& w, const hg_opts& o, int inne
             if (nc == 0) continue;
 #define HG_PATCH_ARGS                                                                                           \
     dim3(nc), dim3(kThreads), lds, s, order + c0, w.tile_t.p, m.tile_ptr.p, halo_ptr, halo_idx, n_ov, ell_ptr, \
-        ell_width, lnb, theta_ell, w.invD.p, w.level.p, va, ea, va, ea, inner, w.partial.p
+        ell_width, lnb, m.tile_k0.p, m.row_ptr.p, m.theta.p, w.invD.p, w.level.p, va, ea, va, ea, inner, w.partial.p
             if (ot) {
                 if (maxw <= 6)
                     hipLaunchKernelGGL(k_patch_pass_ov<6>, HG_PATCH_ARGS);

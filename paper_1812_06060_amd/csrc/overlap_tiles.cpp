@@ -183,7 +183,6 @@ const Mesh::OverlapTileSet* Mesh::ensure_overlap_tiles(int rings, int max_ov, si
         set->max_halo = T.max_halo;
         set->max_ov = T.max_ov;
         set->max_ell_width = T.max_ell_width;
-        build_theta_ell_overlap(*this, *set, s);
         HG_CHECK_HIP(hipStreamSynchronize(s));   // other queries may use it once the lock is released
         set->ok = true;
     }
