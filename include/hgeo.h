@@ -400,6 +400,14 @@ hg_status hg_integrate_face(hg_mesh_t mesh, const int32_t* src, int32_t nsrc,
 /* Canonical edge list: DEVICE int32[ne*2] (smaller id, larger id). */
 hg_status hg_mesh_edges(hg_mesh_t mesh, int32_t* edges_dev, void* stream);
 
+/* The mesh's diffusion weights as computed on the device (Sec. 3.1 and the
+ * sweep of Eq. 7): theta_jk = (cot a + cot b)/2 over the edge's one or two
+ * faces, written to DEVICE double[ne] in the canonical edge order of
+ * hg_mesh_edges, and the lumped vertex area A_j (a third of the areas of
+ * the faces around j), written to DEVICE double[nv] in the caller's vertex
+ * order.  Either pointer may be NULL (not both).  Synchronises the stream. */
+hg_status hg_mesh_weights(hg_mesh_t mesh, double* theta_dev, double* area_dev, void* stream);
+
 /* ---- the comparator of Sec. 6.4: the original heat method by CG ----
  *
  * The paper sets its Gauss-Seidel diffusion and ADMM gradient solver against

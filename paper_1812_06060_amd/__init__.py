@@ -14,6 +14,7 @@ from ._hgeo import (  # noqa: F401
     Opts,
     Server,
     default_opts,
+    paper_opts,
     load_library,
     solve_batch,
 )

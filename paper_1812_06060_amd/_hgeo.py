@@ -130,6 +130,7 @@ _API = {
     "hg_integrate_edge": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_integrate_face": [_P, _P, C.c_int32, _P, _P, _P],
     "hg_mesh_edges": [_P, _P, _P],
+    "hg_mesh_weights": [_P, _P, _P, _P],
     "hg_mesh_cycles": [_P, C.c_int32, _P, _P, _P, C.c_int64],
     "hg_mesh_autotune": [_P, _P, C.c_int32, C.c_double, C.POINTER(Opts), _P, C.POINTER(TuneReport)],
     "hg_server_create": [C.c_int32, C.c_uint64, C.POINTER(_P)],
@@ -192,6 +193,16 @@ def default_opts(**kw) -> Opts:
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return o
+
+
+def paper_opts(formulation="edge", **kw) -> Opts:
+    """The paper's own ADMM setting (Sec. 6): ten iterations, penalty
+    mu = 100, no over-relaxation (alpha = 1).  Ten iterations stop far short
+    of the discrete optimum on meshes of many rings, so solves with these
+    options end at the cap (HG_E_NOT_CONVERGED, results written)."""
+    base = dict(formulation=formulation, max_admm=10, mu=100.0, relax=1.0)
+    base.update(kw)
+    return default_opts(**base)
 
 
 def _torch():
@@ -378,6 +389,15 @@ class Mesh:
         out = torch.empty((self.ne, 2), dtype=torch.int32, device="cuda")
         _check(_lib.hg_mesh_edges(self._h, _dptr(out, torch.int32, 2 * self.ne), _stream(stream)))
         return out
+
+    def weights(self, stream=None):
+        """(theta per canonical edge, lumped area per vertex), float64 on the device."""
+        torch = _torch()
+        th = torch.empty(self.ne, dtype=torch.float64, device="cuda")
+        ar = torch.empty(self.nv, dtype=torch.float64, device="cuda")
+        _check(_lib.hg_mesh_weights(self._h, _dptr(th, torch.float64, self.ne), _dptr(ar, torch.float64, self.nv),
+                                    _stream(stream)))
+        return th, ar
 
     def bfs(self, sources, stream=None):
         torch = _torch()

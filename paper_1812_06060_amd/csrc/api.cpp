@@ -449,6 +449,17 @@ hg_status hg_mesh_edges(hg_mesh_t mesh, int32_t* edges_dev, void* stream) {
     });
 }
 
+hg_status hg_mesh_weights(hg_mesh_t mesh, double* theta_dev, double* area_dev, void* stream) {
+    return guarded([&]() -> hg_status {
+        if (!mesh || (!theta_dev && !area_dev)) return fail(HG_E_INVALID_ARG, "null argument");
+        auto* m = reinterpret_cast<Mesh*>(mesh);
+        hipStream_t s = (hipStream_t)stream;
+        weights_to_user(*m, theta_dev, area_dev, s);
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        return HG_OK;
+    });
+}
+
 hg_status hg_bfs(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, int32_t* level_dev, int32_t* parent_dev,
                  void* stream, int32_t* depth_out) {
     return guarded([&]() -> hg_status {

@@ -146,6 +146,12 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri, int64_t n
                     HostTopo& out);
 // Fills the cyc_* loops of a built topology (tree-cotree, caller-id rules).
 void build_cycles(HostTopo& T);
+// Colours of a conflict graph (symmetric adjacency lists, no self loops) by
+// saturation-degree ordering: fewer colours than greedy in index order (five
+// instead of six on the icosphere tiles).  Fills color_ptr [ncol+1] and
+// order (the nodes grouped by colour, ascending within a colour).
+void colour_tiles(const std::vector<std::vector<int32_t>>& adj, std::vector<int32_t>& color_ptr,
+                  std::vector<int32_t>& order);
 
 // Intrinsic Delaunay triangulation (edge flips on intrinsic lengths) of a
 // caller mesh: the flipped triangles (caller vertex ids, rows in the input's
@@ -608,6 +614,7 @@ void gather_vertices_to_internal_d(Mesh& m, const double* user, double* internal
 void scatter_vertices_to_user_i(Mesh& m, const int32_t* internal, int32_t* user, bool map_values,
                                 hipStream_t s);
 void edges_to_user(Mesh& m, int32_t* edges_user, hipStream_t s);
+void weights_to_user(Mesh& m, double* theta_user, double* area_user, hipStream_t s);
 
 // reductions: sum or max of n doubles produced per block into w.partial
 double reduce_partials(Mesh& m, Work& w, int nblocks, bool is_max, hipStream_t s);

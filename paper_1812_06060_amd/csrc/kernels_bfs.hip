@@ -115,7 +115,16 @@ int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, 
                        b.counters);
     HG_CHECK_HIP(hipGetLastError());
     int32_t hc[4];
-    const int grid = std::max(1, std::min(grid_for(nv, kBlockB), 2048));
+    // The grid follows the frontier size last read back (twice it, in
+    // threads): a launch of far more workgroups than frontier vertices costs
+    // more than the expansion itself.  A frontier that has grown since is
+    // still covered, by the kernel's grid-stride loop.
+    const int max_grid = std::max(1, std::min(grid_for(nv, kBlockB), 2048));
+    auto grid_for_frontier = [&](int64_t n) {
+        const int64_t g = (2 * n + kBlockB - 1) / kBlockB;
+        return (int)std::max<int64_t>(std::min(8, max_grid), std::min<int64_t>(max_grid, g));
+    };
+    int grid = grid_for_frontier((int64_t)src.size() * 64);
     for (int L = 0;; ++L) {
         int32_t* fin = (L % 2 == 0) ? b.frontier_a : b.frontier_b;
         int32_t* fout = (L % 2 == 0) ? b.frontier_b : b.frontier_a;
@@ -126,6 +135,7 @@ int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, 
             HG_CHECK_HIP(hipMemcpyAsync(hc, b.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HG_CHECK_HIP(hipStreamSynchronize(s));
             if (hc[(L + 1) % 3] == 0) break;
+            grid = grid_for_frontier(hc[(L + 1) % 3]);
         }
         if (L > nv + 1) break;
     }

@@ -310,6 +310,25 @@ void scatter_vertices_to_user_i(Mesh& m, const int32_t* in, int32_t* out, bool m
                        out, map_values ? 1 : 0);
     HG_CHECK_HIP(hipGetLastError());
 }
+// theta of each edge from its CSR entry at the smaller internal endpoint,
+// into the canonical edge order
+__global__ void k_theta_user(int nv, const int32_t* row_ptr, const int32_t* col, const int32_t* csr_edge,
+                             const double* theta, const int32_t* perm_e, double* out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    for (int k = row_ptr[j]; k < row_ptr[j + 1]; ++k)
+        if (col[k] > j) out[perm_e[csr_edge[k]]] = theta[k];
+}
+
+void weights_to_user(Mesh& m, double* theta_user, double* area_user, hipStream_t s) {
+    if (theta_user) {
+        hipLaunchKernelGGL(k_theta_user, dim3(grid_for(m.nv, kBlock)), dim3(kBlock), 0, s, (int)m.nv, m.row_ptr.p,
+                           m.col.p, m.csr_edge.p, m.theta.p, m.perm_e.p, theta_user);
+        HG_CHECK_HIP(hipGetLastError());
+    }
+    if (area_user) scatter_vertices_to_user_d(m, m.Av.p, area_user, s);
+}
+
 void edges_to_user(Mesh& m, int32_t* out, hipStream_t s) {
     hipLaunchKernelGGL(k_edges_user, dim3(grid_for(m.ne, kBlock)), dim3(kBlock), 0, s, (int)m.ne, m.perm_e.p,
                        m.perm_v.p, m.ev.p, out);

@@ -103,14 +103,27 @@ __device__ __forceinline__ void patch_pass_body(
     // its row from there.
     const int K0 = tile_k0[p];
     const int nk = tile_k0[p + 1] - K0;
+    // Everything a pass reads from HBM is requested here, before the first
+    // barrier, so the loads overlap: the tables, theta, the core's state and
+    // this thread's first fixed-ring entry (the rest, rare, is read where it
+    // is used).  Tiles of one colour never write what another reads, so the
+    // state read now is the state at any point of the pass.
+    const int ih = tid + no;   // this thread's first fixed-ring entry
+    const bool hh = ih < nh;
+    const int hgl = hh ? halo_idx[h0 + ih] : 0;
     int k0[kPer];
     uint32_t okm[kPer];   // bit s: slot s is a neighbour
+    double vown[kPer];
+    int eown[kPer], lown[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         int i = tid + q * kThreads;
         const bool in = i < np;
         b[q] = in ? invD[v0 + i] : 0.0;
         k0[q] = in ? row_ptr[v0 + i] - K0 : 0;
+        vown[q] = in ? vin[v0 + i] : 0.0;
+        eown[q] = in ? ein[v0 + i] : 0;
+        lown[q] = in ? level[v0 + i] : -1;
         okm[q] = 0;
 #pragma unroll
         for (int s = 0; s < MAXW; ++s) {
@@ -122,6 +135,8 @@ __device__ __forceinline__ void patch_pass_body(
             c[q][s] = 0.0;
         }
     }
+    const double hv = hh ? vin[hgl] : 0.0;
+    const int he = hh ? ein[hgl] : 0;
     constexpr int kChunk = theta_stage_width(MAXW) * kTile;   // doubles
     for (int cb = 0; cb < nk; cb += kChunk) {
         const int nc = min(kChunk, nk - cb);
@@ -175,9 +190,8 @@ __device__ __forceinline__ void patch_pass_body(
         int i = tid + q * kThreads;
         int r = kNone;
         if (i < np) {
-            int g = v0 + i;
-            if (vin[g] != 0.0) r = ein[g];
-            if (level[g] == 0) r = max(r, ilogb(b[q]));
+            if (vown[q] != 0.0) r = eown[q];
+            if (lown[q] == 0) r = max(r, ilogb(b[q]));
         }
         Rown[q] = r;
         R[i] = r;
@@ -189,7 +203,8 @@ __device__ __forceinline__ void patch_pass_body(
         Rown1 = r;
         R[kTile + tid] = r;
     }
-    for (int i = tid + no; i < nh; i += kThreads) {
+    if (hh) R[kTile + ih] = hv != 0.0 ? he : kNone;
+    for (int i = ih + kThreads; i < nh; i += kThreads) {
         int g = halo_idx[h0 + i];
         R[kTile + i] = vin[g] != 0.0 ? ein[g] : kNone;
     }
@@ -247,10 +262,8 @@ __device__ __forceinline__ void patch_pass_body(
         const bool live = i < np && rj != kNone;
         double x = 0.0;
         if (live) {
-            int g = v0 + i;
-            double v = vin[g];
-            if (v != 0.0) x = ldexp(v, ein[g] - rj);
-            b[q] = level[g] == 0 ? ldexp(b[q], -rj) : 0.0;
+            if (vown[q] != 0.0) x = ldexp(vown[q], eown[q] - rj);
+            b[q] = lown[q] == 0 ? ldexp(b[q], -rj) : 0.0;
         } else {
             b[q] = 0.0;
         }
@@ -280,10 +293,13 @@ __device__ __forceinline__ void patch_pass_body(
         }
         cur[kTile + tid] = x;
     }
-    for (int i = tid + no; i < nh; i += kThreads) {
-        int g = halo_idx[h0 + i];
-        double v = vin[g];
-        cur[kTile + i] = v;   // the fixed halo's reference exponent is its own
+    if (hh) {
+        cur[kTile + ih] = hv;   // the fixed halo's reference exponent is its own
+        nxt[kTile + ih] = hv;
+    }
+    for (int i = ih + kThreads; i < nh; i += kThreads) {
+        double v = vin[halo_idx[h0 + i]];
+        cur[kTile + i] = v;
         nxt[kTile + i] = v;
     }
     __syncthreads();
@@ -325,7 +341,7 @@ __device__ __forceinline__ void patch_pass_body(
         } else if (x == 0.0) {
             vout[g] = 0.0;
             eout[g] = 0;
-            if (level[g] >= 0) res = 1.0;
+            if (lown[q] >= 0) res = 1.0;
         } else {
             int ex = ilogb(x);
             vout[g] = ldexp(x, -ex);
@@ -349,9 +365,10 @@ __device__ __forceinline__ void patch_pass_body(
     tile_list, tile_t, tile_ptr, halo_ptr, halo_idx, n_ov, ell_ptr, ell_width, lnb, tile_k0, row_ptr, theta, invD, \
         level, vin, ein, vout, eout, inner, partial
 
-// plain tiles: registers as needed (52 at valence 6: two workgroups per CU)
+// plain tiles: held to 64 registers up to valence 8 so that two workgroups
+// fit per CU (55 at valence 6); registers as needed beyond
 template <int MAXW>
-__global__ void __launch_bounds__(kThreads) k_patch_pass(HG_PATCH_PARAMS) {
+__global__ void __launch_bounds__(kThreads, MAXW <= 8 ? 8 : 4) k_patch_pass(HG_PATCH_PARAMS) {
     patch_pass_body<MAXW, false>(HG_PATCH_FWD);
 }
 // overlapping tiles: held to 64 registers so that two workgroups fit per CU

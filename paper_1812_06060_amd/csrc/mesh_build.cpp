@@ -424,33 +424,82 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
         for (int64_t p = 0; p < np; ++p) T.tile_comp[p] = T.comp[T.tile_ptr[p]];
     }
 
-    // ---- greedy colouring of the tiles: a tile's halo lies in its
-    //      neighbour tiles, so tiles of one colour never read each other
+    // ---- colouring of the tiles: a tile's halo lies in its neighbour
+    //      tiles, so tiles of one colour never read each other
     {
         std::vector<int32_t> tile_of(nv);
         for (int64_t p = 0; p < np; ++p)
             for (int32_t v = T.tile_ptr[p]; v < T.tile_ptr[p + 1]; ++v) tile_of[v] = (int32_t)p;
-        std::vector<int32_t> color(np, -1);
-        std::vector<int32_t> mark;
-        int ncol = 0;
-        for (int64_t p = 0; p < np; ++p) {
-            mark.assign(ncol + 1, 0);
+        std::vector<std::vector<int32_t>> adj(np);
+        for (int64_t p = 0; p < np; ++p)
             for (int32_t h = T.halo_ptr[p]; h < T.halo_ptr[p + 1]; ++h) {
-                int32_t c = color[tile_of[T.halo_idx[h]]];
-                if (c >= 0) mark[c] = 1;
+                const int32_t q = tile_of[T.halo_idx[h]];
+                adj[p].push_back(q);
+                adj[q].push_back((int32_t)p);
             }
-            int c = 0;
-            while (mark[c]) ++c;
-            color[p] = c;
-            ncol = std::max(ncol, c + 1);
+        for (auto& a : adj) {
+            std::sort(a.begin(), a.end());
+            a.erase(std::unique(a.begin(), a.end()), a.end());
         }
-        T.color_ptr.assign(ncol + 1, 0);
-        for (int64_t p = 0; p < np; ++p) T.color_ptr[color[p] + 1]++;
-        for (int c = 0; c < ncol; ++c) T.color_ptr[c + 1] += T.color_ptr[c];
-        T.tile_order.assign(np, 0);
-        std::vector<int32_t> pos(T.color_ptr.begin(), T.color_ptr.end() - 1);
-        for (int64_t p = 0; p < np; ++p) T.tile_order[pos[color[p]]++] = (int32_t)p;
+        colour_tiles(adj, T.color_ptr, T.tile_order);
     }
+}
+
+void colour_tiles(const std::vector<std::vector<int32_t>>& adj, std::vector<int32_t>& color_ptr,
+                  std::vector<int32_t>& order) {
+    const int64_t n = (int64_t)adj.size();
+    std::vector<int32_t> color(n, -1);
+    // per node: the set of its neighbours' colours (a bit mask while the
+    // colours fit 64 bits, a list beyond) and its saturation (their count)
+    std::vector<uint64_t> seen(n, 0);
+    std::vector<std::vector<int32_t>> seen_hi(n);
+    std::vector<int32_t> sat(n, 0);
+    auto has = [&](int64_t v, int c) {
+        if (c < 64) return ((seen[v] >> c) & 1u) != 0;
+        return std::find(seen_hi[v].begin(), seen_hi[v].end(), c) != seen_hi[v].end();
+    };
+    // pick: largest saturation, then largest degree, then smallest index;
+    // a max-heap with lazy deletion of stale entries
+    struct Key {
+        int32_t sat, deg;
+        int64_t v;
+        bool operator<(const Key& o) const {
+            if (sat != o.sat) return sat < o.sat;
+            if (deg != o.deg) return deg < o.deg;
+            return v > o.v;
+        }
+    };
+    std::vector<Key> heap;
+    heap.reserve(n);
+    for (int64_t v = 0; v < n; ++v) heap.push_back({0, (int32_t)adj[v].size(), v});
+    std::make_heap(heap.begin(), heap.end());
+    int ncol = 0;
+    while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end());
+        const Key k = heap.back();
+        heap.pop_back();
+        const int64_t v = k.v;
+        if (color[v] >= 0 || k.sat != sat[v]) continue;   // stale
+        int c = 0;
+        while (has(v, c)) ++c;
+        color[v] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int32_t u : adj[v]) {
+            if (color[u] >= 0 || has(u, c)) continue;
+            if (c < 64)
+                seen[u] |= (uint64_t)1 << c;
+            else
+                seen_hi[u].push_back(c);
+            heap.push_back({++sat[u], (int32_t)adj[u].size(), u});
+            std::push_heap(heap.begin(), heap.end());
+        }
+    }
+    color_ptr.assign(ncol + 1, 0);
+    for (int64_t v = 0; v < n; ++v) color_ptr[color[v] + 1]++;
+    for (int c = 0; c < ncol; ++c) color_ptr[c + 1] += color_ptr[c];
+    order.assign(n, 0);
+    std::vector<int32_t> pos(color_ptr.begin(), color_ptr.end() - 1);
+    for (int64_t v = 0; v < n; ++v) order[pos[color[v]]++] = (int32_t)v;
 }
 
 }  // namespace hg

@@ -138,23 +138,11 @@ bool build_overlap_tiles(const std::vector<int32_t>& row_ptr, const std::vector<
                 conf[q].push_back((int32_t)p);
             }
     }
-    std::vector<int32_t> color(np, -1), used;
-    int ncol = 0;
-    for (int64_t p = 0; p < np; ++p) {
-        used.assign(ncol + 1, 0);
-        for (int32_t q : conf[p])
-            if (color[q] >= 0) used[color[q]] = 1;
-        int c = 0;
-        while (used[c]) ++c;
-        color[p] = c;
-        ncol = std::max(ncol, c + 1);
+    for (auto& a : conf) {
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
     }
-    out.color_ptr.assign(ncol + 1, 0);
-    for (int64_t p = 0; p < np; ++p) out.color_ptr[color[p] + 1]++;
-    for (int c = 0; c < ncol; ++c) out.color_ptr[c + 1] += out.color_ptr[c];
-    out.tile_order.assign(np, 0);
-    std::vector<int32_t> pos(out.color_ptr.begin(), out.color_ptr.end() - 1);
-    for (int64_t p = 0; p < np; ++p) out.tile_order[pos[color[p]]++] = (int32_t)p;
+    colour_tiles(conf, out.color_ptr, out.tile_order);
     return true;
 }
 

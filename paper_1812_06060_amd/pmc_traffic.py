@@ -27,10 +27,13 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# kernel name fragment -> (source file, launches per diffusion pass or None)
+# record name -> (kernel name fragment, source file, launches per diffusion
+# pass or None); the fragments end at the template bracket so that
+# k_patch_pass does not also match k_patch_pass_ov
 KERNELS = {
-    "k_admm_edge_tiled": ("paper_1812_06060_amd/csrc/kernels_admm.hip", None),
-    "k_patch_pass": ("paper_1812_06060_amd/csrc/kernels_patch.hip", "colours"),
+    "k_admm_edge_tiled": ("k_admm_edge_tiled<", "paper_1812_06060_amd/csrc/kernels_admm.hip", None),
+    "k_patch_pass": ("k_patch_pass<", "paper_1812_06060_amd/csrc/kernels_patch.hip", "colours"),
+    "k_patch_pass_ov": ("k_patch_pass_ov<", "paper_1812_06060_amd/csrc/kernels_patch.hip", None),
 }
 COPY_KERNEL = "copyBuffer"
 
@@ -79,7 +82,7 @@ def main(argv=None):
     write = per_dispatch(a.write, "WRITE_SIZE")
     out = {"_scale": {"fetch": sf, "write": sw, "copy_fetch_kib_raw": cf, "copy_write_kib_raw": cw,
                       "copy_kernel": COPY_KERNEL}}
-    for frag, (src, per_pass) in KERNELS.items():
+    for key, (frag, src, per_pass) in KERNELS.items():
         f, nf = mean_for(fetch, frag)
         w, nw = mean_for(write, frag)
         if f is None or w is None:
@@ -90,7 +93,7 @@ def main(argv=None):
         if per_pass:
             rec["launches_per_pass"] = a.colours
             rec["bytes_per_pass"] = rec["bytes_per_launch"] * a.colours
-        out[frag] = rec
+        out[key] = rec
     with open(a.out, "w") as fh:
         json.dump(out, fh, indent=1)
     json.dump(out, sys.stdout, indent=1)

@@ -65,6 +65,22 @@ def test_mesh_stats_and_edges(case):
     assert np.array_equal(e, rf.topo.edges.astype(np.int32))
 
 
+def test_mesh_weights(case):
+    """theta_jk and A_j as the device computed them (Sec. 3.1) against the
+    oracle's assembly: theta_jk = -K_jk of the cotangent stiffness matrix,
+    A_j the lumped area."""
+    name, v, f, src, mesh, rf, _ = case
+    _say(name, "weights")
+    th, ar = mesh.weights()
+    th, ar = th.cpu().numpy(), ar.cpu().numpy()
+    _, K, A, _ = pipeline.prepare(v, f)
+    e = rf.topo.edges
+    th_ref = -np.asarray(K[e[:, 0], e[:, 1]]).ravel()
+    scale = np.abs(th_ref).max()
+    assert np.abs(th - th_ref).max() <= 1e-12 * scale
+    assert np.abs(ar - A).max() <= 1e-13 * A.max()
+
+
 def test_bfs_bit_exact(case):
     name, v, f, src, mesh, rf, _ = case
     _say(name, "bfs")

@@ -106,6 +106,7 @@ def test_mesh_readback_rejects_null_arguments(lib):
     buf_d = (C.c_double * 4)()
     assert lib.hg_mesh_cycles(None, _hgeo.FORM_EDGE, buf_i, buf_i, buf_f, 4) == _hgeo.HG_E_INVALID_ARG
     assert lib.hg_mesh_intrinsic(None, buf_i, buf_d) == _hgeo.HG_E_INVALID_ARG
+    assert lib.hg_mesh_weights(None, buf_d, buf_d, None) == _hgeo.HG_E_INVALID_ARG
 
 
 def test_null_and_empty_arguments(lib):
