@@ -1,10 +1,12 @@
 // Breadth-first vertex sets D_i (Eq. 6) and the pairing of every vertex with
 // a neighbour one set closer to the sources (Sec. 3.3; Sec. 5.2 puts all
-// sources in D_0).  Level-synchronous frontier expansion: one launch per
-// level, frontier membership claimed with atomicCAS on the level array (the
-// levels are unique, so the result does not depend on timing); the pairing
-// is then chosen per vertex as the neighbour of level - 1 with the smallest
-// caller vertex id, which is deterministic.
+// sources in D_0).  Two schedules give the same levels: on meshes with
+// diffusion tiles, min-plus relaxation over the tiles (below); otherwise
+// level-synchronous frontier expansion, one launch per level, frontier
+// membership claimed with atomicCAS on the level array (the levels are
+// unique, so the result does not depend on timing).  The pairing is then
+// chosen per vertex as the neighbour of level - 1 with the smallest caller
+// vertex id, which is deterministic.
 #include "hgeo_internal.h"
 
 namespace hg {
@@ -147,6 +149,140 @@ int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, 
     return hc[3];   // deepest level whose frontier was non-empty
 }
 
+// ---------------------------------------------------------------- tiled
+// The same levels as the shortest hop counts from the sources (D_i = the
+// vertices at hop distance i, Eq. 6), found by min-plus relaxation
+// level_j = min(level_j, level_k + 1) over the diffusion tiles: per colour
+// one launch, each tile relaxing its vertices in LDS until nothing changes
+// (its halo held), passes until no tile changes over a whole pass.  The
+// fixed point is unique, so the levels equal the level-synchronous search's
+// exactly; about depth / (rings crossed per pass) passes instead of depth
+// dependent launches.  The pairing is chosen afterwards as before.
+constexpr int kTileB = 1024;         // vertices per diffusion tile
+constexpr int32_t kFar = 0x3fffffff;   // not reached (yet)
+
+template <int MAXW>
+__global__ void __launch_bounds__(kTileB) k_bfs_tile(const int32_t* __restrict__ tile_list,
+                                                     const int32_t* __restrict__ tile_ptr,
+                                                     const int32_t* __restrict__ halo_ptr,
+                                                     const int32_t* __restrict__ halo_idx,
+                                                     const int32_t* __restrict__ ell_ptr,
+                                                     const uint8_t* __restrict__ ell_width,
+                                                     const uint16_t* __restrict__ lnb, int32_t* level,
+                                                     int32_t* changes) {
+    extern __shared__ int32_t lv[];   // the core's slots, then the halo's
+    const int p = tile_list[xcd_block(blockIdx.x, gridDim.x)];
+    const int v0 = tile_ptr[p], np = tile_ptr[p + 1] - v0;
+    const int h0 = halo_ptr[p], nh = halo_ptr[p + 1] - h0;
+    const int W = ell_width[p], eb = ell_ptr[p];
+    const int tid = threadIdx.x;
+    const bool in = tid < np;
+    int own = in ? level[v0 + tid] : kFar;
+    uint16_t l[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const bool ok = in && k < W;
+        const uint16_t li = ok ? lnb[eb + k * kTileB + tid] : (uint16_t)0xFFFF;
+        l[k] = li != 0xFFFF ? li : (uint16_t)tid;   // padding reads the own slot: no effect
+    }
+    for (int j = tid; j < nh; j += kTileB) lv[kTileB + j] = level[halo_idx[h0 + j]];
+    lv[tid] = own;
+    __syncthreads();
+    const int start = own;
+    // in-place updates in any order reach the same least fixed point; it is
+    // reached within as many rounds as the tile has vertices
+    for (int round = 0; round <= kTileB; ++round) {
+        int best = own;
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) best = min(best, lv[l[k]] + 1);
+        const int ch = best < own;
+        if (ch) {
+            own = best;
+            lv[tid] = best;
+        }
+        if (!__syncthreads_or(ch)) break;
+    }
+    const int moved = in && own != start;
+    if (moved) level[v0 + tid] = own;
+    if (__syncthreads_or(moved) && tid == 0) atomicAdd(changes, 1);
+}
+
+__global__ void k_bfs_seed(int nv, int32_t* level, int32_t* counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nv) level[i] = kFar;
+    if (i < 8) counters[i] = 0;
+}
+__global__ void k_bfs_seed_sources(int nsrc, const int32_t* src, int32_t* level) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nsrc) level[src[i]] = 0;
+}
+// unreached back to -1; the deepest level into counters[3]
+__global__ void k_bfs_tile_finish(int nv, int32_t* level, int32_t* counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int d = 0;
+    if (i < nv) {
+        int v = level[i];
+        if (v >= kFar) level[i] = -1;
+        else d = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_down(d, o, 64));
+    if ((threadIdx.x & 63) == 0 && d > 0) atomicMax(&counters[3], d);
+}
+
+static bool bfs_tiles_supported(const Mesh& m) {
+    return m.patch_size == kTileB && m.n_patches > 0 && m.max_ell_width <= 16 &&
+           (size_t)(kTileB + m.max_halo) * 4 <= 65536;
+}
+
+static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, hipStream_t s) {
+    const int nv = (int)m.nv;
+    HG_CHECK_HIP(hipMemcpyAsync(b.src, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bfs_seed, dim3(grid_for(std::max(nv, 8), kBlockB)), dim3(kBlockB), 0, s, nv, b.level,
+                       b.counters);
+    hipLaunchKernelGGL(k_bfs_seed_sources, dim3(grid_for((int64_t)src.size(), kBlockB)), dim3(kBlockB), 0, s,
+                       (int)src.size(), b.src, b.level);
+    HG_CHECK_HIP(hipGetLastError());
+    const size_t lds = (size_t)(kTileB + m.max_halo) * sizeof(int32_t);
+    const int maxw = m.max_ell_width;
+    const std::vector<int32_t>& cp = m.color_ptr_host;
+    const int ncol = (int)cp.size() - 1;
+    // a pass can move the front by as little as one ring, so depth + 1
+    // passes always suffice; checks read the change count every few passes
+    constexpr int kCheck = 4;
+    int32_t hc[4];
+    int32_t last = -1;
+    for (int pass = 0;; ++pass) {
+        for (int c = 0; c < ncol; ++c) {
+            const int nc = cp[c + 1] - cp[c];
+            if (nc == 0) continue;
+#define HG_BFS_TILE_ARGS                                                                                               dim3(nc), dim3(kTileB), lds, s, m.tile_order.p + cp[c], m.tile_ptr.p, m.halo_ptr.p, m.halo_idx.p, m.ell_ptr.p,         m.ell_width.p, m.lnb.p, b.level, b.counters
+            if (maxw <= 6)
+                hipLaunchKernelGGL(k_bfs_tile<6>, HG_BFS_TILE_ARGS);
+            else if (maxw <= 8)
+                hipLaunchKernelGGL(k_bfs_tile<8>, HG_BFS_TILE_ARGS);
+            else
+                hipLaunchKernelGGL(k_bfs_tile<16>, HG_BFS_TILE_ARGS);
+#undef HG_BFS_TILE_ARGS
+        }
+        HG_CHECK_HIP(hipGetLastError());
+        if (pass % kCheck == kCheck - 1) {
+            HG_CHECK_HIP(hipMemcpyAsync(hc, b.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HG_CHECK_HIP(hipStreamSynchronize(s));
+            if (hc[0] == last) break;   // no tile changed over the last kCheck passes
+            last = hc[0];
+        }
+        if (pass > nv + kCheck) throw Error{HG_E_DEVICE, "tiled breadth-first search did not settle"};
+    }
+    hipLaunchKernelGGL(k_bfs_tile_finish, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, b.level,
+                       b.counters);
+    hipLaunchKernelGGL(k_bfs_parent, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, m.row_ptr.p, m.col.p,
+                       b.level, m.perm_v.p, b.parent, b.pslot);
+    HG_CHECK_HIP(hipGetLastError());
+    HG_CHECK_HIP(hipMemcpyAsync(hc, b.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HG_CHECK_HIP(hipStreamSynchronize(s));
+    return hc[3];
+}
+
 int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src, hipStream_t s) {
     const int nv = (int)m.nv;
     w.level.alloc(nv);
@@ -157,7 +293,7 @@ int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src, hipStream_t s) {
     w.counters.alloc(8);
     w.src.alloc(src.size());
     BfsBuffers b{w.level.p, w.parent.p, w.pslot.p, w.frontier_a.p, w.frontier_b.p, w.counters.p, w.src.p};
-    return run_bfs_into(m, b, src, s);
+    return bfs_tiles_supported(m) ? run_bfs_tiles(m, b, src, s) : run_bfs_into(m, b, src, s);
 }
 
 }  // namespace hg
