@@ -127,9 +127,13 @@ def run_fields(n_fields: int = 64, slots: int = 8, log=print, batched: bool = Fa
         torch.cuda.synchronize()
         t_b = time.perf_counter() - t0
         worst = max(float(np.abs(d.cpu().numpy() - r).max() / r.max()) for d, r in zip(ds, ref))
-        log(f"[fields] one batched solve: {t_b:.2f} s (passes {info.passes}, ADMM {info.admm_iters}); "
+        log(f"[fields] one batched solve: {t_b:.2f} s (passes {info.passes}, ADMM {info.admm_iters}; "
+            f"bfs {info.ms_bfs:.0f} ms, diffusion {info.ms_diffusion:.0f} ms, ADMM {info.ms_admm:.0f} ms of which "
+            f"kernel {info.ms_admm_kernel:.0f} ms in {info.admm_launches} launches); "
             f"largest difference from the fields alone {worst:.2e} of the diameter")
         out["batched"] = {"s": t_b, "fields_per_s": len(src) / t_b, "passes": info.passes,
+                          "stage_ms": {"bfs": info.ms_bfs, "diffusion": info.ms_diffusion, "admm": info.ms_admm,
+                                       "admm_kernel": info.ms_admm_kernel},
                           "admm_iters": info.admm_iters, "mesh_bytes": int(len(src) * mesh.mesh_bytes()),
                           "max_diff_vs_alone_over_diam": worst}
         b.close()

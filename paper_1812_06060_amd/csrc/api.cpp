@@ -20,7 +20,8 @@ size_t Work::bytes() const {
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
            h.bytes() + sumz.bytes() + sumd.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
-           src.bytes() + dprev.bytes() + paths.bytes() + tcomp.bytes() + tile_t.bytes() + cg.bytes();
+           src.bytes() + dprev.bytes() + comp_pair.bytes() + tile_on.bytes() + cflag.bytes() + paths.bytes() +
+           tcomp.bytes() + tile_t.bytes() + cg.bytes();
 }
 
 size_t Work::Paths::bytes() const {

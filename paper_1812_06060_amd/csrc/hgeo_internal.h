@@ -261,6 +261,9 @@ struct Work {
     DBuf<float> shi0, slo0, shi1, slo1; // integration double-float sums
     DBuf<int32_t> jp0, jp1;             // pointer-jumping parents
     DBuf<float> dprev;                  // distance at the previous ADMM check
+    DBuf<double> comp_pair;             // per component (largest change, largest d) of a check
+    DBuf<uint8_t> tile_on, cflag;       // ADMM tiles still iterating; per component 0 active,
+                                        // 1 stopping now, 2 stopped
     DBuf<double> partial;               // reduction partials
     DBuf<double> red_host_dummy;
     double* pinned = nullptr;           // host pinned reduction results
@@ -533,6 +536,9 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
 // the largest |d_head - d_tail - x_e| for the d of the last dist_change and
 // the given field (the same state)
 double seam_now(Mesh& m, Work& w, int form, const float* xe, const float* g, hipStream_t s);
+// As dist_change, per connected component (delta[c], dmax[c]).
+void dist_change_comp(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first,
+                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax);
 
 // Stopping rule on the distance field: with delta_k the largest change of d
 // between two checks and r = delta_k / delta_{k-1} < 1, the remaining change

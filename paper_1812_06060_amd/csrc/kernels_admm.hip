@@ -284,9 +284,11 @@ template <int PER>
 __global__ void __launch_bounds__(kBlockT, 8) k_admm_edge_tiled(
     const int32_t* __restrict__ f0, const int32_t* __restrict__ rptr, const int32_t* __restrict__ halo,
     const uint64_t* __restrict__ rec, const float* __restrict__ sumd, const float* __restrict__ zin,
-    float* __restrict__ zout, float* __restrict__ zprev, int iters, float rmu, float c, float mu_relax) {
+    float* __restrict__ zout, float* __restrict__ zprev, int iters, float rmu, float c, float mu_relax,
+    const uint8_t* __restrict__ tile_on) {
     extern __shared__ float zl[];   // 3 copies per region face
     const int p = xcd_block(blockIdx.x, gridDim.x);
+    if (tile_on && !tile_on[p]) return;   // a stopped component (the same for the whole workgroup)
     const int a = f0[p], nint = f0[p + 1] - a;
     const int rb = rptr[p], nreg = rptr[p + 1] - rb;
     if (nint == 0) return;   // the same for the whole workgroup
@@ -361,6 +363,25 @@ __global__ void __launch_bounds__(kBlockT, 8) k_admm_edge_tiled(
     }
     for (int r = tid; r < nint; r += kBlockT)
         for (int k = 0; k < 3; ++k) zout[3 * (a + r) + k] = cur[3 * r + k];
+}
+
+// A component that stops (cflag 1): its faces' state copied into the other
+// buffer and the one-iteration-back buffer, so that launches that skip its
+// tiles leave it in place; tile_on follows the flags.
+__global__ void k_freeze_faces(int nf, const int32_t* __restrict__ tri, const int32_t* __restrict__ comp,
+                               const uint8_t* __restrict__ cflag, const float* __restrict__ za, float* zb,
+                               float* zback) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf || cflag[comp[tri[3 * f]]] != 1) return;
+    for (int k = 0; k < 3; ++k) {
+        zb[3 * f + k] = za[3 * f + k];
+        zback[3 * f + k] = za[3 * f + k];
+    }
+}
+__global__ void k_tiles_on(int nt, const int32_t* __restrict__ tile_comp, const uint8_t* __restrict__ cflag,
+                           uint8_t* tile_on) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nt) tile_on[p] = cflag ? (uint8_t)(cflag[tile_comp[p]] == 0) : (uint8_t)1;
 }
 
 // r_p = w' - x' with w' = x + (zeta' - zeta)/(mu alpha) (from the zeta
@@ -647,6 +668,26 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         if ((tiles = m.ensure_edge_tiles(k, s))) K = k;
     const int per = tiles ? (tiles->max_region + kBlockT - 1) / kBlockT : 0;
     r.block = K;
+    // Several connected components (meshes joined into one batch): each
+    // stops on its own distance check, and its tiles then sit out the
+    // remaining launches (its state is copied into both buffers first, so
+    // the skipped launches leave it in place).  A face tile's component is
+    // its vertex tile's.
+    const int ncomp = std::max(1, m.n_comp);
+    const bool percomp =
+        monitor && tiles && !use_paths && ncomp > 1 && o.tol_seam <= 0.0 && tiles->n == m.n_patches;
+    std::vector<DistStop> cstop;
+    std::vector<uint8_t> cflag_h;
+    if (percomp) {
+        w.tile_on.alloc((size_t)tiles->n);
+        w.cflag.alloc((size_t)ncomp);
+        hipLaunchKernelGGL(k_tiles_on, dim3(grid_for(tiles->n, kBlockA)), dim3(kBlockA), 0, s, tiles->n,
+                           m.tile_comp.p, nullptr, w.tile_on.p);
+        HG_CHECK_HIP(hipGetLastError());
+        cstop.assign((size_t)ncomp, DistStop());
+        cflag_h.assign((size_t)ncomp, 0);
+    }
+    const uint8_t* tile_on = percomp ? w.tile_on.p : nullptr;
     const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
     // iterations between two checks: one chunk, or kCoarseChecks chunks far
     // from convergence (DistStop)
@@ -704,7 +745,7 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     case P:                                                                                                      \
         hipLaunchKernelGGL(k_admm_edge_tiled<P>, dim3(tiles->n), dim3(kBlockT), lds, s, tiles->f0.p,             \
                            tiles->rptr.p, tiles->halo.p, tiles->rec.p, w.sumd.p, zi, zo, zp, n, rmu, chalf,        \
-                           mu_relax);                                                                            \
+                           mu_relax, tile_on);                                                                   \
         break;
             HG_TILED(1)
             HG_TILED(2)
@@ -772,7 +813,46 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         const bool want = it >= next_check || it == cap;
         if (!fixed && want) {
             bool done;
-            if (monitor) {
+            if (percomp) {
+                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
+                                   w.xe.p);
+                std::vector<double> dl, dm;
+                dist_change_comp(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, dl, dm);
+                stop.first = false;
+                bool stopping = false, all_far = true, any_near = false;
+                done = true;
+                for (int c = 0; c < ncomp; ++c) {
+                    if (cflag_h[c] != 0) {
+                        cflag_h[c] = 2;
+                        continue;
+                    }
+                    if (cstop[c].update(dl[c], dm[c], o.tol_admm)) {
+                        cflag_h[c] = 1;
+                        stopping = true;
+                        continue;
+                    }
+                    done = false;
+                    all_far = all_far && cstop[c].far(dm[c], o.tol_admm);
+                    any_near = any_near || cstop[c].near(dm[c], o.tol_admm);
+                }
+                if (!done && stopping) {
+                    HG_CHECK_HIP(hipMemcpyAsync(w.cflag.p, cflag_h.data(), (size_t)ncomp, hipMemcpyHostToDevice, s));
+                    hipLaunchKernelGGL(k_freeze_faces, dim3(gf), dim3(kBlockA), 0, s, nf, m.tri.p, m.comp_v.p,
+                                       w.cflag.p, za, zb, zback);
+                    hipLaunchKernelGGL(k_tiles_on, dim3(grid_for(tiles->n, kBlockA)), dim3(kBlockA), 0, s,
+                                       tiles->n, m.tile_comp.p, w.cflag.p, w.tile_on.p);
+                    HG_CHECK_HIP(hipGetLastError());
+                    // cflag_h is read by the copy before the next check rewrites it
+                    HG_CHECK_HIP(hipStreamSynchronize(s));
+                }
+                if (!done && interval == check && all_far) {
+                    interval = kCoarseChecks * check;
+                    for (auto& cs : cstop) cs.restart();
+                } else if (!done && interval > check && any_near) {
+                    interval = check;
+                    for (auto& cs : cstop) cs.restart();
+                }
+            } else if (monitor) {
                 hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
                                    w.xe.p);
                 double delta, dmax;

@@ -179,6 +179,51 @@ __global__ void k_dist_delta(int nv, const int32_t* jp, const float* shi, const 
     }
 }
 
+// Per connected component: the largest |d - d_prev| and the largest d, as
+// atomic maxima on the bit patterns (non-negative doubles order as their
+// bits).  A block whose vertices lie in one component (the usual case: the
+// components of a joined batch are contiguous) reduces first.
+__global__ void k_dist_delta_comp(int nv, const int32_t* jp, const float* shi, const float* slo, float* dprev,
+                                  int first, const int32_t* comp, unsigned long long* comp_pair) {
+    __shared__ double sh[kBlockI / 64];
+    __shared__ int c_first, mixed;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double dl = 0.0, mx = 0.0;
+    int c = -1;
+    if (j < nv) {
+        c = comp[j];
+        if (jp[j] >= 0) {
+            float d = shi[j] + slo[j];
+            dl = first ? INFINITY : fabs((double)d - (double)dprev[j]);
+            mx = fabs((double)d);
+            dprev[j] = d;
+        }
+    }
+    if (threadIdx.x == 0) {
+        c_first = c;
+        mixed = 0;
+    }
+    __syncthreads();
+    if (c >= 0 && c != c_first) mixed = 1;
+    __syncthreads();
+    if (!mixed) {
+        dl = blk_max2(dl, sh);
+        mx = blk_max2(mx, sh);
+        if (threadIdx.x == 0 && c_first >= 0) {
+            atomicMax(&comp_pair[2 * c_first], (unsigned long long)__double_as_longlong(dl));
+            atomicMax(&comp_pair[2 * c_first + 1], (unsigned long long)__double_as_longlong(mx));
+        }
+    } else if (c >= 0) {
+        atomicMax(&comp_pair[2 * c], (unsigned long long)__double_as_longlong(dl));
+        atomicMax(&comp_pair[2 * c + 1], (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+__global__ void k_zero_u64(int n, unsigned long long* a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0ull;
+}
+
 __global__ void k_reduce_pairs_max(double* partial, int n) {
     __shared__ double sh[kBlockI / 64];
     double a = 0.0, b = 0.0;
@@ -246,6 +291,28 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
     delta = w.pinned[0];
     dmax = w.pinned[1];
     if (seam) *seam = seam_now(m, w, form, xe, g, s);
+}
+
+void dist_change_comp(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first,
+                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax) {
+    const int nv = (int)m.nv, nc = std::max(1, m.n_comp);
+    w.dprev.alloc(nv);
+    w.comp_pair.alloc((size_t)2 * nc);
+    IntSums r = integrate_sums(m, w, form, depth, xe, g, s);
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(2 * nc, kBlockI)), dim3(kBlockI), 0, s, 2 * nc,
+                       reinterpret_cast<unsigned long long*>(w.comp_pair.p));
+    hipLaunchKernelGGL(k_dist_delta_comp, dim3(grid_for(nv, kBlockI)), dim3(kBlockI), 0, s, nv, r.jp, r.hi, r.lo,
+                       w.dprev.p, first ? 1 : 0, m.comp_v.p, reinterpret_cast<unsigned long long*>(w.comp_pair.p));
+    HG_CHECK_HIP(hipGetLastError());
+    std::vector<double> h((size_t)2 * nc);
+    HG_CHECK_HIP(hipMemcpyAsync(h.data(), w.comp_pair.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HG_CHECK_HIP(hipStreamSynchronize(s));
+    delta.resize(nc);
+    dmax.resize(nc);
+    for (int c = 0; c < nc; ++c) {
+        delta[c] = h[2 * c];
+        dmax[c] = h[2 * c + 1];
+    }
 }
 
 double seam_now(Mesh& m, Work& w, int form, const float* xe, const float* g, hipStream_t s) {

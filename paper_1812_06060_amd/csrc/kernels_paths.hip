@@ -116,9 +116,41 @@ void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_in
     std::vector<float> h_sign, h_vec;
     DBuf<int32_t> d_src, d_lvl, d_base, d_len, d_vert, d_edge, d_face;
     DBuf<float> d_sign, d_vec;
-    while (todo.size() > 1) {
-        run_bfs(m, w, {todo[0]}, s);
-        std::vector<int32_t> rest(todo.begin() + 1, todo.end());
+    // The sources' components: the first source of each is its root, and one
+    // breadth-first search from the roots of the components holding other
+    // sources gives every such component its own tree (components do not
+    // touch).  The other sources are taken component by component, in order
+    // of first appearance, each in the order given.
+    std::vector<int32_t> rest, roots;
+    if (todo.size() > 1) {
+        const int nt = (int)todo.size();
+        d_src.upload(todo, s);
+        d_lvl.alloc(nt);
+        hipLaunchKernelGGL(k_gather_level, dim3(grid_for(nt, kBlockP)), dim3(kBlockP), 0, s, nt, d_src.p, m.comp_v.p,
+                           d_lvl.p);
+        HG_CHECK_HIP(hipGetLastError());
+        std::vector<int32_t> comp(nt);
+        HG_CHECK_HIP(hipMemcpyAsync(comp.data(), d_lvl.p, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HG_CHECK_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> corder;   // components in order of first appearance
+        std::vector<std::vector<int32_t>> members;
+        for (int i = 0; i < nt; ++i) {
+            const auto it = std::find(corder.begin(), corder.end(), comp[i]);
+            const size_t k = (size_t)(it - corder.begin());
+            if (it == corder.end()) {
+                corder.push_back(comp[i]);
+                members.emplace_back();
+            }
+            members[k].push_back(todo[i]);
+        }
+        for (const auto& mb : members)
+            if (mb.size() > 1) {
+                roots.push_back(mb[0]);
+                rest.insert(rest.end(), mb.begin() + 1, mb.end());
+            }
+    }
+    if (!rest.empty()) {
+        run_bfs(m, w, roots, s);
         const int n = (int)rest.size();
         d_src.upload(rest, s);
         d_lvl.alloc(n);
@@ -169,7 +201,7 @@ void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_in
             HG_CHECK_HIP(hipStreamSynchronize(s));
             for (int i = 0; i < np; ++i) h_ptr.push_back((int32_t)(o + base[i] + len[i]));
         }
-        todo = unreached;
+        if (!unreached.empty()) throw Error{HG_E_DEVICE, "source path: a source not reached from its component's root"};
     }
     P.np_src = (int)h_ptr.size() - 1;
     P.ns_src = (int)h_edge.size();

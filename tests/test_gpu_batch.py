@@ -171,3 +171,34 @@ def test_256_small_meshes_match_stored_oracle_samples():
 def MeshBatchLocal(meshes):
     from paper_1812_06060_amd.batch import MeshBatch
     return MeshBatch(meshes)
+
+
+def test_members_stop_on_their_own():
+    """Single-source members of different depths: each member's ADMM stops on
+    its own distance check and its tiles then sit out the rest of the solve.
+    Two copies of one mesh with the same source come out bit-identical, and
+    every member matches its solve alone."""
+    import paper_1812_06060_amd as hg
+    from paper_1812_06060_amd.batch import MeshBatch
+    v5, f5 = meshgen.icosphere(5)
+    v5 = meshgen.harmonic_displacement(v5, seed=11)
+    v3, f3 = meshgen.icosphere(3)
+    s5 = meshgen.random_sources(v5.shape[0], 1, seed=5)
+    s3 = meshgen.random_sources(v3.shape[0], 1, seed=6)
+    m5, m3 = hg.Mesh(v5, f5), hg.Mesh(v3, f3)
+    try:
+        b = MeshBatch([m5, m3, m5])
+        _say("batch of members with their own stopping")
+        ds, info = b.solve([s5, s3, s5], opts=hg.default_opts())
+        assert info.converged_admm
+        assert torch.equal(ds[0], ds[2])
+        for d, m, s in ((ds[0], m5, s5), (ds[1], m3, s3)):
+            d1, i1 = m.solve(s, 0.0, hg.default_opts())
+            a = d1.cpu().numpy()
+            _say("member", m.nv, "admm alone", i1.admm_iters, "batch", info.admm_iters,
+                 "max diff", np.abs(d.cpu().numpy() - a).max() / a.max())
+            assert np.abs(d.cpu().numpy() - a).max() <= 1e-4 * a.max()
+        b.close()
+    finally:
+        m5.close()
+        m3.close()
