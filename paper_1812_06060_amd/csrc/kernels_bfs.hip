@@ -216,17 +216,38 @@ __global__ void k_bfs_seed_sources(int nsrc, const int32_t* src, int32_t* level)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nsrc) level[src[i]] = 0;
 }
-// unreached back to -1; the deepest level into counters[3]
-__global__ void k_bfs_tile_finish(int nv, int32_t* level, int32_t* counters) {
+// unreached back to -1; each block's deepest level into blockmax, then the
+// deepest of all into counters[3] (one block; no contended atomics)
+__global__ void __launch_bounds__(kBlockB) k_bfs_tile_finish(int nv, int32_t* level, int32_t* blockmax) {
+    __shared__ int32_t sh[kBlockB / 64];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int d = 0;
     if (i < nv) {
-        int v = level[i];
-        if (v >= kFar) level[i] = -1;
-        else d = v;
+        const int v = level[i];
+        if (v >= kFar)
+            level[i] = -1;
+        else
+            d = v;
     }
     for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_down(d, o, 64));
-    if ((threadIdx.x & 63) == 0 && d > 0) atomicMax(&counters[3], d);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlockB / 64; ++k) d = max(d, sh[k]);
+        blockmax[blockIdx.x] = d;
+    }
+}
+__global__ void __launch_bounds__(1024) k_bfs_depth(int n, const int32_t* blockmax, int32_t* counters) {
+    __shared__ int32_t sh[1024 / 64];
+    int d = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d = max(d, blockmax[i]);
+    for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_down(d, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 1024 / 64; ++k) d = max(d, sh[k]);
+        counters[3] = d;
+    }
 }
 
 static bool bfs_tiles_supported(const Mesh& m) {
@@ -273,8 +294,10 @@ static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, const std::vector<int32_t
         }
         if (pass > nv + kCheck) throw Error{HG_E_DEVICE, "tiled breadth-first search did not settle"};
     }
-    hipLaunchKernelGGL(k_bfs_tile_finish, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, b.level,
-                       b.counters);
+    // the frontier queue is free in this schedule: it holds the block maxima
+    const int nb = grid_for(nv, kBlockB);
+    hipLaunchKernelGGL(k_bfs_tile_finish, dim3(nb), dim3(kBlockB), 0, s, nv, b.level, b.frontier_a);
+    hipLaunchKernelGGL(k_bfs_depth, dim3(1), dim3(1024), 0, s, nb, b.frontier_a, b.counters);
     hipLaunchKernelGGL(k_bfs_parent, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, m.row_ptr.p, m.col.p,
                        b.level, m.perm_v.p, b.parent, b.pslot);
     HG_CHECK_HIP(hipGetLastError());

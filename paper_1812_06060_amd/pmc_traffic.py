@@ -68,7 +68,7 @@ def main(argv=None):
     ap.add_argument("--calib-write", required=True)
     ap.add_argument("--calib-bytes", type=float, default=float(1 << 30),
                     help="bytes each calibration copy reads and writes (bench.py --copy-calib: 1 GiB)")
-    ap.add_argument("--colours", type=int, default=6, help="diffusion tile colours (launches per pass)")
+    ap.add_argument("--colours", type=int, default=5, help="diffusion tile colours (launches per pass)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     a = ap.parse_args(argv)
 
