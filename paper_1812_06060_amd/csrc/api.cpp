@@ -243,6 +243,19 @@ const char* hg_last_error(void) { return g_last_error.c_str(); }
 // Mesh creation: from the caller's triangles, or (intrinsic) from the
 // intrinsic Delaunay triangulation of them with the geometry taken from the
 // intrinsic edge lengths.
+// Tile workgroups that run at a time on the current device: the diffusion
+// and breadth-first tile kernels fit two 1024-thread workgroups per CU.  0
+// when there is no device to ask (the mesh is then refused later anyway).
+static int tile_slots() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return 2 * cus;
+}
+
 static hg_status create_mesh(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, void* stream,
                              hg_mesh_t* out, bool intrinsic) {
     return guarded([&]() -> hg_status {
@@ -252,7 +265,7 @@ static hg_status create_mesh(const double* xyz, int64_t nv, const int32_t* tri, 
         IntrinsicTri idt;
         if (intrinsic) build_intrinsic(xyz, nv, tri, nf, idt);
         HostTopo T;
-        build_topology(xyz, nv, intrinsic ? idt.tri.data() : tri, nf, 1024, T);
+        build_topology(xyz, nv, intrinsic ? idt.tri.data() : tri, nf, 1024, T, tile_slots());
         build_cycles(T);
         std::vector<double> elen, floc;
         std::vector<int32_t> tile_k0;   // uploaded asynchronously: lives until geometry_init has synchronised

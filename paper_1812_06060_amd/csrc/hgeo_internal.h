@@ -142,16 +142,22 @@ struct HostTopo {
 };
 
 // Builds the host topology; throws Error{HG_E_BAD_MESH} on invalid input.
+// slots > 0: the tile colours are balanced for launches that run that many
+// tile workgroups at a time (see colour_tiles).
 void build_topology(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf, int patch_size,
-                    HostTopo& out);
+                    HostTopo& out, int slots = 0);
 // Fills the cyc_* loops of a built topology (tree-cotree, caller-id rules).
 void build_cycles(HostTopo& T);
 // Colours of a conflict graph (symmetric adjacency lists, no self loops) by
 // saturation-degree ordering: fewer colours than greedy in index order (five
-// instead of six on the icosphere tiles).  Fills color_ptr [ncol+1] and
-// order (the nodes grouped by colour, ascending within a colour).
+// instead of six on the icosphere tiles).  With slots > 0 (the workgroups a
+// colour's launch runs at a time) a colour of n nodes takes ceil(n / slots)
+// waves, so nodes just past a multiple of slots are moved, where no
+// neighbour has the target colour, to colours with room below their next
+// multiple.  Fills color_ptr [ncol+1] and order (the nodes grouped by
+// colour, ascending within a colour).
 void colour_tiles(const std::vector<std::vector<int32_t>>& adj, std::vector<int32_t>& color_ptr,
-                  std::vector<int32_t>& order);
+                  std::vector<int32_t>& order, int slots = 0);
 
 // Intrinsic Delaunay triangulation (edge flips on intrinsic lengths) of a
 // caller mesh: the flipped triangles (caller vertex ids, rows in the input's

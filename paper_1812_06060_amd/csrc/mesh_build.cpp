@@ -36,7 +36,7 @@ static inline uint64_t spread3(uint64_t x) {
 static void bad(const std::string& msg) { throw Error{HG_E_BAD_MESH, msg}; }
 
 void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_t nf,
-                    int patch_size, HostTopo& T) {
+                    int patch_size, HostTopo& T, int slots) {
     if (nv <= 0 || nf <= 0) throw Error{HG_E_INVALID_ARG, "empty mesh"};
     if (nv >= (1ll << 31) || 3 * nf >= (1ll << 31))
         throw Error{HG_E_INVALID_ARG, "mesh too large for 32-bit element indices"};
@@ -441,12 +441,12 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
             std::sort(a.begin(), a.end());
             a.erase(std::unique(a.begin(), a.end()), a.end());
         }
-        colour_tiles(adj, T.color_ptr, T.tile_order);
+        colour_tiles(adj, T.color_ptr, T.tile_order, slots);
     }
 }
 
 void colour_tiles(const std::vector<std::vector<int32_t>>& adj, std::vector<int32_t>& color_ptr,
-                  std::vector<int32_t>& order) {
+                  std::vector<int32_t>& order, int slots) {
     const int64_t n = (int64_t)adj.size();
     std::vector<int32_t> color(n, -1);
     // per node: the set of its neighbours' colours (a bit mask while the
@@ -492,6 +492,36 @@ void colour_tiles(const std::vector<std::vector<int32_t>>& adj, std::vector<int3
                 seen_hi[u].push_back(c);
             heap.push_back({++sat[u], (int32_t)adj[u].size(), u});
             std::push_heap(heap.begin(), heap.end());
+        }
+    }
+    // waves: trim each colour's overflow past a multiple of slots (up to a
+    // quarter of slots) into colours with room, nodes in index order
+    if (slots > 0 && ncol > 1) {
+        std::vector<int64_t> size(ncol, 0);
+        for (int64_t v = 0; v < n; ++v) size[color[v]]++;
+        std::vector<char> nbc(ncol);
+        for (int c = 0; c < ncol; ++c) {
+            const int64_t over = size[c] % slots;
+            if (over == 0 || over > slots / 4 || size[c] <= slots) continue;
+            for (int64_t v = 0; v < n && size[c] % slots != 0; ++v) {
+                if (color[v] != c) continue;
+                std::fill(nbc.begin(), nbc.end(), 0);
+                for (int32_t u : adj[v]) nbc[color[u]] = 1;
+                int best = -1;
+                int64_t room = 0;
+                for (int j = 0; j < ncol; ++j) {
+                    if (j == c || nbc[j] || size[j] % slots == 0) continue;
+                    const int64_t r = slots - size[j] % slots;
+                    if (r > room) {
+                        room = r;
+                        best = j;
+                    }
+                }
+                if (best < 0) continue;
+                color[v] = best;
+                size[c]--;
+                size[best]++;
+            }
         }
     }
     color_ptr.assign(ncol + 1, 0);

@@ -35,7 +35,17 @@ removing them costs.
 No oracle solve at this size: the oracle's direct solves do not scale to
 168M unknowns; parity is shown at the sizes the oracle reaches.
 
+With --sphere LEVELS (say 8,10,12) it solves instead on the plain unit
+icosphere of each level, from one vertex they share (`random_sources(V_8,
+1, seed=104)`: icosphere vertices are numbered parents first), and reports
+the error against the exact distance on the sphere, the great-circle angle
+arccos(p_i . p_s): mean and max over the vertices, relative to pi.  The
+discrete solution approaches it as the spacing h falls, so the error at
+each level against the one before shows the method converging at the
+largest sizes, where no oracle solve exists.
+
 Run: python -m paper_1812_06060_amd.scale_bench [--level 12] [--compare-level 10] [--workers 16]
+     python -m paper_1812_06060_amd.scale_bench --sphere 8,10,12
 """
 from __future__ import annotations
 
@@ -150,16 +160,52 @@ def run(level=12, compare_level=10, workers=16, seam_variant=1.0, log=print):
     return {"scale": row, "compare": row_c}
 
 
+def run_sphere(levels, log=print):
+    """Solves on the plain unit icosphere of each level against the
+    great-circle distance (see the module docstring)."""
+    import torch
+
+    import meshgen
+    torch.cuda.set_device(0)
+    src = meshgen.random_sources(10 * 4 ** min(levels) + 2, 1, seed=104)
+    rows = []
+    for L in levels:
+        t0 = time.perf_counter()
+        v, f = meshgen.icosphere(L, progress=log)
+        log(f"[sphere] L{L} mesh generated: {v.shape[0]} vertices in {time.perf_counter() - t0:.1f} s")
+        row, d, e = _solve(L, v, f, src, log)
+        del f, e
+        u = v / np.linalg.norm(v, axis=1, keepdims=True)
+        err = np.empty(v.shape[0])
+        for a in range(0, v.shape[0], 1 << 24):
+            b = min(v.shape[0], a + (1 << 24))
+            exact = np.arccos(np.clip(u[a:b] @ u[src[0]], -1.0, 1.0))
+            err[a:b] = np.abs(d[a:b] - exact)
+        row["vs_great_circle"] = {"mean_over_pi": float(err.mean() / np.pi), "max_over_pi": float(err.max() / np.pi),
+                                  "source_zero": bool(d[src[0]] == 0.0)}
+        log(f"[sphere] L{L}: vs great circle {json.dumps(row['vs_great_circle'])}")
+        rows.append(row)
+        del v, u, d, err
+    for a, b in zip(rows, rows[1:]):
+        b["vs_great_circle"]["mean_ratio_to_previous_level"] = (a["vs_great_circle"]["mean_over_pi"] /
+                                                               b["vs_great_circle"]["mean_over_pi"])
+    return {"sphere": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--sphere", default=None, help="levels of plain unit icospheres, e.g. 8,10,12")
     ap.add_argument("--level", type=int, default=12)
     ap.add_argument("--compare-level", type=int, default=10)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--tol-seam", type=float, default=1.0,
                     help="also solve the large mesh once with this hg_opts.tol_seam (0 = skip)")
     a = ap.parse_args()
-    res = run(a.level, a.compare_level, a.workers, a.tol_seam or None,
-              log=lambda s: print(s, file=sys.stderr, flush=True))
+    log = lambda s: print(s, file=sys.stderr, flush=True)   # noqa: E731
+    if a.sphere:
+        print(json.dumps(run_sphere([int(x) for x in a.sphere.split(",")], log=log)), flush=True)
+        return
+    res = run(a.level, a.compare_level, a.workers, a.tol_seam or None, log=log)
     print(json.dumps(res), flush=True)
 
 
