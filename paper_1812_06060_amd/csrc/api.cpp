@@ -20,7 +20,8 @@ size_t Work::bytes() const {
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
            h.bytes() + sumz.bytes() + sumd.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
-           src.bytes() + dprev.bytes() + comp_pair.bytes() + tile_on.bytes() + cflag.bytes() + paths.bytes() +
+           src.bytes() + dprev.bytes() + comp_pair.bytes() + tile_mark.bytes() + tile_on.bytes() + cflag.bytes() +
+           paths.bytes() +
            tcomp.bytes() + tile_t.bytes() + cg.bytes();
 }
 
@@ -48,7 +49,7 @@ uint64_t Mesh::mesh_bytes() const {
     return face_form + blocked + floc.bytes() + px.bytes() + py.bytes() + pz.bytes() + perm_v.bytes() + perm_f.bytes() + perm_e.bytes() +
            row_ptr.bytes() + col.bytes() + csr_edge.bytes() + theta.bytes() + Av.bytes() + sum_theta.bytes() +
            tri.bytes() + fslot.bytes() + fsign.bytes() + farea.bytes() + ev.bytes() + ef.bytes() +
-           tile_ptr.bytes() + tile_k0.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
+           tile_ptr.bytes() + tile_k0.bytes() + tile_adj_ptr.bytes() + tile_adj.bytes() + halo_ptr.bytes() + halo_idx.bytes() + ell_ptr.bytes() + lnb.bytes() + ell_width.bytes() +
            tile_order.bytes() + twin.bytes() + h01.bytes() + comp_v.bytes() + tile_comp.bytes();
 }
 
@@ -339,6 +340,8 @@ static hg_status create_mesh(const double* xyz, int64_t nv, const int32_t* tri, 
             tile_k0.resize(T.tile_ptr.size());
             for (size_t p = 0; p < tile_k0.size(); ++p) tile_k0[p] = T.row_ptr[T.tile_ptr[p]];
             m->tile_k0.upload(tile_k0, s);
+            m->tile_adj_ptr.upload(T.tile_adj_ptr, s);
+            m->tile_adj.upload(T.tile_adj, s);
             m->halo_ptr.upload(T.halo_ptr, s);
             m->halo_idx.upload(T.halo_idx, s);
             m->ell_ptr.upload(T.ell_ptr, s);

@@ -64,7 +64,7 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
     const size_t n = parts.size();
     // offsets of each member
     std::vector<int64_t> vo(n + 1, 0), fo(n + 1, 0), eo(n + 1, 0), to(n + 1, 0), ho(n + 1, 0), lo(n + 1, 0),
-        co(n + 1, 0), ko(n + 1, 0), ceo(n + 1, 0), cfo(n + 1, 0);
+        co(n + 1, 0), ko(n + 1, 0), ceo(n + 1, 0), cfo(n + 1, 0), ao(n + 1, 0);
     int ncol = 0;
     for (size_t i = 0; i < n; ++i) {
         const Mesh& p = *parts[i];
@@ -76,6 +76,7 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
         lo[i + 1] = lo[i] + (int64_t)p.lnb.n;
         co[i + 1] = co[i] + std::max(1, p.n_comp);
         ko[i + 1] = ko[i] + (int64_t)p.col.n;
+        ao[i + 1] = ao[i] + (int64_t)p.tile_adj.n;
         ceo[i + 1] = ceo[i] + (int64_t)p.cyc_e_edge.size();
         cfo[i + 1] = cfo[i] + (int64_t)p.cyc_f_face.size();
         ncol = std::max(ncol, (int)p.color_ptr_host.size() - 1);
@@ -130,6 +131,8 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
     m.h01.alloc(2 * NE);
     m.tile_ptr.alloc(NT + 1);
     m.tile_k0.alloc(NT + 1);
+    m.tile_adj_ptr.alloc(NT + 1);
+    m.tile_adj.alloc(ao[n]);
     m.halo_ptr.alloc(NT + 1);
     m.halo_idx.alloc(ho[n]);
     m.ell_ptr.alloc(NT + 1);
@@ -170,6 +173,8 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
         shift_into(m.h01.p, 2 * eo[i], p.h01.p, 2 * ne, 3 * fo[i], true, s);
         shift_into(m.tile_ptr.p, to[i], p.tile_ptr.p, nt, vo[i], false, s);
         shift_into(m.tile_k0.p, to[i], p.tile_k0.p, nt, ko[i], false, s);
+        shift_into(m.tile_adj_ptr.p, to[i], p.tile_adj_ptr.p, nt, ao[i], false, s);
+        shift_into(m.tile_adj.p, ao[i], p.tile_adj.p, p.tile_adj.n, to[i], false, s);
         shift_into(m.halo_ptr.p, to[i], p.halo_ptr.p, nt, ho[i], false, s);
         shift_into(m.halo_idx.p, ho[i], p.halo_idx.p, p.halo_idx.n, vo[i], false, s);
         shift_into(m.ell_ptr.p, to[i], p.ell_ptr.p, nt, lo[i], false, s);
@@ -178,10 +183,11 @@ std::unique_ptr<Mesh> join_meshes(const std::vector<Mesh*>& parts, hipStream_t s
     }
     // closing entries of the pointer arrays
     {
-        const int32_t tail[4] = {(int32_t)ko[n], (int32_t)NV, (int32_t)ho[n], (int32_t)lo[n]};
+        const int32_t tail[5] = {(int32_t)ko[n], (int32_t)NV, (int32_t)ho[n], (int32_t)lo[n], (int32_t)ao[n]};
         HG_CHECK_HIP(hipMemcpyAsync(m.row_ptr.p + NV, &tail[0], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipMemcpyAsync(m.tile_ptr.p + NT, &tail[1], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipMemcpyAsync(m.tile_k0.p + NT, &tail[0], 4, hipMemcpyHostToDevice, s));
+        HG_CHECK_HIP(hipMemcpyAsync(m.tile_adj_ptr.p + NT, &tail[4], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipMemcpyAsync(m.halo_ptr.p + NT, &tail[2], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipMemcpyAsync(m.ell_ptr.p + NT, &tail[3], 4, hipMemcpyHostToDevice, s));
         HG_CHECK_HIP(hipStreamSynchronize(s));   // tail lives on this stack frame

@@ -122,6 +122,8 @@ struct HostTopo {
     // colouring of the tile adjacency graph (tiles sharing a mesh edge get
     // different colours): tiles of colour c are tile_order[color_ptr[c] ..]
     std::vector<int32_t> color_ptr, tile_order;
+    // the tile adjacency itself (CSR, neighbours ascending)
+    std::vector<int32_t> tile_adj_ptr, tile_adj;
     // connected components: comp[v] per internal vertex, numbered in the
     // order of their smallest caller vertex id; mean edge length of each;
     // the component of each tile (tiles are connected)
@@ -268,6 +270,7 @@ struct Work {
     DBuf<int32_t> jp0, jp1;             // pointer-jumping parents
     DBuf<float> dprev;                  // distance at the previous ADMM check
     DBuf<double> comp_pair;             // per component (largest change, largest d) of a check
+    DBuf<int32_t> tile_mark;            // tiled search: last pass a tile or a neighbour changed
     DBuf<uint8_t> tile_on, cflag;       // ADMM tiles still iterating; per component 0 active,
                                         // 1 stopping now, 2 stopped
     DBuf<double> partial;               // reduction partials
@@ -364,6 +367,7 @@ struct Mesh {
     int patch_size = 0, n_patches = 0, max_halo = 0, max_ell_width = 0;
     DBuf<int32_t> tile_ptr, halo_ptr, halo_idx, ell_ptr;
     DBuf<int32_t> tile_k0;                  // [n_tiles+1] first CSR entry of each tile's rows
+    DBuf<int32_t> tile_adj_ptr, tile_adj;   // tile adjacency (HostTopo)
     DBuf<uint16_t> lnb;
     DBuf<uint8_t> ell_width;
     std::vector<int32_t> color_ptr_host;    // tile colours (see HostTopo)
@@ -534,17 +538,30 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
 void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, bool source_paths,
                             bool cycles, int form, hipStream_t s);
 void integrate(Mesh& m, Work& w, int form, int depth, float* d_user, hipStream_t s);
+// The edge-form state an edge difference is formed from (Eq. 21):
+// x_e = (S_e + zeta_h0 + zeta_h1) / (|H_e| (1 + mu)), a boundary edge without
+// zeta_h1.  Given to the distance checks, which then form x only on the
+// edges the integration follows instead of reading a full x array.
+struct EdgeX {
+    const float* S;
+    const float* z;
+    float inv1mu;
+};
+__device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1mu) {
+    // x_e = (S + z0 + z1) / (|H_e| (1 + mu)); a boundary edge has z1 = 0
+    return bnd ? (S + z0) * inv1mu : 0.5f * (S + z0 + z1) * inv1mu;
+}
 // integrates the given state (edge differences xe or face gradients g) and
 // returns max |d - d_prev| (inf on the first call) and max |d|; d_prev <- d;
 // with seam, also the largest |d_head - d_tail - x_e| over the edges
 void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
-                 double& delta, double& dmax, double* seam = nullptr);
+                 double& delta, double& dmax, double* seam = nullptr, const EdgeX* ex = nullptr);
 // the largest |d_head - d_tail - x_e| for the d of the last dist_change and
 // the given field (the same state)
 double seam_now(Mesh& m, Work& w, int form, const float* xe, const float* g, hipStream_t s);
 // As dist_change, per connected component (delta[c], dmax[c]).
 void dist_change_comp(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first,
-                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax);
+                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax, const EdgeX* ex = nullptr);
 
 // Stopping rule on the distance field: with delta_k the largest change of d
 // between two checks and r = delta_k / delta_{k-1} < 1, the remaining change

@@ -207,10 +207,6 @@ __global__ void k_zeta_init(int ne, const int32_t* h01, const float* sumz, float
     }
 }
 
-__device__ inline float edge_x(float S, float z0, float z1, int bnd, float inv1mu) {
-    // x_e = (S + z0 + z1) / (|H_e| (1 + mu)); a boundary edge has z1 = 0
-    return bnd ? (S + z0) * inv1mu : 0.5f * (S + z0 + z1) * inv1mu;
-}
 
 // One folded iteration of a face from its three copies zo and per slot the
 // twin's copy tz and target sum S, with c = 1 / (2 (1 + mu)) and the sign q
@@ -813,11 +809,10 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         const bool want = it >= next_check || it == cap;
         if (!fixed && want) {
             bool done;
+            const EdgeX ex{S, za, inv1mu};
             if (percomp) {
-                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
-                                   w.xe.p);
                 std::vector<double> dl, dm;
-                dist_change_comp(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, dl, dm);
+                dist_change_comp(m, w, HG_FORM_EDGE, depth, nullptr, nullptr, stop.first, s, dl, dm, &ex);
                 stop.first = false;
                 bool stopping = false, all_far = true, any_near = false;
                 done = true;
@@ -853,12 +848,18 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                     for (auto& cs : cstop) cs.restart();
                 }
             } else if (monitor) {
-                hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
-                                   w.xe.p);
+                // the seam needs x on every edge; the change alone only on the
+                // edges the integration follows
+                if (o.tol_seam > 0.0)
+                    hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
+                                       w.xe.p);
                 double delta, dmax;
                 double seam = 0.0;
-                dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax,
-                            o.tol_seam > 0.0 ? &seam : nullptr);
+                if (o.tol_seam > 0.0)
+                    dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax, &seam);
+                else
+                    dist_change(m, w, HG_FORM_EDGE, depth, nullptr, nullptr, stop.first, s, delta, dmax, nullptr,
+                                &ex);
                 r.seam = seam / m.hbar;
                 done = stop.update(delta, dmax, o.tol_admm);
                 done = done && (o.tol_seam <= 0.0 || r.seam <= o.tol_seam);

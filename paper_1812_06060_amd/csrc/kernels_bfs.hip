@@ -158,6 +158,9 @@ int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, 
 // fixed point is unique, so the levels equal the level-synchronous search's
 // exactly; about depth / (rings crossed per pass) passes instead of depth
 // dependent launches.  The pairing is chosen afterwards as before.
+// A tile works in pass k only if it or a neighbour tile changed in pass
+// k - 1 or earlier in pass k (mark >= k - 1): elsewhere nothing can move,
+// so the other workgroups read one word and leave.
 constexpr int kTileB = 1024;         // vertices per diffusion tile
 constexpr int32_t kFar = 0x3fffffff;   // not reached (yet)
 
@@ -168,10 +171,13 @@ __global__ void __launch_bounds__(kTileB) k_bfs_tile(const int32_t* __restrict__
                                                      const int32_t* __restrict__ halo_idx,
                                                      const int32_t* __restrict__ ell_ptr,
                                                      const uint8_t* __restrict__ ell_width,
-                                                     const uint16_t* __restrict__ lnb, int32_t* level,
-                                                     int32_t* changes) {
+                                                     const uint16_t* __restrict__ lnb,
+                                                     const int32_t* __restrict__ adj_ptr,
+                                                     const int32_t* __restrict__ adj, int32_t* level,
+                                                     int32_t* mark, int pass, int32_t* changes) {
     extern __shared__ int32_t lv[];   // the core's slots, then the halo's
     const int p = tile_list[xcd_block(blockIdx.x, gridDim.x)];
+    if (mark[p] < pass - 1) return;   // the same for the whole workgroup
     const int v0 = tile_ptr[p], np = tile_ptr[p + 1] - v0;
     const int h0 = halo_ptr[p], nh = halo_ptr[p + 1] - h0;
     const int W = ell_width[p], eb = ell_ptr[p];
@@ -204,7 +210,36 @@ __global__ void __launch_bounds__(kTileB) k_bfs_tile(const int32_t* __restrict__
     }
     const int moved = in && own != start;
     if (moved) level[v0 + tid] = own;
-    if (__syncthreads_or(moved) && tid == 0) atomicAdd(changes, 1);
+    if (__syncthreads_or(moved)) {
+        // the tile and its neighbours work in this pass (later colours)
+        // and the next (earlier colours); every writer writes this pass
+        const int a0 = adj_ptr[p], na = adj_ptr[p + 1] - a0;
+        for (int k = tid; k < na; k += kTileB) mark[adj[a0 + k]] = pass;
+        if (tid == 0) {
+            mark[p] = pass;
+            atomicAdd(changes, 1);
+        }
+    }
+}
+
+// marks: -2 everywhere, -1 on the tiles holding a source (they work in pass 0)
+__global__ void k_bfs_marks(int nt, int32_t* mark) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nt) mark[p] = -2;
+}
+__global__ void k_bfs_mark_sources(int nsrc, const int32_t* src, int nt, const int32_t* tile_ptr, int32_t* mark) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsrc) return;
+    const int v = src[i];
+    int lo = 0, hi = nt - 1;   // the tile p with tile_ptr[p] <= v < tile_ptr[p + 1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (tile_ptr[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    mark[lo] = -1;
 }
 
 __global__ void k_bfs_seed(int nv, int32_t* level, int32_t* counters) {
@@ -252,16 +287,22 @@ __global__ void __launch_bounds__(1024) k_bfs_depth(int n, const int32_t* blockm
 
 static bool bfs_tiles_supported(const Mesh& m) {
     return m.patch_size == kTileB && m.n_patches > 0 && m.max_ell_width <= 16 &&
+           m.tile_adj_ptr.n == (size_t)m.n_patches + 1 &&
            (size_t)(kTileB + m.max_halo) * 4 <= 65536;
 }
 
-static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, hipStream_t s) {
+static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, int32_t* mark, const std::vector<int32_t>& src,
+                         hipStream_t s) {
     const int nv = (int)m.nv;
     HG_CHECK_HIP(hipMemcpyAsync(b.src, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_bfs_seed, dim3(grid_for(std::max(nv, 8), kBlockB)), dim3(kBlockB), 0, s, nv, b.level,
                        b.counters);
     hipLaunchKernelGGL(k_bfs_seed_sources, dim3(grid_for((int64_t)src.size(), kBlockB)), dim3(kBlockB), 0, s,
                        (int)src.size(), b.src, b.level);
+    const int nt = m.n_patches;
+    hipLaunchKernelGGL(k_bfs_marks, dim3(grid_for(nt, kBlockB)), dim3(kBlockB), 0, s, nt, mark);
+    hipLaunchKernelGGL(k_bfs_mark_sources, dim3(grid_for((int64_t)src.size(), kBlockB)), dim3(kBlockB), 0, s,
+                       (int)src.size(), b.src, nt, m.tile_ptr.p, mark);
     HG_CHECK_HIP(hipGetLastError());
     const size_t lds = (size_t)(kTileB + m.max_halo) * sizeof(int32_t);
     const int maxw = m.max_ell_width;
@@ -276,7 +317,9 @@ static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, const std::vector<int32_t
         for (int c = 0; c < ncol; ++c) {
             const int nc = cp[c + 1] - cp[c];
             if (nc == 0) continue;
-#define HG_BFS_TILE_ARGS                                                                                               dim3(nc), dim3(kTileB), lds, s, m.tile_order.p + cp[c], m.tile_ptr.p, m.halo_ptr.p, m.halo_idx.p, m.ell_ptr.p,         m.ell_width.p, m.lnb.p, b.level, b.counters
+#define HG_BFS_TILE_ARGS                                                                                     \
+    dim3(nc), dim3(kTileB), lds, s, m.tile_order.p + cp[c], m.tile_ptr.p, m.halo_ptr.p, m.halo_idx.p, m.ell_ptr.p, \
+        m.ell_width.p, m.lnb.p, m.tile_adj_ptr.p, m.tile_adj.p, b.level, mark, pass, b.counters
             if (maxw <= 6)
                 hipLaunchKernelGGL(k_bfs_tile<6>, HG_BFS_TILE_ARGS);
             else if (maxw <= 8)
@@ -316,7 +359,9 @@ int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src, hipStream_t s) {
     w.counters.alloc(8);
     w.src.alloc(src.size());
     BfsBuffers b{w.level.p, w.parent.p, w.pslot.p, w.frontier_a.p, w.frontier_b.p, w.counters.p, w.src.p};
-    return bfs_tiles_supported(m) ? run_bfs_tiles(m, b, src, s) : run_bfs_into(m, b, src, s);
+    if (!bfs_tiles_supported(m)) return run_bfs_into(m, b, src, s);
+    w.tile_mark.alloc((size_t)m.n_patches);
+    return run_bfs_tiles(m, b, w.tile_mark.p, src, s);
 }
 
 }  // namespace hg

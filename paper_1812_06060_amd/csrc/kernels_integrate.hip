@@ -44,8 +44,8 @@ __device__ inline void df_add(float ah, float al, float bh, float bl, float& rh,
 // Per vertex: the change along the edge to its partner, and the jump state.
 __global__ void k_int_step(int nv, int form, const int32_t* level, const int32_t* parent, const int32_t* pslot,
                            const int32_t* csr_edge, const int32_t* ev, const int32_t* ef, const float* xe,
-                           const float* g, const double* px, const double* py, const double* pz, float* shi,
-                           float* slo, int32_t* jp) {
+                           const int32_t* h01, EdgeX ex, const float* g, const double* px, const double* py,
+                           const double* pz, float* shi, float* slo, int32_t* jp) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nv) return;
     int lj = level[j];
@@ -59,7 +59,13 @@ __global__ void k_int_step(int nv, int form, const int32_t* level, const int32_t
     int e = csr_edge[pslot[j]];
     double step;
     if (form == HG_FORM_EDGE) {
-        double x = (double)xe[e];
+        double x;
+        if (xe) {
+            x = (double)xe[e];
+        } else {   // formed here, as k_edge_x forms it
+            const int h0 = h01[2 * e], h1 = h01[2 * e + 1];
+            x = (double)edge_x(ex.S[e], ex.z[h0], h1 >= 0 ? ex.z[h1] : 0.f, ef[2 * e + 1] < 0, ex.inv1mu);
+        }
         step = (ev[2 * e + 1] == j) ? x : -x;
     } else {
         double d0 = px[j] - px[k], d1 = py[j] - py[k], d2 = pz[j] - pz[k];
@@ -112,7 +118,8 @@ struct IntSums {
     int32_t* jp;
 };
 
-static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, hipStream_t s) {
+static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, hipStream_t s,
+                              const EdgeX* ex = nullptr) {
     const int nv = (int)m.nv;
     w.shi0.alloc(nv);
     w.slo0.alloc(nv);
@@ -122,7 +129,8 @@ static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float
     w.jp1.alloc(nv);
     const int grid = grid_for(nv, kBlockI);
     hipLaunchKernelGGL(k_int_step, dim3(grid), dim3(kBlockI), 0, s, nv, form, w.level.p, w.parent.p, w.pslot.p,
-                       m.csr_edge.p, m.ev.p, m.ef.p, xe, g, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p, w.jp0.p);
+                       m.csr_edge.p, m.ev.p, m.ef.p, ex ? nullptr : xe, m.h01.p, ex ? *ex : EdgeX{nullptr, nullptr, 0.f},
+                       g, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p, w.jp0.p);
     HG_CHECK_HIP(hipGetLastError());
     // after r rounds every vertex sums 2^r chain edges; sources stop the walk
     int rounds = 0;
@@ -276,12 +284,12 @@ __global__ void k_seam(int ne, const int32_t* ev, const int32_t* ef, const int32
 }
 
 void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first, hipStream_t s,
-                 double& delta, double& dmax, double* seam) {
+                 double& delta, double& dmax, double* seam, const EdgeX* ex) {
     const int nv = (int)m.nv;
     w.dprev.alloc(nv);
     const int grid = grid_for(nv, kBlockI);
     if ((int)w.partial.n < 2 * grid + 8) w.partial.alloc((size_t)2 * grid + 8);
-    IntSums r = integrate_sums(m, w, form, depth, xe, g, s);
+    IntSums r = integrate_sums(m, w, form, depth, xe, g, s, ex);
     hipLaunchKernelGGL(k_dist_delta, dim3(grid), dim3(kBlockI), 0, s, nv, r.jp, r.hi, r.lo, w.dprev.p,
                        first ? 1 : 0, w.partial.p);
     hipLaunchKernelGGL(k_reduce_pairs_max, dim3(1), dim3(kBlockI), 0, s, w.partial.p, grid);
@@ -294,11 +302,11 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
 }
 
 void dist_change_comp(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first,
-                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax) {
+                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax, const EdgeX* ex) {
     const int nv = (int)m.nv, nc = std::max(1, m.n_comp);
     w.dprev.alloc(nv);
     w.comp_pair.alloc((size_t)2 * nc);
-    IntSums r = integrate_sums(m, w, form, depth, xe, g, s);
+    IntSums r = integrate_sums(m, w, form, depth, xe, g, s, ex);
     hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(2 * nc, kBlockI)), dim3(kBlockI), 0, s, 2 * nc,
                        reinterpret_cast<unsigned long long*>(w.comp_pair.p));
     hipLaunchKernelGGL(k_dist_delta_comp, dim3(grid_for(nv, kBlockI)), dim3(kBlockI), 0, s, nv, r.jp, r.hi, r.lo,

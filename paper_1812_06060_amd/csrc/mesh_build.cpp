@@ -442,6 +442,11 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
             a.erase(std::unique(a.begin(), a.end()), a.end());
         }
         colour_tiles(adj, T.color_ptr, T.tile_order, slots);
+        T.tile_adj_ptr.assign(np + 1, 0);
+        for (int64_t p = 0; p < np; ++p) T.tile_adj_ptr[p + 1] = T.tile_adj_ptr[p] + (int32_t)adj[p].size();
+        T.tile_adj.clear();
+        T.tile_adj.reserve(T.tile_adj_ptr[np]);
+        for (const auto& a : adj) T.tile_adj.insert(T.tile_adj.end(), a.begin(), a.end());
     }
 }
 
