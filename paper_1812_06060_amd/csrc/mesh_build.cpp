@@ -500,14 +500,14 @@ void colour_tiles(const std::vector<std::vector<int32_t>>& adj, std::vector<int3
         }
     }
     // waves: trim each colour's overflow past a multiple of slots (up to a
-    // quarter of slots) into colours with room, nodes in index order
+    // half of slots) into colours with room, nodes in index order
     if (slots > 0 && ncol > 1) {
         std::vector<int64_t> size(ncol, 0);
         for (int64_t v = 0; v < n; ++v) size[color[v]]++;
         std::vector<char> nbc(ncol);
         for (int c = 0; c < ncol; ++c) {
             const int64_t over = size[c] % slots;
-            if (over == 0 || over > slots / 4 || size[c] <= slots) continue;
+            if (over == 0 || over > slots / 2 || size[c] <= slots) continue;
             for (int64_t v = 0; v < n && size[c] % slots != 0; ++v) {
                 if (color[v] != c) continue;
                 std::fill(nbc.begin(), nbc.end(), 0);
