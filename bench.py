@@ -173,6 +173,10 @@ def main():
         print(f"[bench] autotune ({time.perf_counter() - t0:.1f}s): " +
               ", ".join(f"{label(c)}={c['ms']:.0f}ms ({c['passes']} passes)" for c in tune["candidates"]) +
               f" -> {label(ch)}", file=sys.stderr, flush=True)
+        if tune["admm"]:
+            print("[bench] autotune ADMM block: " +
+                  ", ".join(f"{a['block']}={a['us_per_iteration']:.1f}us/it" for a in tune["admm"]) +
+                  f" -> {tune['admm'][tune['admm_chosen']]['block']}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         _, info = mesh.solve(src, 0.0, opts, out=out)

@@ -141,7 +141,9 @@ typedef struct {
                                Between two checks the iterations run in
                                launches of k and one launch of the rest, so
                                the result, the iteration count included, is
-                               the same for every k.  0 = auto (default, 6) */
+                               the same for every k.  0 = auto (default: the
+                               block hg_mesh_autotune chose for the mesh,
+                               else 6) */
     int32_t overlap_rings;  /* schedule 3: rings of overlap around each tile,
                                1..4 (a tile whose region would not fit the
                                LDS gets fewer); 0 = auto: the autotuned
@@ -512,6 +514,10 @@ typedef struct {
     float ms[8];                 /* time of the diffusion stage (converged) */
     int32_t passes[8];
     int32_t overlap_rings[8];    /* rings of overlap (schedule 3), else 0 */
+    int32_t n_admm;              /* ADMM block candidates timed (edge form) */
+    int32_t admm_chosen;         /* index into the two arrays below, -1 if none */
+    int32_t admm_block[4];       /* iterations per launch */
+    float admm_us_per_iteration[4];
 } hg_tune_report;
 
 /* Times the diffusion stage of a probe query (src/nsrc, t, opts as in
@@ -522,10 +528,14 @@ typedef struct {
  * workspace and stream, and stores
  * the fastest one that converges in the mesh: later queries whose
  * diffusion_schedule / inner_sweeps options are 0 (auto) use it.  The
- * arithmetic of every candidate has the same fixed point.  Overlapping tiles
- * built for the trial are kept only if they are chosen.  The call changes
- * the mesh: it must not run while other calls use the same mesh.  report
- * (optional) receives the timings. */
+ * arithmetic of every candidate has the same fixed point.  For the edge form
+ * with opts->admm_block 0 it then times 192 ADMM iterations (runs of 64, as
+ * between two checks of a solve) in launches of 4, 5 and 6 iterations over
+ * LDS face tiles and stores the fastest block for later queries with
+ * admm_block 0; every block gives the same iterates.  Overlapping tiles and
+ * face tiles built for the trials are kept only if they are chosen.  The
+ * call changes the mesh: it must not run while other calls use the same
+ * mesh.  report (optional) receives the timings. */
 hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, double t, const hg_opts* opts,
                            void* stream, hg_tune_report* report);
 

@@ -93,7 +93,8 @@ class TuneReport(C.Structure):
     _fields_ = [
         ("n_candidates", C.c_int32), ("chosen", C.c_int32), ("schedule", C.c_int32 * 8),
         ("inner_sweeps", C.c_int32 * 8), ("ms", C.c_float * 8), ("passes", C.c_int32 * 8),
-        ("overlap_rings", C.c_int32 * 8),
+        ("overlap_rings", C.c_int32 * 8), ("n_admm", C.c_int32), ("admm_chosen", C.c_int32),
+        ("admm_block", C.c_int32 * 4), ("admm_us_per_iteration", C.c_float * 4),
     ]
 
 
@@ -355,7 +356,10 @@ class Mesh:
         return {"chosen": rep.chosen,
                 "candidates": [{"schedule": rep.schedule[i], "inner_sweeps": rep.inner_sweeps[i],
                                 "overlap_rings": rep.overlap_rings[i], "ms": rep.ms[i], "passes": rep.passes[i]}
-                               for i in range(k)]}
+                               for i in range(k)],
+                "admm_chosen": rep.admm_chosen,
+                "admm": [{"block": rep.admm_block[i], "us_per_iteration": rep.admm_us_per_iteration[i]}
+                         for i in range(rep.n_admm)]}
 
     def intrinsic_triangulation(self):
         """(flipped triangles int32[F, 3], edge lengths float64[E] in

@@ -84,7 +84,6 @@ static hg_opts resolve_opts(const hg_opts* o) {
     if (!(r.tol_seam >= 0.0) || !std::isfinite(r.tol_seam)) throw Error{HG_E_INVALID_ARG, "tol_seam must be >= 0"};
     if (r.admm_block < 0 || r.admm_block > kMaxAdmmBlock)
         throw Error{HG_E_INVALID_ARG, "admm_block must lie in 0..8 (0 = auto)"};
-    if (r.admm_block == 0) r.admm_block = kAutoAdmmBlock;
     if (r.overlap_rings < 0 || r.overlap_rings > 4) throw Error{HG_E_INVALID_ARG, "overlap_rings must lie in 0..4"};
     if (r.diffusion_schedule < 0 || r.diffusion_schedule > 3)
         throw Error{HG_E_INVALID_ARG, "diffusion_schedule must lie in 0..3"};
@@ -647,6 +646,7 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
         std::memset(&rep, 0, sizeof(rep));
         rep.n_candidates = (int)cands.size();
         rep.chosen = -1;
+        rep.admm_chosen = -1;
         hipEvent_t a, b;
         HG_CHECK_HIP(hipEventCreate(&a));
         HG_CHECK_HIP(hipEventCreate(&b));
@@ -713,6 +713,54 @@ hg_status hg_mesh_autotune(hg_mesh_t mesh, const int32_t* src, int32_t nsrc, dou
             auto& ot = m->otiles;
             for (size_t i = ot.size(); i-- > overlap_sets_before;)
                 if (m->tuned_schedule != 3 || ot[i]->rings != m->tuned_rings) ot.erase(ot.begin() + i);
+        }
+        // the edge form's ADMM block: the same iterations (their count a
+        // multiple of every candidate) timed for each, from the probe's
+        // normalised field; face tiles built for the trial are kept only
+        // for the block chosen
+        if (rep.chosen >= 0 && o.formulation == HG_FORM_EDGE && o.admm_block == 0) {
+            run_diffusion(*m, w, si, tt, o, s);
+            run_normalize(*m, w, s);
+            hg_opts oa = o;
+            if (oa.mu == 0.0) oa.mu = 100.0;   // timing only: the arithmetic per iteration does not depend on mu
+            oa.check_every = 64;               // runs of 64 iterations, as a solve's between two checks
+            size_t edge_sets_before;
+            {
+                std::lock_guard<std::mutex> lock(m->et_mu);
+                edge_sets_before = m->etiles.size();
+            }
+            const int saved_block = m->tuned_admm_block;
+            float best_us = 0.f;
+            int nb = 0;
+            for (int kb : {4, 5, 6}) {
+                oa.admm_block = kb;
+                AdmmResult r0 = run_admm_edge(*m, w, 64, oa, s);   // builds the face tiles, warms up
+                if (r0.block != kb) continue;                          // regions of kb rings do not fit
+                HG_CHECK_HIP(hipEventCreate(&a));
+                HG_CHECK_HIP(hipEventCreate(&b));
+                HG_CHECK_HIP(hipEventRecord(a, s));
+                run_admm_edge(*m, w, 192, oa, s);
+                HG_CHECK_HIP(hipEventRecord(b, s));
+                HG_CHECK_HIP(hipEventSynchronize(b));
+                float ms = 0.f;
+                HG_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                rep.admm_block[nb] = kb;
+                rep.admm_us_per_iteration[nb] = 1e3f * ms / 192.f;
+                if (rep.admm_chosen < 0 || rep.admm_us_per_iteration[nb] < best_us) {
+                    best_us = rep.admm_us_per_iteration[nb];
+                    rep.admm_chosen = nb;
+                }
+                ++nb;
+            }
+            rep.n_admm = nb;
+            m->tuned_admm_block = rep.admm_chosen >= 0 ? rep.admm_block[rep.admm_chosen] : saved_block;
+            HG_CHECK_HIP(hipStreamSynchronize(s));
+            std::lock_guard<std::mutex> lock(m->et_mu);
+            auto& et = m->etiles;
+            for (size_t i = et.size(); i-- > edge_sets_before;)
+                if (et[i]->rings != m->tuned_admm_block) et.erase(et.begin() + i);
         }
         if (report) *report = rep;
         return rep.chosen >= 0 ? HG_OK : fail(HG_E_NOT_CONVERGED, "no candidate schedule converged");

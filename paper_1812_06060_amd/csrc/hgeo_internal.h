@@ -396,7 +396,7 @@ struct Mesh {
 
     // diffusion schedule picked by hg_mesh_autotune for options left at 0
     // (auto): 0 = not tuned
-    int tuned_schedule = 0, tuned_inner = 0, tuned_rings = 0;
+    int tuned_schedule = 0, tuned_inner = 0, tuned_rings = 0, tuned_admm_block = 0;
     // default per-query workspace of the synchronous entry points (also
     // used for the mesh's own reductions)
     Work w;

@@ -660,7 +660,9 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     // the largest block size up to the requested one whose regions fit
     const Mesh::EdgeTileSet* tiles = nullptr;
     int K = 1;
-    for (int k = use_paths ? 1 : o.admm_block; k > 1 && !tiles; --k)
+    // requested block: the option, else the mesh's autotuned one, else 6
+    const int req = o.admm_block > 0 ? o.admm_block : (m.tuned_admm_block > 0 ? m.tuned_admm_block : kAutoAdmmBlock);
+    for (int k = use_paths ? 1 : req; k > 1 && !tiles; --k)
         if ((tiles = m.ensure_edge_tiles(k, s))) K = k;
     const int per = tiles ? (tiles->max_region + kBlockT - 1) / kBlockT : 0;
     r.block = K;

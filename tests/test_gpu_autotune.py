@@ -1,6 +1,6 @@
-"""hg_mesh_autotune times the diffusion schedules on a probe query, stores
-the fastest converged one in the mesh, and later solves with automatic
-options use it and still match the oracle."""
+"""hg_mesh_autotune times the diffusion schedules and the edge form's ADMM
+blocks on a probe query, stores the fastest in the mesh, and later solves
+with automatic options use them and still match the oracle."""
 import numpy as np
 import pytest
 
@@ -29,7 +29,12 @@ def test_autotune_then_solve(name):
         if mesh.stats["n_patches"] > 16:   # global Jacobi only on meshes of a few tiles
             assert all(x["schedule"] in (2, 3) for x in c)
         assert {x["schedule"] for x in c} >= {2, 3}
+        # the ADMM block: the fastest timed one, used by later solves
+        a = rep["admm"]
+        assert a and 0 <= rep["admm_chosen"] < len(a)
+        assert all(a[rep["admm_chosen"]]["us_per_iteration"] <= x["us_per_iteration"] + 1e-6 for x in a)
         d, info = mesh.solve(src, 0.0, hg.default_opts())
+        assert info.admm_block == a[rep["admm_chosen"]]["block"]
         if c[rep["chosen"]]["schedule"] in (2, 3):
             assert info.sweeps == info.passes * c[rep["chosen"]]["inner_sweeps"]
         ref = pipeline.heat_method(v, f, src, form="edge")

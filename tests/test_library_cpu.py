@@ -43,15 +43,17 @@ def test_exports_every_declared_symbol(lib):
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include "hgeo.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hg_opts), sizeof(hg_info),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hg_opts), sizeof(hg_info),'
                    ' sizeof(hg_mesh_stats), offsetof(hg_info, bytes_alg), offsetof(hg_opts, mu),'
-                   ' sizeof(hg_result), offsetof(hg_result, info), sizeof(hg_server_stats_t));return 0;}\n')
+                   ' sizeof(hg_result), offsetof(hg_result, info), sizeof(hg_server_stats_t),'
+                   ' sizeof(hg_tune_report), offsetof(hg_tune_report, admm_us_per_iteration));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(_hgeo.Opts), C.sizeof(_hgeo.Info), C.sizeof(_hgeo.MeshStats),
                    _hgeo.Info.bytes_alg.offset, _hgeo.Opts.mu.offset, C.sizeof(_hgeo.Result),
-                   _hgeo.Result.info.offset, C.sizeof(_hgeo.ServerStats)]
+                   _hgeo.Result.info.offset, C.sizeof(_hgeo.ServerStats), C.sizeof(_hgeo.TuneReport),
+                   _hgeo.TuneReport.admm_us_per_iteration.offset]
 
 
 def test_defaults(lib):
