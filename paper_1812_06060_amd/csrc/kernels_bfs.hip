@@ -164,20 +164,16 @@ int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, 
 constexpr int kTileB = 1024;         // vertices per diffusion tile
 constexpr int32_t kFar = 0x3fffffff;   // not reached (yet)
 
+// One tile's relaxation (the whole workgroup; lv: its LDS levels).
 template <int MAXW>
-__global__ void __launch_bounds__(kTileB) k_bfs_tile(const int32_t* __restrict__ tile_list,
-                                                     const int32_t* __restrict__ tile_ptr,
-                                                     const int32_t* __restrict__ halo_ptr,
-                                                     const int32_t* __restrict__ halo_idx,
-                                                     const int32_t* __restrict__ ell_ptr,
-                                                     const uint8_t* __restrict__ ell_width,
-                                                     const uint16_t* __restrict__ lnb,
-                                                     const int32_t* __restrict__ adj_ptr,
-                                                     const int32_t* __restrict__ adj, int32_t* level,
-                                                     int32_t* mark, int pass, int32_t* changes) {
-    extern __shared__ int32_t lv[];   // the core's slots, then the halo's
-    const int p = tile_list[xcd_block(blockIdx.x, gridDim.x)];
-    if (mark[p] < pass - 1) return;   // the same for the whole workgroup
+__device__ __forceinline__ void bfs_tile_body(int p, const int32_t* __restrict__ tile_ptr,
+                                              const int32_t* __restrict__ halo_ptr,
+                                              const int32_t* __restrict__ halo_idx,
+                                              const int32_t* __restrict__ ell_ptr,
+                                              const uint8_t* __restrict__ ell_width,
+                                              const uint16_t* __restrict__ lnb, const int32_t* __restrict__ adj_ptr,
+                                              const int32_t* __restrict__ adj, int32_t* level, int32_t* mark,
+                                              int pass, int32_t* changes, int32_t* lv) {
     const int v0 = tile_ptr[p], np = tile_ptr[p + 1] - v0;
     const int h0 = halo_ptr[p], nh = halo_ptr[p + 1] - h0;
     const int W = ell_width[p], eb = ell_ptr[p];
@@ -219,6 +215,45 @@ __global__ void __launch_bounds__(kTileB) k_bfs_tile(const int32_t* __restrict__
             mark[p] = pass;
             atomicAdd(changes, 1);
         }
+    }
+}
+
+// One colour of one pass: workgroup b takes the colour's entries b, b + G,
+// b + 2G, ... (G = gridDim.x; at most kTileB of them), keeps those whose
+// tile is marked (mark >= pass - 1: it or a neighbour changed in the last
+// pass or earlier in this one) and relaxes them one after the other.  Only
+// the marked tiles cost more than one read.  The order within a workgroup
+// does not matter: tiles of one colour never read what another writes.
+template <int MAXW>
+__global__ void __launch_bounds__(kTileB) k_bfs_tiles(const int32_t* __restrict__ tile_list, int nc,
+                                                      const int32_t* __restrict__ tile_ptr,
+                                                      const int32_t* __restrict__ halo_ptr,
+                                                      const int32_t* __restrict__ halo_idx,
+                                                      const int32_t* __restrict__ ell_ptr,
+                                                      const uint8_t* __restrict__ ell_width,
+                                                      const uint16_t* __restrict__ lnb,
+                                                      const int32_t* __restrict__ adj_ptr,
+                                                      const int32_t* __restrict__ adj, int32_t* level,
+                                                      int32_t* mark, int pass, int32_t* changes, int lv_slots) {
+    extern __shared__ int32_t lds[];   // levels (lv_slots: core, then halo), then the active list
+    int32_t* lv = lds;
+    int32_t* act = lds + lv_slots;
+    __shared__ int n_act;
+    const int tid = threadIdx.x;
+    const int G = gridDim.x, b = blockIdx.x;
+    if (tid == 0) n_act = 0;
+    __syncthreads();
+    const int i = b + tid * G;
+    if (i < nc) {
+        const int p = tile_list[i];
+        if (mark[p] >= pass - 1) act[atomicAdd(&n_act, 1)] = p;
+    }
+    __syncthreads();
+    const int na = n_act;
+    for (int k = 0; k < na; ++k) {
+        bfs_tile_body<MAXW>(act[k], tile_ptr, halo_ptr, halo_idx, ell_ptr, ell_width, lnb, adj_ptr, adj, level, mark,
+                            pass, changes, lv);
+        __syncthreads();   // the next tile rewrites lv
     }
 }
 
@@ -285,10 +320,16 @@ __global__ void __launch_bounds__(1024) k_bfs_depth(int n, const int32_t* blockm
     }
 }
 
+// The tiled search wins while the tiles are few: 16 against 35 ms at L10
+// (10,487 tiles, depth 2,589), but 286 against 177 ms at L12 (164k tiles,
+// depth 10-11k), where a pass's colour launches carry many more marked
+// tiles; the level-synchronous search is used beyond 32,768 tiles.
+constexpr int kMaxTilesTiledBfs = 32768;
+
 static bool bfs_tiles_supported(const Mesh& m) {
-    return m.patch_size == kTileB && m.n_patches > 0 && m.max_ell_width <= 16 &&
+    return m.patch_size == kTileB && m.n_patches > 0 && m.n_patches <= kMaxTilesTiledBfs && m.max_ell_width <= 16 &&
            m.tile_adj_ptr.n == (size_t)m.n_patches + 1 &&
-           (size_t)(kTileB + m.max_halo) * 4 <= 65536;
+           (size_t)(2 * kTileB + m.max_halo) * 4 <= 65536;
 }
 
 static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, int32_t* mark, const std::vector<int32_t>& src,
@@ -304,10 +345,15 @@ static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, int32_t* mark, const std:
     hipLaunchKernelGGL(k_bfs_mark_sources, dim3(grid_for((int64_t)src.size(), kBlockB)), dim3(kBlockB), 0, s,
                        (int)src.size(), b.src, nt, m.tile_ptr.p, mark);
     HG_CHECK_HIP(hipGetLastError());
-    const size_t lds = (size_t)(kTileB + m.max_halo) * sizeof(int32_t);
+    const int lv_slots = kTileB + m.max_halo;
+    const size_t lds = (size_t)(lv_slots + kTileB) * sizeof(int32_t);
     const int maxw = m.max_ell_width;
     const std::vector<int32_t>& cp = m.color_ptr_host;
     const int ncol = (int)cp.size() - 1;
+    int dev = 0, cus = 0;
+    HG_CHECK_HIP(hipGetDevice(&dev));
+    HG_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int slots = std::max(1, 2 * cus);   // two 1024-thread workgroups per CU
     // a pass can move the front by as little as one ring, so depth + 1
     // passes always suffice; checks read the change count every few passes
     constexpr int kCheck = 4;
@@ -317,15 +363,18 @@ static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, int32_t* mark, const std:
         for (int c = 0; c < ncol; ++c) {
             const int nc = cp[c + 1] - cp[c];
             if (nc == 0) continue;
-#define HG_BFS_TILE_ARGS                                                                                     \
-    dim3(nc), dim3(kTileB), lds, s, m.tile_order.p + cp[c], m.tile_ptr.p, m.halo_ptr.p, m.halo_idx.p, m.ell_ptr.p, \
-        m.ell_width.p, m.lnb.p, m.tile_adj_ptr.p, m.tile_adj.p, b.level, mark, pass, b.counters
+            // one wave of workgroups, each scanning at most kTileB entries
+            const int G = std::max(std::min(nc, slots), (nc + kTileB - 1) / kTileB);
+#define HG_BFS_TILE_ARGS                                                                                      \
+    dim3(G), dim3(kTileB), lds, s, m.tile_order.p + cp[c], nc, m.tile_ptr.p, m.halo_ptr.p, m.halo_idx.p,      \
+        m.ell_ptr.p, m.ell_width.p, m.lnb.p, m.tile_adj_ptr.p, m.tile_adj.p, b.level, mark, pass, b.counters, \
+        lv_slots
             if (maxw <= 6)
-                hipLaunchKernelGGL(k_bfs_tile<6>, HG_BFS_TILE_ARGS);
+                hipLaunchKernelGGL(k_bfs_tiles<6>, HG_BFS_TILE_ARGS);
             else if (maxw <= 8)
-                hipLaunchKernelGGL(k_bfs_tile<8>, HG_BFS_TILE_ARGS);
+                hipLaunchKernelGGL(k_bfs_tiles<8>, HG_BFS_TILE_ARGS);
             else
-                hipLaunchKernelGGL(k_bfs_tile<16>, HG_BFS_TILE_ARGS);
+                hipLaunchKernelGGL(k_bfs_tiles<16>, HG_BFS_TILE_ARGS);
 #undef HG_BFS_TILE_ARGS
         }
         HG_CHECK_HIP(hipGetLastError());

@@ -48,7 +48,9 @@ uint64_t work_estimate(const Mesh& m, int form, int nsrc) {
                  + 24 * nv + 8 * nv + 8 * nv   // v0, v1, invD; e0, e1; logu
                  + 12 * nf + 4 * ne           // h, target sums
                  + 4 * ne + 12 * nf           // xe, gf
-                 + 16 * nv + 8 * nv + 4 * nv; // shi/slo pairs, jp0/jp1, dprev
+                 + 16 * nv + 8 * nv + 4 * nv  // shi/slo pairs, jp0/jp1, dprev
+                 + 6 * (uint64_t)m.n_patches  // tile marks of the tiled search, ADMM tile flags
+                 + 17 * (uint64_t)std::max(1, m.n_comp);   // per component: check maxima, flags
     if (form == HG_FORM_EDGE)
         b += 36 * nf;                          // zeta per slot (double-buffered) and S per slot
     else
