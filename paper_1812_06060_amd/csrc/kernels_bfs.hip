@@ -160,7 +160,7 @@ int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, 
 // dependent launches.  The pairing is chosen afterwards as before.
 // A tile works in pass k only if it or a neighbour tile changed in pass
 // k - 1 or earlier in pass k (mark >= k - 1): elsewhere nothing can move,
-// so the other workgroups read one word and leave.
+// so the other tiles cost one read of their mark (k_bfs_tiles).
 constexpr int kTileB = 1024;         // vertices per diffusion tile
 constexpr int32_t kFar = 0x3fffffff;   // not reached (yet)
 
