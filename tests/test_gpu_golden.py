@@ -82,3 +82,27 @@ def test_full_size_parity(hg, path, field):
     assert info.converged_u and info.converged_admm
     assert np.isfinite(ds).all()
     assert err.mean() <= 1e-4 and err.max() <= 1e-3
+
+
+def test_batched_fields_match_their_goldens(hg):
+    """Eight of the 64 single-source level-9 fields answered by one batched
+    solve (hg_geodesic_solve_batch over eight instances of the resident mesh,
+    each member stopping its ADMM on its own check): every member within the
+    same bar of its stored oracle field."""
+    from paper_1812_06060_amd.batch import MeshBatch
+    path = os.path.join(HERE, "golden", "bumpy9_fields_edge.npz")
+    g = np.load(path)
+    pick = [0, 9, 18, 27, 36, 45, 54, 63]
+    mesh = _mesh(hg, "bumpy9")
+    print(f"[gpu-case] batched fields {pick}", flush=True)
+    b = MeshBatch([mesh] * len(pick))
+    try:
+        ds, info = b.solve([[int(g["sources"][i])] for i in pick], opts=hg.default_opts())
+        assert info.converged_u and info.converged_admm
+        for k, i in enumerate(pick):
+            d = ds[k].cpu().numpy()[g["idx"][i]].astype(np.float64)
+            err = np.abs(d - g["d"][i].astype(np.float64)) / float(g["diam"][i])
+            print(f"[gpu-case] batched field {i}: mean={err.mean():.2e} max={err.max():.2e}", flush=True)
+            assert err.mean() <= 1e-4 and err.max() <= 1e-3, i
+    finally:
+        b.close()
