@@ -116,14 +116,16 @@ typedef struct {
                                Eq. 22 face form), so that it is the gradient
                                of a function there; 0 = without them.
                                Components with boundary get none. */
-    double tol_seam;        /* hg_geodesic_solve: at each distance check also
-                               measure the seam, max over edges of
+    double tol_seam;        /* hg_geodesic_solve: once the distance check is
+                               met, also measure the seam, max over edges of
                                |d_head - d_tail - x_e| / hbar (d the field
                                integrated along the breadth-first tree, x_e
                                the edge difference of the optimised field;
                                zero on the tree's edges, elsewhere the jump
                                left by what is still not a gradient), and
-                               stop only once it is <= tol_seam as well;
+                               stop only once it is <= tol_seam as well
+                               (otherwise measure it again at every later
+                               check);
                                default 0 = not required (it is reported in
                                hg_info.seam either way) */
     int32_t admm_block;     /* edge form without constraint groups: ADMM

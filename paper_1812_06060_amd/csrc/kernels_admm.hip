@@ -850,21 +850,17 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                     for (auto& cs : cstop) cs.restart();
                 }
             } else if (monitor) {
-                // the seam needs x on every edge; the change alone only on the
-                // edges the integration follows
-                if (o.tol_seam > 0.0)
+                // the change needs x only on the edges the integration follows
+                double delta, dmax;
+                dist_change(m, w, HG_FORM_EDGE, depth, nullptr, nullptr, stop.first, s, delta, dmax, nullptr, &ex);
+                done = stop.update(delta, dmax, o.tol_admm);
+                // the seam (x on every edge) only once the distance has settled
+                if (done && o.tol_seam > 0.0) {
                     hipLaunchKernelGGL(k_edge_x, dim3(ge), dim3(kBlockA), 0, s, ne, m.h01.p, m.ef.p, S, za, inv1mu,
                                        w.xe.p);
-                double delta, dmax;
-                double seam = 0.0;
-                if (o.tol_seam > 0.0)
-                    dist_change(m, w, HG_FORM_EDGE, depth, w.xe.p, nullptr, stop.first, s, delta, dmax, &seam);
-                else
-                    dist_change(m, w, HG_FORM_EDGE, depth, nullptr, nullptr, stop.first, s, delta, dmax, nullptr,
-                                &ex);
-                r.seam = seam / m.hbar;
-                done = stop.update(delta, dmax, o.tol_admm);
-                done = done && (o.tol_seam <= 0.0 || r.seam <= o.tol_seam);
+                    r.seam = seam_now(m, w, HG_FORM_EDGE, w.xe.p, nullptr, s) / m.hbar;
+                    done = r.seam <= o.tol_seam;
+                }
                 if (!done && interval == check && stop.far(dmax, o.tol_admm)) {
                     interval = kCoarseChecks * check;
                     stop.restart();
@@ -1171,12 +1167,13 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
             bool done;
             if (monitor) {
                 double delta, dmax;
-                double seam = 0.0;
-                dist_change(m, w, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax,
-                            o.tol_seam > 0.0 ? &seam : nullptr);
-                r.seam = seam / m.hbar;
+                dist_change(m, w, HG_FORM_FACE, depth, nullptr, ga, stop.first, s, delta, dmax);
                 done = stop.update(delta, dmax, o.tol_admm);
-                done = done && (o.tol_seam <= 0.0 || r.seam <= o.tol_seam);
+                // the seam only once the distance has settled
+                if (done && o.tol_seam > 0.0) {
+                    r.seam = seam_now(m, w, HG_FORM_FACE, nullptr, ga, s) / m.hbar;
+                    done = r.seam <= o.tol_seam;
+                }
                 if (!done && interval == check && stop.far(dmax, o.tol_admm)) {
                     interval = kCoarseChecks * check;
                     stop.restart();
