@@ -73,7 +73,7 @@ typedef struct {
     int32_t max_sweeps;     /* diffusion sweep cap; default 100000 */
     int32_t max_admm;       /* ADMM iteration cap; default 50000 */
     double mu;              /* ADMM penalty (the paper uses 100); default 0 =
-                               auto: max(30, depth/2, 1.5 L, C/2) in
+                               auto: max(30, depth/2, L, C/2) in
                                hg_geodesic_solve (depth = breadth-first depth
                                of the query, L = edges on the longest source
                                path, C = edges on the longest generator loop
