@@ -21,6 +21,7 @@ size_t Work::bytes() const {
            h.bytes() + sumz.bytes() + sumd.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +
            src.bytes() + dprev.bytes() + comp_pair.bytes() + tile_mark.bytes() + tile_on.bytes() + cflag.bytes() +
+           cdue.bytes() + bdue.bytes() +
            paths.bytes() +
            tcomp.bytes() + tile_t.bytes() + cg.bytes();
 }

@@ -273,6 +273,8 @@ struct Work {
     DBuf<int32_t> tile_mark;            // tiled search: last pass a tile or a neighbour changed
     DBuf<uint8_t> tile_on, cflag;       // ADMM tiles still iterating; per component 0 active,
                                         // 1 stopping now, 2 stopped
+    DBuf<uint8_t> cdue, bdue;           // per component: checked now; per vertex block of a
+                                        // check: 0 none, 1 all, 2 some of its vertices checked
     DBuf<double> partial;               // reduction partials
     DBuf<double> red_host_dummy;
     double* pinned = nullptr;           // host pinned reduction results
@@ -559,9 +561,13 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
 // the largest |d_head - d_tail - x_e| for the d of the last dist_change and
 // the given field (the same state)
 double seam_now(Mesh& m, Work& w, int form, const float* xe, const float* g, hipStream_t s);
-// As dist_change, per connected component (delta[c], dmax[c]).
+// As dist_change, per connected component (delta[c], dmax[c]).  With due
+// (host, one byte per component), only the components with due[c] != 0 are
+// integrated and compared (the others keep their d_prev, and their delta and
+// dmax come back 0).
 void dist_change_comp(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first,
-                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax, const EdgeX* ex = nullptr);
+                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax, const EdgeX* ex = nullptr,
+                      const uint8_t* due = nullptr);
 
 // Stopping rule on the distance field: with delta_k the largest change of d
 // between two checks and r = delta_k / delta_{k-1} < 1, the remaining change

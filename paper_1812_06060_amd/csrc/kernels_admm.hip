@@ -667,15 +667,17 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
     const int per = tiles ? (tiles->max_region + kBlockT - 1) / kBlockT : 0;
     r.block = K;
     // Several connected components (meshes joined into one batch): each
-    // stops on its own distance check, and its tiles then sit out the
-    // remaining launches (its state is copied into both buffers first, so
-    // the skipped launches leave it in place).  A face tile's component is
-    // its vertex tile's.
+    // keeps its own check schedule (a check covers only the components due
+    // for one) and stops on its own distance check, as it would alone; its
+    // tiles then sit out the remaining launches (its state is copied into
+    // both buffers first, so the skipped launches leave it in place).  A
+    // face tile's component is its vertex tile's.
     const int ncomp = std::max(1, m.n_comp);
     const bool percomp =
         monitor && tiles && !use_paths && ncomp > 1 && o.tol_seam <= 0.0 && tiles->n == m.n_patches;
     std::vector<DistStop> cstop;
-    std::vector<uint8_t> cflag_h;
+    std::vector<uint8_t> cflag_h, cdue_h;
+    std::vector<int> cnext, cint;   // per component: its next check, iterations between checks
     if (percomp) {
         w.tile_on.alloc((size_t)tiles->n);
         w.cflag.alloc((size_t)ncomp);
@@ -684,12 +686,17 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         HG_CHECK_HIP(hipGetLastError());
         cstop.assign((size_t)ncomp, DistStop());
         cflag_h.assign((size_t)ncomp, 0);
+        cdue_h.assign((size_t)ncomp, 0);
     }
     const uint8_t* tile_on = percomp ? w.tile_on.p : nullptr;
     const int check = monitor ? std::max(64, o.check_every) : std::max(1, o.check_every);
     // iterations between two checks: one chunk, or kCoarseChecks chunks far
     // from convergence (DistStop)
     int interval = check, next_check = check;
+    if (percomp) {
+        cnext.assign((size_t)ncomp, check);
+        cint.assign((size_t)ncomp, check);
+    }
     float* za = w.z0.p;
     float* zb = w.z1.p;
     // algorithmic bytes of one launch: per face its three zeta, S copies
@@ -808,30 +815,48 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
         run_len = launches;
         r.kernel_ms += rt.stop(s);
         r.timed_launches += run_len;
-        const bool want = it >= next_check || it == cap;
+        bool want = it >= next_check || it == cap;
+        if (percomp) {   // the components still iterating whose check is due
+            want = false;
+            for (int c = 0; c < ncomp; ++c) {
+                cdue_h[c] = cflag_h[c] == 0 && (it >= cnext[c] || it == cap) ? 1 : 0;
+                want = want || cdue_h[c] != 0;
+            }
+        }
         if (!fixed && want) {
             bool done;
             const EdgeX ex{S, za, inv1mu};
             if (percomp) {
                 std::vector<double> dl, dm;
-                dist_change_comp(m, w, HG_FORM_EDGE, depth, nullptr, nullptr, stop.first, s, dl, dm, &ex);
+                dist_change_comp(m, w, HG_FORM_EDGE, depth, nullptr, nullptr, stop.first, s, dl, dm, &ex,
+                                 cdue_h.data());
                 stop.first = false;
-                bool stopping = false, all_far = true, any_near = false;
-                done = true;
+                bool stopping = false;
                 for (int c = 0; c < ncomp; ++c) {
-                    if (cflag_h[c] != 0) {
+                    if (cflag_h[c] != 0) {   // stopped at an earlier check
                         cflag_h[c] = 2;
                         continue;
                     }
-                    if (cstop[c].update(dl[c], dm[c], o.tol_admm)) {
+                    if (!cdue_h[c]) continue;
+                    // the schedule of a solve alone (below): checks every
+                    // chunk, or every kCoarseChecks chunks while far
+                    DistStop& cs = cstop[c];
+                    if (cs.update(dl[c], dm[c], o.tol_admm)) {
                         cflag_h[c] = 1;
                         stopping = true;
                         continue;
                     }
-                    done = false;
-                    all_far = all_far && cstop[c].far(dm[c], o.tol_admm);
-                    any_near = any_near || cstop[c].near(dm[c], o.tol_admm);
+                    if (cint[c] == check && cs.far(dm[c], o.tol_admm)) {
+                        cint[c] = kCoarseChecks * check;
+                        cs.restart();
+                    } else if (cint[c] > check && cs.near(dm[c], o.tol_admm)) {
+                        cint[c] = check;
+                        cs.restart();
+                    }
+                    cnext[c] = it + cint[c];
                 }
+                done = true;
+                for (int c = 0; c < ncomp && done; ++c) done = cflag_h[c] != 0;
                 if (!done && stopping) {
                     HG_CHECK_HIP(hipMemcpyAsync(w.cflag.p, cflag_h.data(), (size_t)ncomp, hipMemcpyHostToDevice, s));
                     hipLaunchKernelGGL(k_freeze_faces, dim3(gf), dim3(kBlockA), 0, s, nf, m.tri.p, m.comp_v.p,
@@ -841,13 +866,6 @@ AdmmResult run_admm_edge(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
                     HG_CHECK_HIP(hipGetLastError());
                     // cflag_h is read by the copy before the next check rewrites it
                     HG_CHECK_HIP(hipStreamSynchronize(s));
-                }
-                if (!done && interval == check && all_far) {
-                    interval = kCoarseChecks * check;
-                    for (auto& cs : cstop) cs.restart();
-                } else if (!done && interval > check && any_near) {
-                    interval = check;
-                    for (auto& cs : cstop) cs.restart();
                 }
             } else if (monitor) {
                 // the change needs x only on the edges the integration follows

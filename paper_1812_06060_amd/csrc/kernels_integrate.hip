@@ -41,13 +41,50 @@ __device__ inline void df_add(float ah, float al, float bh, float bl, float& rh,
     rh = h;
 }
 
+// The part of the mesh a distance check covers.  With bdue null, every
+// vertex; else the vertices of the components with cdue[c] != 0, where
+// bdue[b] says for the block of kBlockI vertices b whether none (0), all (1)
+// or some (2, then decided per vertex) of its vertices are covered.  A
+// vertex's partner chain stays in its component, so the integration of the
+// covered components reads nothing the skipped vertices would write.
+struct CheckDue {
+    const uint8_t* bdue;
+    const int32_t* comp;
+    const uint8_t* cdue;
+};
+__device__ inline bool vertex_due(const CheckDue& d, int block, int j) {
+    if (!d.bdue) return true;
+    const uint8_t b = d.bdue[block];
+    return b == 1 || (b == 2 && d.cdue[d.comp[j]] != 0);
+}
+
+// Per vertex block: 0 if none of its vertices' components is due, 1 if all
+// are, 2 otherwise.
+__global__ void k_block_due(int nv, const int32_t* comp, const uint8_t* cdue, uint8_t* bdue) {
+    __shared__ int any_due, all_due;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (threadIdx.x == 0) {
+        any_due = 0;
+        all_due = 1;
+    }
+    __syncthreads();
+    if (j < nv) {
+        if (cdue[comp[j]] != 0)
+            any_due = 1;
+        else
+            all_due = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) bdue[blockIdx.x] = any_due ? (all_due ? 1 : 2) : 0;
+}
+
 // Per vertex: the change along the edge to its partner, and the jump state.
 __global__ void k_int_step(int nv, int form, const int32_t* level, const int32_t* parent, const int32_t* pslot,
                            const int32_t* csr_edge, const int32_t* ev, const int32_t* ef, const float* xe,
                            const int32_t* h01, EdgeX ex, const float* g, const double* px, const double* py,
-                           const double* pz, float* shi, float* slo, int32_t* jp) {
+                           const double* pz, float* shi, float* slo, int32_t* jp, CheckDue due) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nv) return;
+    if (j >= nv || !vertex_due(due, blockIdx.x, j)) return;
     int lj = level[j];
     if (lj <= 0) {
         shi[j] = lj == 0 ? 0.f : INFINITY;
@@ -86,9 +123,10 @@ __global__ void k_int_step(int nv, int form, const int32_t* level, const int32_t
 }
 
 __global__ void k_int_jump(int nv, const float* shi, const float* slo, const int32_t* jp, float* shi2, float* slo2,
-                           int32_t* jp2) {
-    int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (j >= nv) return;
+                           int32_t* jp2, CheckDue due) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    int j = b * blockDim.x + threadIdx.x;
+    if (j >= nv || !vertex_due(due, b, j)) return;
     int p = jp[j];
     if (p < 0 || jp[p] == p) {
         // unreachable, a source, or already pointing at a source
@@ -119,7 +157,7 @@ struct IntSums {
 };
 
 static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, hipStream_t s,
-                              const EdgeX* ex = nullptr) {
+                              const EdgeX* ex = nullptr, CheckDue due = CheckDue{nullptr, nullptr, nullptr}) {
     const int nv = (int)m.nv;
     w.shi0.alloc(nv);
     w.slo0.alloc(nv);
@@ -130,7 +168,7 @@ static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float
     const int grid = grid_for(nv, kBlockI);
     hipLaunchKernelGGL(k_int_step, dim3(grid), dim3(kBlockI), 0, s, nv, form, w.level.p, w.parent.p, w.pslot.p,
                        m.csr_edge.p, m.ev.p, m.ef.p, ex ? nullptr : xe, m.h01.p, ex ? *ex : EdgeX{nullptr, nullptr, 0.f},
-                       g, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p, w.jp0.p);
+                       g, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p, w.jp0.p, due);
     HG_CHECK_HIP(hipGetLastError());
     // after r rounds every vertex sums 2^r chain edges; sources stop the walk
     int rounds = 0;
@@ -138,7 +176,7 @@ static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float
     float *ha = w.shi0.p, *la = w.slo0.p, *hb = w.shi1.p, *lb = w.slo1.p;
     int32_t *pa = w.jp0.p, *pb = w.jp1.p;
     for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL(k_int_jump, dim3(grid), dim3(kBlockI), 0, s, nv, ha, la, pa, hb, lb, pb);
+        hipLaunchKernelGGL(k_int_jump, dim3(grid), dim3(kBlockI), 0, s, nv, ha, la, pa, hb, lb, pb, due);
         HG_CHECK_HIP(hipGetLastError());
         std::swap(ha, hb);
         std::swap(la, lb);
@@ -192,13 +230,14 @@ __global__ void k_dist_delta(int nv, const int32_t* jp, const float* shi, const 
 // bits).  A block whose vertices lie in one component (the usual case: the
 // components of a joined batch are contiguous) reduces first.
 __global__ void k_dist_delta_comp(int nv, const int32_t* jp, const float* shi, const float* slo, float* dprev,
-                                  int first, const int32_t* comp, unsigned long long* comp_pair) {
+                                  int first, const int32_t* comp, unsigned long long* comp_pair, CheckDue due) {
     __shared__ double sh[kBlockI / 64];
     __shared__ int c_first, mixed;
+    if (due.bdue && due.bdue[blockIdx.x] == 0) return;   // the whole block
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     double dl = 0.0, mx = 0.0;
     int c = -1;
-    if (j < nv) {
+    if (j < nv && vertex_due(due, blockIdx.x, j)) {
         c = comp[j];
         if (jp[j] >= 0) {
             float d = shi[j] + slo[j];
@@ -302,15 +341,27 @@ void dist_change(Mesh& m, Work& w, int form, int depth, const float* xe, const f
 }
 
 void dist_change_comp(Mesh& m, Work& w, int form, int depth, const float* xe, const float* g, bool first,
-                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax, const EdgeX* ex) {
+                      hipStream_t s, std::vector<double>& delta, std::vector<double>& dmax, const EdgeX* ex,
+                      const uint8_t* due) {
     const int nv = (int)m.nv, nc = std::max(1, m.n_comp);
+    const int grid = grid_for(nv, kBlockI);
     w.dprev.alloc(nv);
     w.comp_pair.alloc((size_t)2 * nc);
-    IntSums r = integrate_sums(m, w, form, depth, xe, g, s, ex);
+    CheckDue cd{nullptr, nullptr, nullptr};
+    if (due) {
+        w.cdue.alloc((size_t)nc);
+        w.bdue.alloc((size_t)grid);
+        // the stream is synchronised below, before the host array can change
+        HG_CHECK_HIP(hipMemcpyAsync(w.cdue.p, due, (size_t)nc, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_block_due, dim3(grid), dim3(kBlockI), 0, s, nv, m.comp_v.p, w.cdue.p, w.bdue.p);
+        HG_CHECK_HIP(hipGetLastError());
+        cd = CheckDue{w.bdue.p, m.comp_v.p, w.cdue.p};
+    }
+    IntSums r = integrate_sums(m, w, form, depth, xe, g, s, ex, cd);
     hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(2 * nc, kBlockI)), dim3(kBlockI), 0, s, 2 * nc,
                        reinterpret_cast<unsigned long long*>(w.comp_pair.p));
-    hipLaunchKernelGGL(k_dist_delta_comp, dim3(grid_for(nv, kBlockI)), dim3(kBlockI), 0, s, nv, r.jp, r.hi, r.lo,
-                       w.dprev.p, first ? 1 : 0, m.comp_v.p, reinterpret_cast<unsigned long long*>(w.comp_pair.p));
+    hipLaunchKernelGGL(k_dist_delta_comp, dim3(grid), dim3(kBlockI), 0, s, nv, r.jp, r.hi, r.lo, w.dprev.p,
+                       first ? 1 : 0, m.comp_v.p, reinterpret_cast<unsigned long long*>(w.comp_pair.p), cd);
     HG_CHECK_HIP(hipGetLastError());
     std::vector<double> h((size_t)2 * nc);
     HG_CHECK_HIP(hipMemcpyAsync(h.data(), w.comp_pair.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -50,7 +50,8 @@ uint64_t work_estimate(const Mesh& m, int form, int nsrc) {
                  + 4 * ne + 12 * nf           // xe, gf
                  + 16 * nv + 8 * nv + 4 * nv  // shi/slo pairs, jp0/jp1, dprev
                  + 6 * (uint64_t)m.n_patches  // tile marks of the tiled search, ADMM tile flags
-                 + 17 * (uint64_t)std::max(1, m.n_comp);   // per component: check maxima, flags
+                 + nv / 256 + 1               // per vertex block: its share of a check
+                 + 18 * (uint64_t)std::max(1, m.n_comp);   // per component: check maxima, flags
     if (form == HG_FORM_EDGE)
         b += 36 * nf;                          // zeta per slot (double-buffered) and S per slot
     else

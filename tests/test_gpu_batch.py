@@ -174,10 +174,12 @@ def MeshBatchLocal(meshes):
 
 
 def test_members_stop_on_their_own():
-    """Single-source members of different depths: each member's ADMM stops on
-    its own distance check and its tiles then sit out the rest of the solve.
-    Two copies of one mesh with the same source come out bit-identical, and
-    every member matches its solve alone."""
+    """Single-source members of different depths: each member keeps the check
+    schedule of its solve alone, its ADMM stops on its own distance check and
+    its tiles then sit out the rest of the solve.  Two copies of one mesh
+    with the same source come out bit-identical; every member matches its
+    solve alone, and the deepest one, whose automatic penalty is the batch's,
+    equals it bit for bit."""
     import paper_1812_06060_amd as hg
     from paper_1812_06060_amd.batch import MeshBatch
     v5, f5 = meshgen.icosphere(5)
@@ -198,6 +200,8 @@ def test_members_stop_on_their_own():
             _say("member", m.nv, "admm alone", i1.admm_iters, "batch", info.admm_iters,
                  "max diff", np.abs(d.cpu().numpy() - a).max() / a.max())
             assert np.abs(d.cpu().numpy() - a).max() <= 1e-4 * a.max()
+            if m is m5:
+                assert torch.equal(d, d1)
         b.close()
     finally:
         m5.close()
