@@ -13,13 +13,16 @@
 //     the diffusion sweeps (Eq. 7);
 //   * per tile: its halo (outside one-ring) and the tile-local neighbour
 //     slots of every vertex (ELL layout).
-// Geometry (areas, cotangent weights) is computed later on the GPU.
+// Geometry (areas, cotangent weights) is computed later on the GPU.  The
+// per-element phases run on host worker threads (host_par.h); every output
+// is the same for any number of them.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 
 #include "hgeo_internal.h"
+#include "host_par.h"
 
 namespace hg {
 
@@ -34,6 +37,31 @@ static inline uint64_t spread3(uint64_t x) {
 }
 
 static void bad(const std::string& msg) { throw Error{HG_E_BAD_MESH, msg}; }
+
+// Items 0..n-1 grouped by key (keys[i] in [0, nk)), in increasing i within a
+// key: items[ptr[k] .. ptr[k+1]) -- a stable counting sort.  Each worker owns
+// a range of keys and scans all of them, so the result is the sequential one.
+static void group_by_key(const std::vector<int32_t>& keys, int64_t nk, std::vector<int32_t>& ptr,
+                         std::vector<int32_t>& items) {
+    const int64_t n = (int64_t)keys.size();
+    const int parts = host_threads();
+    ptr.assign(nk + 1, 0);
+    items.assign(n, 0);
+    parallel_parts(nk, parts, [&](int64_t k0, int64_t k1, int) {
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t k = keys[i];
+            if (k >= k0 && k < k1) ++ptr[k + 1];
+        }
+    });
+    for (int64_t k = 0; k < nk; ++k) ptr[k + 1] += ptr[k];
+    parallel_parts(nk, parts, [&](int64_t k0, int64_t k1, int) {
+        std::vector<int32_t> pos(ptr.begin() + k0, ptr.begin() + k1);
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t k = keys[i];
+            if (k >= k0 && k < k1) items[pos[k - k0]++] = (int32_t)i;
+        }
+    });
+}
 
 void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_t nf,
                     int patch_size, HostTopo& T, int slots) {
@@ -61,37 +89,51 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
         }
     double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
     std::vector<std::pair<uint64_t, int32_t>> mk(nv);
-    for (int64_t i = 0; i < nv; ++i) {
-        uint64_t q[3];
-        for (int c = 0; c < 3; ++c) {
-            double r = (xyz[3 * i + c] - lo[c]) / ext;
-            q[c] = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(r * 2097151.0)));
+    parallel_for(nv, 1 << 16, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+            uint64_t q[3];
+            for (int c = 0; c < 3; ++c) {
+                double r = (xyz[3 * i + c] - lo[c]) / ext;
+                q[c] = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(r * 2097151.0)));
+            }
+            mk[i] = {spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2), (int32_t)i};
         }
-        mk[i] = {spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2), (int32_t)i};
-    }
-    std::sort(mk.begin(), mk.end());
+    });
+    // (key, vertex) pairs are distinct: a total order
+    parallel_sort(mk, [](const std::pair<uint64_t, int32_t>& a, const std::pair<uint64_t, int32_t>& b) {
+        return a < b;
+    });
 
     // ---- tiles: breadth-first region growing over the caller's one-ring
     // adjacency, seeded at the first unassigned vertex in Morton order; each
     // tile is connected and holds at most patch_size vertices.  The internal
     // vertex order is tile-major, breadth-first inside a tile.
     const int P = patch_size;
+    const int parts = host_threads();
     std::vector<int32_t> order_v;
     order_v.reserve(nv);
     T.tile_ptr.clear();
     {
+        // a vertex's neighbours in face order (two per incident face); each
+        // worker fills the lists of its own range of vertices
         std::vector<int32_t> deg(nv + 1, 0);
-        for (int64_t f = 0; f < nf; ++f)
-            for (int k = 0; k < 3; ++k) deg[tri_in[3 * f + k] + 1] += 2;
+        parallel_parts(nv, parts, [&](int64_t v0, int64_t v1, int) {
+            for (int64_t i = 0; i < 3 * nf; ++i) {
+                const int32_t a = tri_in[i];
+                if (a >= v0 && a < v1) deg[a + 1] += 2;
+            }
+        });
         for (int64_t i = 0; i < nv; ++i) deg[i + 1] += deg[i];
         std::vector<int32_t> adj(deg[nv]);
-        std::vector<int32_t> pos(deg.begin(), deg.end() - 1);
-        for (int64_t f = 0; f < nf; ++f)
-            for (int k = 0; k < 3; ++k) {
-                int32_t a = tri_in[3 * f + k], b = tri_in[3 * f + (k + 1) % 3];
-                adj[pos[a]++] = b;
-                adj[pos[b]++] = a;
-            }
+        parallel_parts(nv, parts, [&](int64_t v0, int64_t v1, int) {
+            std::vector<int32_t> pos(deg.begin() + v0, deg.begin() + v1);
+            for (int64_t f = 0; f < nf; ++f)
+                for (int k = 0; k < 3; ++k) {
+                    const int32_t a = tri_in[3 * f + k], b = tri_in[3 * f + (k + 1) % 3];
+                    if (a >= v0 && a < v1) adj[pos[a - v0]++] = b;
+                    if (b >= v0 && b < v1) adj[pos[b - v0]++] = a;
+                }
+        });
         std::vector<int32_t> assigned(nv, -1);
         std::vector<int32_t> queue;
         queue.reserve(P);
@@ -123,260 +165,337 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
     T.px.resize(nv);
     T.py.resize(nv);
     T.pz.resize(nv);
-    for (int64_t i = 0; i < nv; ++i) {
-        int32_t u = order_v[i];
-        T.perm_v[i] = u;
-        T.iperm_v[u] = (int32_t)i;
-        T.px[i] = xyz[3 * u];
-        T.py[i] = xyz[3 * u + 1];
-        T.pz[i] = xyz[3 * u + 2];
-    }
+    parallel_for(nv, 1 << 16, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+            int32_t u = order_v[i];
+            T.perm_v[i] = u;
+            T.iperm_v[u] = (int32_t)i;
+            T.px[i] = xyz[3 * u];
+            T.py[i] = xyz[3 * u + 1];
+            T.pz[i] = xyz[3 * u + 2];
+        }
+    });
     mk.clear();
     mk.shrink_to_fit();
 
     // ---- faces sorted (stably) by smallest internal vertex
-    std::vector<int32_t> cnt(nv + 1, 0);
-    auto fmin = [&](int64_t f) {
-        return std::min({T.iperm_v[tri_in[3 * f]], T.iperm_v[tri_in[3 * f + 1]], T.iperm_v[tri_in[3 * f + 2]]});
-    };
-    for (int64_t f = 0; f < nf; ++f) cnt[fmin(f) + 1]++;
-    for (int64_t i = 0; i < nv; ++i) cnt[i + 1] += cnt[i];
-    T.perm_f.assign(nf, 0);
-    for (int64_t f = 0; f < nf; ++f) T.perm_f[cnt[fmin(f)]++] = (int32_t)f;
-    T.tri.resize(3 * nf);
-    for (int64_t f = 0; f < nf; ++f) {
-        int32_t u = T.perm_f[f];
-        for (int k = 0; k < 3; ++k) T.tri[3 * f + k] = T.iperm_v[tri_in[3 * u + k]];
+    {
+        std::vector<int32_t> key(nf), fptr;
+        parallel_for(nf, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t f = b; f < e; ++f)
+                key[f] = std::min({T.iperm_v[tri_in[3 * f]], T.iperm_v[tri_in[3 * f + 1]],
+                                   T.iperm_v[tri_in[3 * f + 2]]});
+        });
+        group_by_key(key, nv, fptr, T.perm_f);
     }
+    T.tri.resize(3 * nf);
+    parallel_for(nf, 1 << 16, [&](int64_t b, int64_t e) {
+        for (int64_t f = b; f < e; ++f) {
+            int32_t u = T.perm_f[f];
+            for (int k = 0; k < 3; ++k) T.tri[3 * f + k] = T.iperm_v[tri_in[3 * u + k]];
+        }
+    });
 
     // ---- halfedges bucketed by smaller internal endpoint
     const int64_t nh = 3 * nf;
-    std::fill(cnt.begin(), cnt.end(), 0);
-    for (int64_t h = 0; h < nh; ++h) {
-        int32_t a = T.tri[h], b = T.tri[(h / 3) * 3 + (h % 3 + 1) % 3];
-        cnt[std::min(a, b) + 1]++;
-    }
-    for (int64_t i = 0; i < nv; ++i) cnt[i + 1] += cnt[i];
-    std::vector<int32_t> hb(nh);
+    auto hend = [&](int64_t h) { return T.tri[(h / 3) * 3 + (h % 3 + 1) % 3]; };
+    std::vector<int32_t> hptr, hb;
     {
-        std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
-        for (int64_t h = 0; h < nh; ++h) {
-            int32_t a = T.tri[h], b = T.tri[(h / 3) * 3 + (h % 3 + 1) % 3];
-            hb[pos[std::min(a, b)]++] = (int32_t)h;
-        }
-    }
-    auto hother = [&](int32_t h) {
-        int32_t a = T.tri[h], b = T.tri[(h / 3) * 3 + (h % 3 + 1) % 3];
-        return std::max(a, b);
-    };
-    // within a bucket: order by larger endpoint, then halfedge id
-    for (int64_t v = 0; v < nv; ++v) {
-        auto b0 = hb.begin() + cnt[v], b1 = hb.begin() + cnt[v + 1];
-        std::sort(b0, b1, [&](int32_t x, int32_t y) {
-            int32_t ox = hother(x), oy = hother(y);
-            return ox != oy ? ox < oy : x < y;
+        std::vector<int32_t> key(nh);
+        parallel_for(nh, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t h = b; h < e; ++h) key[h] = std::min(T.tri[h], hend(h));
         });
+        group_by_key(key, nv, hptr, hb);
     }
-    // unique edges
+    auto hother = [&](int32_t h) { return std::max(T.tri[h], hend(h)); };
+    // within a bucket: order by larger endpoint, then halfedge id
+    parallel_for(nv, 1 << 14, [&](int64_t vb, int64_t ve) {
+        for (int64_t v = vb; v < ve; ++v)
+            std::sort(hb.begin() + hptr[v], hb.begin() + hptr[v + 1], [&](int32_t x, int32_t y) {
+                int32_t ox = hother(x), oy = hother(y);
+                return ox != oy ? ox < oy : x < y;
+            });
+    });
+    // unique edges: a group of equal (smaller, larger) endpoints never
+    // leaves its bucket, so each worker numbers the groups of a range of
+    // buckets; a first pass counts them (and finds the first invalid edge),
+    // the second writes them at the worker's offset
     T.fslot.assign(nh, 0);
     T.fsign.assign(nf, 0);
-    T.ev.clear();
-    T.ef.clear();
-    T.ev.reserve(nh);   // upper bound, trimmed below
-    T.ef.reserve(nh);
     int64_t ne = 0, nbnd = 0;
-    for (int64_t i = 0; i < nh;) {
-        int32_t h0 = hb[i];
-        int32_t a0 = T.tri[h0], b0 = T.tri[(h0 / 3) * 3 + (h0 % 3 + 1) % 3];
-        int32_t lo_v = std::min(a0, b0), hi_v = std::max(a0, b0);
-        int64_t j = i + 1;
-        while (j < nh) {
-            int32_t h1 = hb[j];
-            int32_t a1 = T.tri[h1], b1 = T.tri[(h1 / 3) * 3 + (h1 % 3 + 1) % 3];
-            if (std::min(a1, b1) != lo_v || std::max(a1, b1) != hi_v) break;
-            ++j;
-        }
-        int64_t m = j - i;
-        if (m > 2) bad("non-manifold edge (more than two incident faces)");
-        // orientation halfedge: from the smaller to the larger caller id
-        int32_t tail = T.perm_v[lo_v] < T.perm_v[hi_v] ? lo_v : hi_v;
-        int32_t head = tail == lo_v ? hi_v : lo_v;
-        if (m == 2) {
-            int32_t h1 = hb[i + 1];
-            int32_t a1 = T.tri[h1];
-            if (a0 == a1) bad("inconsistently oriented faces share an edge");
-        } else {
-            ++nbnd;
-        }
-        T.ev.push_back(tail);
-        T.ev.push_back(head);
-        for (int64_t s = 0; s < 2; ++s) {
-            if (s < m) {
-                int32_t h = hb[i + s];
-                int32_t f = h / 3, k = h % 3;
-                T.ef.push_back(f);
-                T.fslot[h] = ((uint32_t)ne << 2) | ((m == 1 ? 1u : 0u) << 1) | (uint32_t)s;
-                if (T.tri[h] == tail) T.fsign[f] |= (uint8_t)(1u << k);
-            } else {
-                T.ef.push_back(-1);
+    {
+        std::vector<int64_t> pne(parts + 1, 0), pbnd(parts, 0);
+        std::vector<int> perr(parts, 0);   // 1 non-manifold, 2 inconsistent orientation
+        std::vector<uint8_t> tailbit(nh, 0);
+        auto groups = [&](int64_t v0, int64_t v1, int p, bool write) {
+            int64_t n = 0, nb = 0;
+            for (int64_t i = hptr[v0]; i < hptr[v1];) {
+                int32_t h0 = hb[i];
+                int32_t a0 = T.tri[h0], b0 = hend(h0);
+                int32_t lo_v = std::min(a0, b0), hi_v = std::max(a0, b0);
+                int64_t j = i + 1;
+                while (j < hptr[v1]) {
+                    int32_t h1 = hb[j];
+                    int32_t a1 = T.tri[h1], b1 = hend(h1);
+                    if (std::min(a1, b1) != lo_v || std::max(a1, b1) != hi_v) break;
+                    ++j;
+                }
+                const int64_t m = j - i;
+                if (!write) {
+                    if (m > 2) {
+                        perr[p] = 1;
+                        return;
+                    }
+                    if (m == 2 && a0 == T.tri[hb[i + 1]]) {
+                        perr[p] = 2;
+                        return;
+                    }
+                    if (m == 1) ++nb;
+                } else {
+                    // orientation halfedge: from the smaller to the larger caller id
+                    const int32_t tail = T.perm_v[lo_v] < T.perm_v[hi_v] ? lo_v : hi_v;
+                    const int32_t head = tail == lo_v ? hi_v : lo_v;
+                    const int64_t e = pne[p] + n;
+                    T.ev[2 * e] = tail;
+                    T.ev[2 * e + 1] = head;
+                    for (int64_t s = 0; s < 2; ++s) {
+                        if (s < m) {
+                            const int32_t h = hb[i + s];
+                            T.ef[2 * e + s] = h / 3;
+                            T.fslot[h] = ((uint32_t)e << 2) | ((m == 1 ? 1u : 0u) << 1) | (uint32_t)s;
+                            tailbit[h] = T.tri[h] == tail;
+                        } else {
+                            T.ef[2 * e + s] = -1;
+                        }
+                    }
+                }
+                ++n;
+                i = j;
             }
+            if (!write) {
+                pne[p + 1] = n;
+                pbnd[p] = nb;
+            }
+        };
+        parallel_parts(nv, parts, [&](int64_t v0, int64_t v1, int p) { groups(v0, v1, p, false); });
+        for (int p = 0; p < parts; ++p) {
+            if (perr[p] == 1) bad("non-manifold edge (more than two incident faces)");
+            if (perr[p] == 2) bad("inconsistently oriented faces share an edge");
         }
-        ++ne;
-        i = j;
+        for (int p = 0; p < parts; ++p) {
+            pne[p + 1] += pne[p];
+            nbnd += pbnd[p];
+        }
+        ne = pne[parts];
+        if (ne >= (1ll << 30)) throw Error{HG_E_INVALID_ARG, "too many edges"};
+        T.ev.assign(2 * ne, 0);
+        T.ef.assign(2 * ne, 0);
+        parallel_parts(nv, parts, [&](int64_t v0, int64_t v1, int p) { groups(v0, v1, p, true); });
+        parallel_for(nf, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t f = b; f < e; ++f)
+                T.fsign[f] = (uint8_t)(tailbit[3 * f] | (tailbit[3 * f + 1] << 1) | (tailbit[3 * f + 2] << 2));
+        });
     }
-    if (ne >= (1ll << 30)) throw Error{HG_E_INVALID_ARG, "too many edges"};
     T.ne = ne;
     T.nbnd = nbnd;
-    T.ev.shrink_to_fit();
-    T.ef.shrink_to_fit();
     hb.clear();
     hb.shrink_to_fit();
+    hptr.clear();
+    hptr.shrink_to_fit();
 
     // ---- internal edge order: by owning face (the side-0 face, which has the
     //      smaller internal id), then slot, so consecutive faces touch mostly
     //      consecutive edges
     {
         std::vector<int32_t> nid(ne, -1);
-        int32_t next = 0;
-        for (int64_t h = 0; h < nh; ++h) {
-            uint32_t sl = T.fslot[h];
-            if ((sl & 1u) == 0u) nid[sl >> 2] = next++;
-        }
+        std::vector<int64_t> pcnt(parts + 1, 0);
+        parallel_parts(nh, parts, [&](int64_t b, int64_t e, int p) {
+            int64_t c = 0;
+            for (int64_t h = b; h < e; ++h) c += (T.fslot[h] & 1u) == 0u;
+            pcnt[p + 1] = c;
+        });
+        for (int p = 0; p < parts; ++p) pcnt[p + 1] += pcnt[p];
+        parallel_parts(nh, parts, [&](int64_t b, int64_t e, int p) {
+            int32_t next = (int32_t)pcnt[p];
+            for (int64_t h = b; h < e; ++h) {
+                uint32_t sl = T.fslot[h];
+                if ((sl & 1u) == 0u) nid[sl >> 2] = next++;
+            }
+        });
         std::vector<int32_t> ev2(2 * ne), ef2(2 * ne);
-        for (int64_t e = 0; e < ne; ++e) {
-            int32_t n = nid[e];
-            ev2[2 * n] = T.ev[2 * e];
-            ev2[2 * n + 1] = T.ev[2 * e + 1];
-            ef2[2 * n] = T.ef[2 * e];
-            ef2[2 * n + 1] = T.ef[2 * e + 1];
-        }
+        parallel_for(ne, 1 << 16, [&](int64_t b, int64_t eend) {
+            for (int64_t e = b; e < eend; ++e) {
+                int32_t n = nid[e];
+                ev2[2 * n] = T.ev[2 * e];
+                ev2[2 * n + 1] = T.ev[2 * e + 1];
+                ef2[2 * n] = T.ef[2 * e];
+                ef2[2 * n + 1] = T.ef[2 * e + 1];
+            }
+        });
         T.ev.swap(ev2);
         T.ef.swap(ef2);
-        for (int64_t h = 0; h < nh; ++h) {
-            uint32_t sl = T.fslot[h];
-            T.fslot[h] = ((uint32_t)nid[sl >> 2] << 2) | (sl & 3u);
-        }
+        parallel_for(nh, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t h = b; h < e; ++h) {
+                uint32_t sl = T.fslot[h];
+                T.fslot[h] = ((uint32_t)nid[sl >> 2] << 2) | (sl & 3u);
+            }
+        });
     }
 
     // ---- slot twins
     {
         T.h01.assign(2 * ne, -1);
-        for (int64_t h = 0; h < nh; ++h) {
-            uint32_t sl = T.fslot[h];
-            T.h01[2 * (sl >> 2) + (sl & 1u)] = (int32_t)h;
-        }
-        T.twin.assign(nh, -1);
-        for (int64_t e = 0; e < ne; ++e)
-            if (T.h01[2 * e + 1] >= 0) {
-                T.twin[T.h01[2 * e]] = T.h01[2 * e + 1];
-                T.twin[T.h01[2 * e + 1]] = T.h01[2 * e];
+        parallel_for(nh, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t h = b; h < e; ++h) {
+                uint32_t sl = T.fslot[h];
+                T.h01[2 * (sl >> 2) + (sl & 1u)] = (int32_t)h;
             }
+        });
+        T.twin.assign(nh, -1);
+        parallel_for(ne, 1 << 16, [&](int64_t b, int64_t eend) {
+            for (int64_t e = b; e < eend; ++e)
+                if (T.h01[2 * e + 1] >= 0) {
+                    T.twin[T.h01[2 * e]] = T.h01[2 * e + 1];
+                    T.twin[T.h01[2 * e + 1]] = T.h01[2 * e];
+                }
+        });
     }
 
     // ---- canonical edge numbering: sort by (min caller id, max caller id)
     {
-        std::vector<int32_t> c2(nv + 1, 0);
         auto umin = [&](int64_t e) { return std::min(T.perm_v[T.ev[2 * e]], T.perm_v[T.ev[2 * e + 1]]); };
         auto umax = [&](int64_t e) { return std::max(T.perm_v[T.ev[2 * e]], T.perm_v[T.ev[2 * e + 1]]); };
-        for (int64_t e = 0; e < ne; ++e) c2[umin(e) + 1]++;
-        for (int64_t i = 0; i < nv; ++i) c2[i + 1] += c2[i];
-        std::vector<int32_t> order(ne);
-        std::vector<int32_t> pos(c2.begin(), c2.end() - 1);
-        for (int64_t e = 0; e < ne; ++e) order[pos[umin(e)]++] = (int32_t)e;
-        for (int64_t v = 0; v < nv; ++v)
-            std::sort(order.begin() + c2[v], order.begin() + c2[v + 1],
-                      [&](int32_t x, int32_t y) { return umax(x) < umax(y); });
+        std::vector<int32_t> key(ne), c2, order;
+        parallel_for(ne, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t x = b; x < e; ++x) key[x] = umin(x);
+        });
+        group_by_key(key, nv, c2, order);
+        parallel_for(nv, 1 << 14, [&](int64_t vb, int64_t ve) {
+            for (int64_t v = vb; v < ve; ++v)
+                std::sort(order.begin() + c2[v], order.begin() + c2[v + 1],
+                          [&](int32_t x, int32_t y) { return umax(x) < umax(y); });
+        });
         T.perm_e.assign(ne, 0);
-        for (int64_t r = 0; r < ne; ++r) T.perm_e[order[r]] = (int32_t)r;
+        parallel_for(ne, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t r = b; r < e; ++r) T.perm_e[order[r]] = (int32_t)r;
+        });
     }
 
     // ---- CSR adjacency in internal order, neighbours sorted by internal id
     T.row_ptr.assign(nv + 1, 0);
-    for (int64_t e = 0; e < ne; ++e) {
-        T.row_ptr[T.ev[2 * e] + 1]++;
-        T.row_ptr[T.ev[2 * e + 1] + 1]++;
-    }
+    parallel_parts(nv, parts, [&](int64_t v0, int64_t v1, int) {
+        for (int64_t i = 0; i < 2 * ne; ++i) {
+            const int32_t a = T.ev[i];
+            if (a >= v0 && a < v1) T.row_ptr[a + 1]++;
+        }
+    });
     for (int64_t i = 0; i < nv; ++i) T.row_ptr[i + 1] += T.row_ptr[i];
     T.col.assign(2 * ne, 0);
     T.csr_edge.assign(2 * ne, 0);
-    {
-        std::vector<int32_t> pos(T.row_ptr.begin(), T.row_ptr.end() - 1);
+    parallel_parts(nv, parts, [&](int64_t v0, int64_t v1, int) {
+        std::vector<int32_t> pos(T.row_ptr.begin() + v0, T.row_ptr.begin() + v1);
         for (int64_t e = 0; e < ne; ++e) {
-            int32_t a = T.ev[2 * e], b = T.ev[2 * e + 1];
-            T.col[pos[a]] = b;
-            T.csr_edge[pos[a]++] = (int32_t)e;
-            T.col[pos[b]] = a;
-            T.csr_edge[pos[b]++] = (int32_t)e;
+            const int32_t a = T.ev[2 * e], b = T.ev[2 * e + 1];
+            if (a >= v0 && a < v1) {
+                T.col[pos[a - v0]] = b;
+                T.csr_edge[pos[a - v0]++] = (int32_t)e;
+            }
+            if (b >= v0 && b < v1) {
+                T.col[pos[b - v0]] = a;
+                T.csr_edge[pos[b - v0]++] = (int32_t)e;
+            }
         }
+    });
+    {
+        std::vector<int> pmax(parts, 0);
+        parallel_parts(nv, parts, [&](int64_t vb, int64_t ve, int p) {
+            std::vector<std::pair<int32_t, int32_t>> tmp;
+            int maxdeg = 0;
+            for (int64_t v = vb; v < ve; ++v) {
+                int32_t b = T.row_ptr[v], e = T.row_ptr[v + 1];
+                maxdeg = std::max(maxdeg, e - b);
+                tmp.clear();
+                for (int32_t k = b; k < e; ++k) tmp.push_back({T.col[k], T.csr_edge[k]});
+                std::sort(tmp.begin(), tmp.end());
+                for (int32_t k = b; k < e; ++k) {
+                    T.col[k] = tmp[k - b].first;
+                    T.csr_edge[k] = tmp[k - b].second;
+                }
+            }
+            pmax[p] = maxdeg;
+        });
+        T.max_valence = *std::max_element(pmax.begin(), pmax.end());
     }
-    int maxdeg = 0;
-    std::vector<std::pair<int32_t, int32_t>> tmp;
-    for (int64_t v = 0; v < nv; ++v) {
-        int32_t b = T.row_ptr[v], e = T.row_ptr[v + 1];
-        maxdeg = std::max(maxdeg, e - b);
-        tmp.clear();
-        for (int32_t k = b; k < e; ++k) tmp.push_back({T.col[k], T.csr_edge[k]});
-        std::sort(tmp.begin(), tmp.end());
-        for (int32_t k = b; k < e; ++k) {
-            T.col[k] = tmp[k - b].first;
-            T.csr_edge[k] = tmp[k - b].second;
-        }
-    }
-    T.max_valence = maxdeg;
 
-    // ---- LDS tiles: halos and ELL local slots of the tiles built above
+    // ---- LDS tiles: halos and ELL local slots of the tiles built above.
+    //      Per tile in parallel: its halo and ELL width; then the offsets (and
+    //      the first invalid tile, in tile order); then the tables.
     T.patch_size = P;
     const int64_t np = (int64_t)T.tile_ptr.size() - 1;
     T.halo_ptr.assign(np + 1, 0);
-    T.halo_idx.clear();
     T.ell_ptr.assign(np + 1, 0);
     T.ell_width.assign(np, 0);
-    T.lnb.clear();
     T.max_halo = 0;
     T.max_ell_width = 0;
-    std::vector<int32_t> hmap;   // global -> halo slot for the current tile
-    std::vector<int32_t> halo;
-    for (int64_t p = 0; p < np; ++p) {
-        int64_t v0 = T.tile_ptr[p], v1 = T.tile_ptr[p + 1];
-        halo.clear();
-        int width = 0;
-        for (int64_t v = v0; v < v1; ++v) {
-            width = std::max(width, T.row_ptr[v + 1] - T.row_ptr[v]);
-            for (int32_t k = T.row_ptr[v]; k < T.row_ptr[v + 1]; ++k) {
-                int32_t u = T.col[k];
-                if (u < v0 || u >= v1) halo.push_back(u);
-            }
-        }
-        std::sort(halo.begin(), halo.end());
-        halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
-        if ((int64_t)P + (int64_t)halo.size() >= 65535)
-            throw Error{HG_E_BAD_MESH, "tile halo too large for 16-bit local slots"};
-        T.halo_idx.insert(T.halo_idx.end(), halo.begin(), halo.end());
-        T.halo_ptr[p + 1] = (int32_t)T.halo_idx.size();
-        T.max_halo = std::max<int>(T.max_halo, (int)halo.size());
-        T.ell_width[p] = (uint8_t)std::min(width, 255);
-        if (width > 255) throw Error{HG_E_BAD_MESH, "vertex valence above 255"};
-        T.max_ell_width = std::max(T.max_ell_width, width);
-        int64_t base = T.lnb.size();
-        T.ell_ptr[p] = (int32_t)base;
-        T.lnb.resize(base + (int64_t)width * P, (uint16_t)0xFFFF);
-        for (int64_t v = v0; v < v1; ++v) {
-            int i = (int)(v - v0);
-            int s = 0;
-            for (int32_t k = T.row_ptr[v]; k < T.row_ptr[v + 1]; ++k, ++s) {
-                int32_t u = T.col[k];
-                uint16_t l;
-                if (u >= v0 && u < v1) {
-                    l = (uint16_t)(u - v0);
-                } else {
-                    l = (uint16_t)(P + (std::lower_bound(halo.begin(), halo.end(), u) - halo.begin()));
+    {
+        std::vector<std::vector<int32_t>> halos(np);
+        std::vector<int32_t> width(np, 0);
+        parallel_for(np, 16, [&](int64_t pb, int64_t pe) {
+            for (int64_t p = pb; p < pe; ++p) {
+                const int64_t v0 = T.tile_ptr[p], v1 = T.tile_ptr[p + 1];
+                auto& halo = halos[p];
+                int w = 0;
+                for (int64_t v = v0; v < v1; ++v) {
+                    w = std::max(w, T.row_ptr[v + 1] - T.row_ptr[v]);
+                    for (int32_t k = T.row_ptr[v]; k < T.row_ptr[v + 1]; ++k) {
+                        int32_t u = T.col[k];
+                        if (u < v0 || u >= v1) halo.push_back(u);
+                    }
                 }
-                T.lnb[base + (int64_t)s * P + i] = l;
+                std::sort(halo.begin(), halo.end());
+                halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+                width[p] = w;
             }
+        });
+        int64_t base = 0;
+        for (int64_t p = 0; p < np; ++p) {
+            if ((int64_t)P + (int64_t)halos[p].size() >= 65535)
+                throw Error{HG_E_BAD_MESH, "tile halo too large for 16-bit local slots"};
+            T.halo_ptr[p + 1] = T.halo_ptr[p] + (int32_t)halos[p].size();
+            T.max_halo = std::max<int>(T.max_halo, (int)halos[p].size());
+            T.ell_width[p] = (uint8_t)std::min(width[p], 255);
+            if (width[p] > 255) throw Error{HG_E_BAD_MESH, "vertex valence above 255"};
+            T.max_ell_width = std::max(T.max_ell_width, width[p]);
+            T.ell_ptr[p] = (int32_t)base;
+            base += (int64_t)width[p] * P;
+            if (base >= (1ll << 31)) throw Error{HG_E_INVALID_ARG, "tile table too large"};
         }
-        if ((int64_t)T.lnb.size() >= (1ll << 31)) throw Error{HG_E_INVALID_ARG, "tile table too large"};
+        T.ell_ptr[np] = (int32_t)base;
+        T.halo_idx.assign(T.halo_ptr[np], 0);
+        T.lnb.assign(base, (uint16_t)0xFFFF);
+        parallel_for(np, 16, [&](int64_t pb, int64_t pe) {
+            for (int64_t p = pb; p < pe; ++p) {
+                const int64_t v0 = T.tile_ptr[p], v1 = T.tile_ptr[p + 1];
+                const auto& halo = halos[p];
+                std::copy(halo.begin(), halo.end(), T.halo_idx.begin() + T.halo_ptr[p]);
+                const int64_t b = T.ell_ptr[p];
+                for (int64_t v = v0; v < v1; ++v) {
+                    int i = (int)(v - v0);
+                    int s = 0;
+                    for (int32_t k = T.row_ptr[v]; k < T.row_ptr[v + 1]; ++k, ++s) {
+                        int32_t u = T.col[k];
+                        uint16_t l;
+                        if (u >= v0 && u < v1) {
+                            l = (uint16_t)(u - v0);
+                        } else {
+                            l = (uint16_t)(P + (std::lower_bound(halo.begin(), halo.end(), u) - halo.begin()));
+                        }
+                        T.lnb[b + (int64_t)s * P + i] = l;
+                    }
+                }
+            }
+        });
     }
-    T.ell_ptr[np] = (int32_t)T.lnb.size();
 
     // ---- connected components (several meshes may be packed into one)
     {
