@@ -497,38 +497,70 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
         });
     }
 
-    // ---- connected components (several meshes may be packed into one)
+    // ---- tile adjacency: a tile's halo lies in its neighbour tiles
+    std::vector<int32_t> tile_of(nv);
+    parallel_for(np, 16, [&](int64_t pb, int64_t pe) {
+        for (int64_t p = pb; p < pe; ++p)
+            for (int32_t v = T.tile_ptr[p]; v < T.tile_ptr[p + 1]; ++v) tile_of[v] = (int32_t)p;
+    });
+    std::vector<std::vector<int32_t>> adj(np);
+    for (int64_t p = 0; p < np; ++p)
+        for (int32_t h = T.halo_ptr[p]; h < T.halo_ptr[p + 1]; ++h) {
+            const int32_t q = tile_of[T.halo_idx[h]];
+            adj[p].push_back(q);
+            adj[q].push_back((int32_t)p);
+        }
+    parallel_for(np, 64, [&](int64_t pb, int64_t pe) {
+        for (int64_t p = pb; p < pe; ++p) {
+            auto& a = adj[p];
+            std::sort(a.begin(), a.end());
+            a.erase(std::unique(a.begin(), a.end()), a.end());
+        }
+    });
+
+    // ---- connected components (several meshes may be packed into one):
+    //      tiles are connected, so the components are those of the tile
+    //      graph; numbered in the order of their smallest caller vertex id
     {
-        T.comp.assign(nv, -1);
-        std::vector<int32_t> stack;
-        std::vector<int32_t> first_caller;   // smallest caller id per provisional component
+        std::vector<int32_t> tc(np, -1), stack;
         int nc = 0;
-        for (int64_t v = 0; v < nv; ++v) {
-            if (T.comp[v] >= 0) continue;
-            int32_t lo = T.perm_v[v];
-            T.comp[v] = nc;
-            stack.assign(1, (int32_t)v);
+        for (int64_t p0 = 0; p0 < np; ++p0) {
+            if (tc[p0] >= 0) continue;
+            tc[p0] = nc;
+            stack.assign(1, (int32_t)p0);
             while (!stack.empty()) {
-                int32_t u = stack.back();
+                const int32_t p = stack.back();
                 stack.pop_back();
-                lo = std::min(lo, T.perm_v[u]);
-                for (int32_t k = T.row_ptr[u]; k < T.row_ptr[u + 1]; ++k) {
-                    int32_t x = T.col[k];
-                    if (T.comp[x] < 0) {
-                        T.comp[x] = nc;
-                        stack.push_back(x);
+                for (int32_t q : adj[p])
+                    if (tc[q] < 0) {
+                        tc[q] = nc;
+                        stack.push_back(q);
                     }
-                }
             }
-            first_caller.push_back(lo);
             ++nc;
         }
+        std::vector<int32_t> tile_lo(np);
+        parallel_for(np, 16, [&](int64_t pb, int64_t pe) {
+            for (int64_t p = pb; p < pe; ++p) {
+                int32_t lo = 0x7fffffff;
+                for (int32_t v = T.tile_ptr[p]; v < T.tile_ptr[p + 1]; ++v) lo = std::min(lo, T.perm_v[v]);
+                tile_lo[p] = lo;
+            }
+        });
+        std::vector<int32_t> first_caller(nc, 0x7fffffff);
+        for (int64_t p = 0; p < np; ++p) first_caller[tc[p]] = std::min(first_caller[tc[p]], tile_lo[p]);
         std::vector<int32_t> ord(nc), rank(nc);
         for (int c = 0; c < nc; ++c) ord[c] = c;
         std::sort(ord.begin(), ord.end(), [&](int a, int b) { return first_caller[a] < first_caller[b]; });
         for (int c = 0; c < nc; ++c) rank[ord[c]] = c;
-        for (int64_t v = 0; v < nv; ++v) T.comp[v] = rank[T.comp[v]];
         T.n_comp = nc;
+        T.tile_comp.assign(np, 0);
+        for (int64_t p = 0; p < np; ++p) T.tile_comp[p] = rank[tc[p]];
+        T.comp.assign(nv, -1);
+        parallel_for(nv, 1 << 16, [&](int64_t b, int64_t e) {
+            for (int64_t v = b; v < e; ++v) T.comp[v] = T.tile_comp[tile_of[v]];
+        });
+        // mean edge length per component, summed in edge order
         std::vector<double> len(nc, 0.0);
         std::vector<int64_t> cnt(nc, 0);
         for (int64_t e = 0; e < ne; ++e) {
@@ -539,27 +571,10 @@ void build_topology(const double* xyz, int64_t nv, const int32_t* tri_in, int64_
         }
         T.comp_hbar.assign(nc, 0.0);
         for (int c = 0; c < nc; ++c) T.comp_hbar[c] = cnt[c] ? len[c] / (double)cnt[c] : 0.0;
-        T.tile_comp.assign(np, 0);
-        for (int64_t p = 0; p < np; ++p) T.tile_comp[p] = T.comp[T.tile_ptr[p]];
     }
 
-    // ---- colouring of the tiles: a tile's halo lies in its neighbour
-    //      tiles, so tiles of one colour never read each other
+    // ---- colouring of the tiles: tiles of one colour never read each other
     {
-        std::vector<int32_t> tile_of(nv);
-        for (int64_t p = 0; p < np; ++p)
-            for (int32_t v = T.tile_ptr[p]; v < T.tile_ptr[p + 1]; ++v) tile_of[v] = (int32_t)p;
-        std::vector<std::vector<int32_t>> adj(np);
-        for (int64_t p = 0; p < np; ++p)
-            for (int32_t h = T.halo_ptr[p]; h < T.halo_ptr[p + 1]; ++h) {
-                const int32_t q = tile_of[T.halo_idx[h]];
-                adj[p].push_back(q);
-                adj[q].push_back((int32_t)p);
-            }
-        for (auto& a : adj) {
-            std::sort(a.begin(), a.end());
-            a.erase(std::unique(a.begin(), a.end()), a.end());
-        }
         colour_tiles(adj, T.color_ptr, T.tile_order, slots);
         T.tile_adj_ptr.assign(np + 1, 0);
         for (int64_t p = 0; p < np; ++p) T.tile_adj_ptr[p + 1] = T.tile_adj_ptr[p] + (int32_t)adj[p].size();
