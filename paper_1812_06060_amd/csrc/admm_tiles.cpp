@@ -20,6 +20,7 @@
 #include <thread>
 
 #include "hgeo_internal.h"
+#include "host_par.h"
 
 namespace hg {
 
@@ -85,7 +86,7 @@ bool build_edge_tiles(int64_t nf, const std::vector<int32_t>& tri, const std::ve
     std::vector<std::vector<int32_t>> halo(nt);
     std::vector<std::vector<uint64_t>> rec(nt);
     std::vector<int> nreg(nt, 0);
-    int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int nth = host_threads();
     std::vector<int> too_big(nth, 0);
     auto work = [&](int id) {
         int cap = 1;
