@@ -16,7 +16,7 @@ static thread_local std::string g_last_error;
 std::string& last_error_ref() { return g_last_error; }
 
 size_t Work::bytes() const {
-    return level.bytes() + parent.bytes() + pslot.bytes() + frontier_a.bytes() + frontier_b.bytes() +
+    return level.bytes() + parent.bytes() + pedge.bytes() + frontier_a.bytes() + frontier_b.bytes() +
            counters.bytes() + v0.bytes() + v1.bytes() + invD.bytes() + e0.bytes() + e1.bytes() + logu.bytes() +
            h.bytes() + sumz.bytes() + sumd.bytes() + z0.bytes() + z1.bytes() + g0.bytes() + g1.bytes() + xe.bytes() + gf.bytes() +
            shi0.bytes() + slo0.bytes() + shi1.bytes() + slo1.bytes() + jp0.bytes() + jp1.bytes() + partial.bytes() +

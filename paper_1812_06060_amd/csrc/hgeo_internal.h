@@ -252,7 +252,7 @@ struct Work {
         if (!own_stream) HG_CHECK_HIP(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
         if (!ev) HG_CHECK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     }
-    DBuf<int32_t> level, parent, pslot, frontier_a, frontier_b, counters;
+    DBuf<int32_t> level, parent, pedge, frontier_a, frontier_b, counters;   // pedge: the edge to the parent
     DBuf<double> v0, v1, invD;          // diffusion mantissas, 1/(A + t sum theta)
     DBuf<double> tcomp, tile_t;         // diffusion time per component and per tile
     DBuf<int32_t> e0, e1;               // diffusion exponents
@@ -420,9 +420,10 @@ struct Mesh {
 void geometry_init(Mesh& m, hipStream_t s, const std::vector<double>* elen = nullptr);
 int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, hipStream_t s);
 // The breadth-first search on caller-provided device buffers: level, parent,
-// pslot, frontier_a, frontier_b [nv] each, counters [8], src [nsrc].
+// pedge (the edge to the parent), frontier_a, frontier_b [nv] each, counters [8],
+// src [nsrc].
 struct BfsBuffers {
-    int32_t *level, *parent, *pslot, *frontier_a, *frontier_b, *counters, *src;
+    int32_t *level, *parent, *pedge, *frontier_a, *frontier_b, *counters, *src;
 };
 int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src_internal, hipStream_t s);
 // caller id -> internal id of each source, checked (throws HG_E_INVALID_ARG)
@@ -535,7 +536,7 @@ AdmmResult run_admm_face(Mesh& m, Work& w, int iters, const hg_opts& o, hipStrea
 // Builds w.paths: with source_paths, the paths between the (internal)
 // sources (Eqs. 24-25); with cycles, the mesh's generator loops in the given
 // form (Sec. 5.1).  The source paths come from breadth-first searches from
-// single sources, which overwrite level/parent/pslot: run the query's own
+// single sources, which overwrite level/parent/pedge: run the query's own
 // breadth-first search after it.
 void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_internal, bool source_paths,
                             bool cycles, int form, hipStream_t s);

@@ -86,8 +86,10 @@ __global__ void k_bfs_expand(int L, int nv, const int32_t* __restrict__ row_ptr,
     }
 }
 
-__global__ void k_bfs_parent(int nv, const int32_t* row_ptr, const int32_t* col, const int32_t* level,
-                             const int32_t* perm_v, int32_t* parent, int32_t* pslot) {
+// Each reached vertex's partner in the previous set (the neighbour of smallest
+// caller id) and the edge to it, -1 for sources and unreached vertices.
+__global__ void k_bfs_parent(int nv, const int32_t* row_ptr, const int32_t* col, const int32_t* csr_edge,
+                             const int32_t* level, const int32_t* perm_v, int32_t* parent, int32_t* pedge) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nv) return;
     int lj = level[j];
@@ -106,7 +108,7 @@ __global__ void k_bfs_parent(int nv, const int32_t* row_ptr, const int32_t* col,
         }
     }
     parent[j] = best;
-    pslot[j] = bslot;
+    pedge[j] = bslot >= 0 ? csr_edge[bslot] : -1;
 }
 
 int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, hipStream_t s) {
@@ -142,7 +144,7 @@ int run_bfs_into(Mesh& m, const BfsBuffers& b, const std::vector<int32_t>& src, 
         if (L > nv + 1) break;
     }
     hipLaunchKernelGGL(k_bfs_parent, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, m.row_ptr.p, m.col.p,
-                       b.level, m.perm_v.p, b.parent, b.pslot);
+                       m.csr_edge.p, b.level, m.perm_v.p, b.parent, b.pedge);
     HG_CHECK_HIP(hipGetLastError());
     HG_CHECK_HIP(hipMemcpyAsync(hc, b.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HG_CHECK_HIP(hipStreamSynchronize(s));
@@ -391,7 +393,7 @@ static int run_bfs_tiles(Mesh& m, const BfsBuffers& b, int32_t* mark, const std:
     hipLaunchKernelGGL(k_bfs_tile_finish, dim3(nb), dim3(kBlockB), 0, s, nv, b.level, b.frontier_a);
     hipLaunchKernelGGL(k_bfs_depth, dim3(1), dim3(1024), 0, s, nb, b.frontier_a, b.counters);
     hipLaunchKernelGGL(k_bfs_parent, dim3(grid_for(nv, kBlockB)), dim3(kBlockB), 0, s, nv, m.row_ptr.p, m.col.p,
-                       b.level, m.perm_v.p, b.parent, b.pslot);
+                       m.csr_edge.p, b.level, m.perm_v.p, b.parent, b.pedge);
     HG_CHECK_HIP(hipGetLastError());
     HG_CHECK_HIP(hipMemcpyAsync(hc, b.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HG_CHECK_HIP(hipStreamSynchronize(s));
@@ -402,12 +404,12 @@ int run_bfs(Mesh& m, Work& w, const std::vector<int32_t>& src, hipStream_t s) {
     const int nv = (int)m.nv;
     w.level.alloc(nv);
     w.parent.alloc(nv);
-    w.pslot.alloc(nv);
+    w.pedge.alloc(nv);
     w.frontier_a.alloc(nv);
     w.frontier_b.alloc(nv);
     w.counters.alloc(8);
     w.src.alloc(src.size());
-    BfsBuffers b{w.level.p, w.parent.p, w.pslot.p, w.frontier_a.p, w.frontier_b.p, w.counters.p, w.src.p};
+    BfsBuffers b{w.level.p, w.parent.p, w.pedge.p, w.frontier_a.p, w.frontier_b.p, w.counters.p, w.src.p};
     if (!bfs_tiles_supported(m)) return run_bfs_into(m, b, src, s);
     w.tile_mark.alloc((size_t)m.n_patches);
     return run_bfs_tiles(m, b, w.tile_mark.p, src, s);

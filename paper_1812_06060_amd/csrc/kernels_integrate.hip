@@ -79,29 +79,32 @@ __global__ void k_block_due(int nv, const int32_t* comp, const uint8_t* cdue, ui
 }
 
 // Per vertex: the change along the edge to its partner, and the jump state.
-__global__ void k_int_step(int nv, int form, const int32_t* level, const int32_t* parent, const int32_t* pslot,
-                           const int32_t* csr_edge, const int32_t* ev, const int32_t* ef, const float* xe,
+__global__ void k_int_step(int nv, int form, const int32_t* level, const int32_t* parent, const int32_t* pedge,
+                           const int32_t* ev, const int32_t* ef, const float* xe,
                            const int32_t* h01, EdgeX ex, const float* g, const double* px, const double* py,
                            const double* pz, float* shi, float* slo, int32_t* jp, CheckDue due) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nv || !vertex_due(due, blockIdx.x, j)) return;
-    int lj = level[j];
+    // the three per-vertex loads issued together (parent and edge are -1
+    // on sources and unreached vertices, and not used there)
+    const int lj = level[j];
+    const int k = parent[j];
+    const int e = pedge[j];
     if (lj <= 0) {
         shi[j] = lj == 0 ? 0.f : INFINITY;
         slo[j] = 0.f;
         jp[j] = lj == 0 ? j : -1;
         return;
     }
-    int k = parent[j];
-    int e = csr_edge[pslot[j]];
     double step;
     if (form == HG_FORM_EDGE) {
         double x;
         if (xe) {
             x = (double)xe[e];
         } else {   // formed here, as k_edge_x forms it
+            // an edge has a side-1 slot exactly when it has a second face
             const int h0 = h01[2 * e], h1 = h01[2 * e + 1];
-            x = (double)edge_x(ex.S[e], ex.z[h0], h1 >= 0 ? ex.z[h1] : 0.f, ef[2 * e + 1] < 0, ex.inv1mu);
+            x = (double)edge_x(ex.S[e], ex.z[h0], h1 >= 0 ? ex.z[h1] : 0.f, h1 < 0, ex.inv1mu);
         }
         step = (ev[2 * e + 1] == j) ? x : -x;
     } else {
@@ -166,8 +169,8 @@ static IntSums integrate_sums(Mesh& m, Work& w, int form, int depth, const float
     w.jp0.alloc(nv);
     w.jp1.alloc(nv);
     const int grid = grid_for(nv, kBlockI);
-    hipLaunchKernelGGL(k_int_step, dim3(grid), dim3(kBlockI), 0, s, nv, form, w.level.p, w.parent.p, w.pslot.p,
-                       m.csr_edge.p, m.ev.p, m.ef.p, ex ? nullptr : xe, m.h01.p, ex ? *ex : EdgeX{nullptr, nullptr, 0.f},
+    hipLaunchKernelGGL(k_int_step, dim3(grid), dim3(kBlockI), 0, s, nv, form, w.level.p, w.parent.p, w.pedge.p,
+                       m.ev.p, m.ef.p, ex ? nullptr : xe, m.h01.p, ex ? *ex : EdgeX{nullptr, nullptr, 0.f},
                        g, m.px.p, m.py.p, m.pz.p, w.shi0.p, w.slo0.p, w.jp0.p, due);
     HG_CHECK_HIP(hipGetLastError());
     // after r rounds every vertex sums 2^r chain edges; sources stop the walk

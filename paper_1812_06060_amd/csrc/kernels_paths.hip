@@ -49,15 +49,15 @@ __global__ void k_path_walk(int np, const int32_t* src, const int32_t* base, con
     }
 }
 
-__global__ void k_path_slots(int ns, const int32_t* vert, const int32_t* parent, const int32_t* pslot,
-                             const int32_t* csr_edge, const int32_t* ev, const int32_t* ef, const uint32_t* fslot,
+__global__ void k_path_slots(int ns, const int32_t* vert, const int32_t* parent, const int32_t* pedge,
+                             const int32_t* ev, const int32_t* ef, const uint32_t* fslot,
                              const uint8_t* fsign, const double* px, const double* py, const double* pz,
                              int32_t* edge, float* sign, int32_t* face, float* vec) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ns) return;
     const int v = vert[k];
     const int p = parent[v];
-    const int e = csr_edge[pslot[v]];
+    const int e = pedge[v];
     const bool along = ev[2 * e] == p;   // the path runs p -> v
     edge[k] = e;
     sign[k] = along ? 1.f : -1.f;
@@ -185,7 +185,7 @@ void build_constraint_paths(Mesh& m, Work& w, const std::vector<int32_t>& src_in
             hipLaunchKernelGGL(k_path_walk, dim3(grid_for(np, 64)), dim3(64), 0, s, np, d_src.p, d_base.p, d_len.p,
                                w.parent.p, d_vert.p);
             hipLaunchKernelGGL(k_path_slots, dim3(grid_for(ns, kBlockP)), dim3(kBlockP), 0, s, ns, d_vert.p,
-                               w.parent.p, w.pslot.p, m.csr_edge.p, m.ev.p, m.ef.p, m.fslot.p, m.fsign.p,
+                               w.parent.p, w.pedge.p, m.ev.p, m.ef.p, m.fslot.p, m.fsign.p,
                                m.px.p, m.py.p, m.pz.p, d_edge.p, d_sign.p, d_face.p, d_vec.p);
             HG_CHECK_HIP(hipGetLastError());
             const size_t o = h_edge.size();

@@ -75,7 +75,7 @@ extern "C" hg_status hg_bfs_noalloc(hg_mesh_t mesh, const int32_t* src, int32_t 
         BfsBuffers b;
         b.level = take(nvb);
         b.parent = take(nvb);
-        b.pslot = take(nvb);
+        b.pedge = take(nvb);
         b.frontier_a = take(nvb);
         b.frontier_b = take(nvb);
         b.counters = take(256);

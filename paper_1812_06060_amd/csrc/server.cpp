@@ -44,7 +44,7 @@ static double now_s() {
 // pointer-jumping parents, plus the source paths (bounded by nsrc * depth).
 uint64_t work_estimate(const Mesh& m, int form, int nsrc) {
     const uint64_t nv = m.nv, nf = m.nf, ne = m.ne;
-    uint64_t b = 24 * nv          // level, parent, pslot, two frontiers, counters
+    uint64_t b = 24 * nv          // level, parent, pedge, two frontiers, counters
                  + 24 * nv + 8 * nv + 8 * nv   // v0, v1, invD; e0, e1; logu
                  + 12 * nf + 4 * ne           // h, target sums
                  + 4 * ne + 12 * nf           // xe, gf
