@@ -17,7 +17,6 @@
 // slot and kTwinOut for a twin outside the region; bits 48..50 hold the
 // face's sign bits (Eq. 20).
 #include <algorithm>
-#include <thread>
 
 #include "hgeo_internal.h"
 #include "host_par.h"
@@ -151,9 +150,9 @@ bool build_edge_tiles(int64_t nf, const std::vector<int32_t>& tri, const std::ve
             }
         }
     };
-    std::vector<std::thread> pool;
-    for (int i = 0; i < nth; ++i) pool.emplace_back(work, i);
-    for (auto& t : pool) t.join();
+    parallel_parts(nth, nth, [&](int64_t b, int64_t e, int) {
+        for (int64_t id = b; id < e; ++id) work((int)id);
+    });
     for (int b : too_big)
         if (b) return false;
     out.rptr.assign(nt + 1, 0);

@@ -37,21 +37,24 @@ void parallel_parts(int64_t n, int parts, F&& f) {
         return;
     }
     std::vector<std::exception_ptr> err(parts);
+    auto part = [&](int p) {
+        try {
+            f(lo(p), lo(p + 1), p);
+        } catch (...) {
+            err[p] = std::current_exception();
+        }
+    };
     std::vector<std::thread> th;
+    std::vector<int> inline_parts{0};   // parts run on the calling thread
     th.reserve(parts - 1);
-    for (int p = 1; p < parts; ++p)
-        th.emplace_back([&, p] {
-            try {
-                f(lo(p), lo(p + 1), p);
-            } catch (...) {
-                err[p] = std::current_exception();
-            }
-        });
-    try {
-        f(lo(0), lo(1), 0);
-    } catch (...) {
-        err[0] = std::current_exception();
+    for (int p = 1; p < parts; ++p) {
+        try {
+            th.emplace_back(part, p);
+        } catch (...) {   // no thread to be had: run the part here
+            inline_parts.push_back(p);
+        }
     }
+    for (int p : inline_parts) part(p);
     for (auto& t : th) t.join();
     for (auto& e : err)
         if (e) std::rethrow_exception(e);
