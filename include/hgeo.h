@@ -225,6 +225,10 @@ hg_status hg_opts_default(hg_opts* opts);
  * the GPU: face areas, cotangent weights theta_jk = (cot a + cot b)/2, lumped
  * vertex areas A_j = (1/3) sum of incident face areas (Sec. 3.1), the mean
  * edge length; builds the breadth-first/LDS-tile schedules' connectivity.
+ * The connectivity, tiles and colours are built on host worker threads: the
+ * environment variable HG_HOST_THREADS sets their number (read once per
+ * process; default the hardware's, at most 16); every table is the same for
+ * any number of them.
  * The mesh owns its device memory until hg_mesh_destroy.
  */
 hg_status hg_mesh_create(const double* xyz, int64_t nv, const int32_t* tri, int64_t nf,
